@@ -1,0 +1,230 @@
+"""FP64 CPU oracle of the OFDM monostatic radar receive path.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this module.  The product path
+(the HIP library and its Python binding) never imports, calls or links it, and
+this module imports nothing from the product path.
+
+Every function follows the passage of Delamou, Noubir, Dang and Amhoud, "An
+Efficient OFDM-Based Monostatic Radar Design for Multitarget Detection"
+(arXiv 2209.03883) that its docstring names.  The paper is a simulation study;
+where it is silent, garbled or ambiguous the reading used here is stated in the
+docstring and listed in the design notes.
+
+Conventions
+-----------
+* All arithmetic is float64 / complex128.  numpy's FFT is used as the library
+  primitive for the DFT sums; it is pinned against brute-force sums in the
+  tests.
+* Frames are symbol-major: ``X[l, k]`` is subcarrier ``k`` of OFDM symbol ``l``
+  (the paper writes the same matrices with ``k`` as the row index).
+* ``DFT_n(x)[k] = sum_i x[i] exp(-2j*pi*i*k/n)``;
+  ``IDFT_n(X)[i] = (1/n) sum_k X[k] exp(+2j*pi*i*k/n)``.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+SPEED_OF_LIGHT = 3.0e8  # m/s, Table I
+
+WINDOW_RECT = 0
+WINDOW_HANN = 1
+WINDOW_HAMMING = 2
+
+
+# --------------------------------------------------------------------------
+# Zadoff-Chu precoding (Sec. III-B, Eq. 23 and Eq. 24)
+# --------------------------------------------------------------------------
+def zc_phase_index(n: int, root: int, shift: int = 0) -> np.ndarray:
+    """Exact phase indices m_k of a length-n Zadoff-Chu sequence (Eq. 23).
+
+    Eq. 23 gives Z(k) = exp(j*2*pi*r/L * (k^2/2 + q*k)) for even L and
+    exp(j*2*pi*r/L * (k(k+1)/2 + q*k)) for odd L.  Both equal
+    exp(j*pi*m_k/L) with the integer
+        m_k = r*(k^2 + 2qk)      mod 2L   (L even)
+        m_k = r*(k(k+1) + 2qk)   mod 2L   (L odd),
+    which this function returns (int64, exact).  The root r must be
+    relatively prime to L (Sec. III-B); otherwise ValueError.
+    """
+    if n < 1:
+        raise ValueError("ZC length must be positive")
+    if math.gcd(int(root), int(n)) != 1:
+        raise ValueError(f"ZC root {root} is not relatively prime to length {n}")
+    k = np.arange(n, dtype=np.int64)
+    if n % 2 == 0:
+        base = k * k
+    else:
+        base = k * (k + 1)
+    return (int(root) * ((base + 2 * int(shift) * k) % (2 * n))) % (2 * n)
+
+
+def zc_sequence(n: int, root: int, shift: int = 0) -> np.ndarray:
+    """Length-n Zadoff-Chu sequence z_k = exp(j*pi*m_k/n) (Eq. 23), complex128."""
+    m = zc_phase_index(n, root, shift).astype(np.float64)
+    ang = np.pi * m / n
+    return np.cos(ang) + 1j * np.sin(ang)
+
+
+# --------------------------------------------------------------------------
+# Spectral division / LS channel estimate (Sec. II-B.2, Eq. 16)
+# --------------------------------------------------------------------------
+def ls_estimate(Y: np.ndarray, A: np.ndarray, z: np.ndarray | None = None) -> np.ndarray:
+    """LS channel estimate h = y / a of Eq. 16, after ZC de-precoding.
+
+    Sec. III-B precodes the symbols as A_p = Z_m A and removes the precoding
+    at the receiver with Z_m^{-1}.  Under the diagonal reading used here
+    (Z_m = diag(z_0..z_{N-1}) along the subcarriers, the same z for every
+    symbol) the received element is y = z_k * a * h + noise, so
+        h_{k,l} = y_{k,l} / (z_k * a_{k,l}).
+    ``z=None`` means no precoding.  Zero symbols raise ZeroDivisionError.
+    """
+    Y = np.asarray(Y, dtype=np.complex128)
+    A = np.asarray(A, dtype=np.complex128)
+    if Y.shape != A.shape:
+        raise ValueError("Y and A must have the same shape")
+    if np.any(A == 0):
+        raise ZeroDivisionError("a transmitted symbol is zero")
+    tx = A if z is None else A * np.asarray(z, dtype=np.complex128)[None, :]
+    return Y / tx
+
+
+# --------------------------------------------------------------------------
+# DFT-based channel estimation (Sec. III-A, Eq. 20-22)
+# --------------------------------------------------------------------------
+def dft_ce(H: np.ndarray, n_cp: int) -> np.ndarray:
+    """DFT-CE denoising of Sec. III-A, per OFDM symbol along the subcarriers.
+
+    Step 1 (Eq. 20): hhat = IDFT_N(H_l), with the 1/N factor.
+    Step 2 (Eq. 21): keep taps 0 <= n <= N_cp-1, zero the rest.
+    Step 3 (Eq. 22): back to the frequency domain with DFT_N.  Eq. 22 prints
+    a second 1/K; it is read as absent so that N_cp = N is the identity.
+    """
+    H = np.asarray(H, dtype=np.complex128)
+    n = H.shape[1]
+    if not 1 <= n_cp <= n:
+        raise ValueError("n_cp must lie in [1, N]")
+    taps = np.fft.ifft(H, axis=1)
+    taps[:, n_cp:] = 0.0
+    return np.fft.fft(taps, axis=1)
+
+
+# --------------------------------------------------------------------------
+# Window (Sec. II-B.2, the matrix W of Eq. 17; Hamming in Sec. IV)
+# --------------------------------------------------------------------------
+def window(length: int, kind: int) -> np.ndarray:
+    """Periodic (DFT-even) window of the given length, float64.
+
+    Rect: 1.  Hann: 0.5 - 0.5 cos(2 pi n / L).  Hamming: 0.54 - 0.46 cos(2 pi n / L).
+    The paper does not say symmetric or periodic; the periodic form is used.
+    """
+    n = np.arange(length, dtype=np.float64)
+    if kind == WINDOW_RECT:
+        return np.ones(length)
+    if kind == WINDOW_HANN:
+        return 0.5 - 0.5 * np.cos(2.0 * np.pi * n / length)
+    if kind == WINDOW_HAMMING:
+        return 0.54 - 0.46 * np.cos(2.0 * np.pi * n / length)
+    raise ValueError(f"unknown window kind {kind}")
+
+
+# --------------------------------------------------------------------------
+# 2D periodogram (Sec. II-B.2, Eq. 17)
+# --------------------------------------------------------------------------
+def periodogram(H: np.ndarray, n_pad: int, m_pad: int, window_kind: int = WINDOW_HANN) -> np.ndarray:
+    """Zero-padded, windowed 2D periodogram of Eq. 17.
+
+        P(s, r) = 1/(N M) | sum_{k<N'} ( sum_{l<M'} h_{k,l} w_{k,l} e^{-j2pi l s/M'} ) e^{+j2pi k r/N'} |^2
+
+    with h = 0 for k >= N or l >= M (trailing zero padding), the separable
+    window w_{k,l} = w_k w_l, the printed denominators R', S' read as M', N',
+    r = 0..N'-1 and the signed Doppler index s = -M'/2..M'/2-1.
+
+    Returns float64 P with shape (M', N'); row s + M'/2 holds Doppler s.
+    """
+    H = np.asarray(H, dtype=np.complex128)
+    m, n = H.shape
+    if n_pad < n or m_pad < m:
+        raise ValueError("padding must not shrink the frame")
+    hw = H * window(m, window_kind)[:, None] * window(n, window_kind)[None, :]
+    padded = np.zeros((m_pad, n_pad), dtype=np.complex128)
+    padded[:m, :n] = hw
+    doppler = np.fft.fft(padded, axis=0)            # sum over l with e^{-j...}
+    rng = np.fft.ifft(doppler, axis=1) * n_pad       # sum over k with e^{+j...}
+    power = (rng.real ** 2 + rng.imag ** 2) / (n * m)
+    # unsigned Doppler index u -> row (u + M'/2) mod M'
+    return np.roll(power, m_pad // 2, axis=0)
+
+
+def frame_periodogram(Y, A, *, n_pad, m_pad, n_cp, window_kind=WINDOW_HANN,
+                      zc_root=None, zc_shift=0):
+    """The whole estimator of Fig. 2 / Fig. 3: de-precode, divide, DFT-CE, Eq. 17."""
+    n = np.asarray(Y).shape[1]
+    z = None if zc_root is None else zc_sequence(n, zc_root, zc_shift)
+    H = ls_estimate(Y, A, z)
+    Hd = dft_ce(H, n_cp)
+    return periodogram(Hd, n_pad, m_pad, window_kind)
+
+
+# --------------------------------------------------------------------------
+# Peak extraction (Sec. II-B.2, Eq. 17-18: the dominant frequencies of P)
+# --------------------------------------------------------------------------
+def find_peaks(P: np.ndarray, k: int):
+    """Top-k 3x3 cyclic local maxima of P.
+
+    A cell is a peak when its value is >= each of its 8 cyclic neighbours.
+    Peaks are ranked by (value descending, flat index row*N'+r ascending) and
+    the first min(k, #peaks) are returned as a list of (row, r, value).
+    The paper picks "the dominant peaks" of P; this is the reading used.
+    """
+    P = np.asarray(P)
+    is_peak = np.ones(P.shape, dtype=bool)
+    for dr in (-1, 0, 1):
+        for dc in (-1, 0, 1):
+            if dr == 0 and dc == 0:
+                continue
+            is_peak &= P >= np.roll(np.roll(P, dr, axis=0), dc, axis=1)
+    rows, cols = np.nonzero(is_peak)
+    vals = P[rows, cols]
+    flat = rows.astype(np.int64) * P.shape[1] + cols
+    order = np.lexsort((flat, -vals))[:k]
+    return [(int(rows[i]), int(cols[i]), float(vals[i])) for i in order]
+
+
+# --------------------------------------------------------------------------
+# Radar parameters (Sec. II-B.2, Eq. 13-15 and Eq. 19; Table I)
+# --------------------------------------------------------------------------
+def symbol_time(delta_f: float, cp_fraction: float) -> float:
+    """T_s = T + T_cp with T = 1/delta_f (Sec. II-B); cp_fraction = T_cp/T."""
+    return (1.0 + cp_fraction) / delta_f
+
+
+def resolution(n: int, m: int, delta_f: float, f_c: float, cp_fraction: float,
+               c: float = SPEED_OF_LIGHT):
+    """(Delta d, Delta v) of Eq. 15."""
+    ts = symbol_time(delta_f, cp_fraction)
+    return c / (2.0 * n * delta_f), c / (2.0 * m * f_c * ts)
+
+
+def unambiguous(delta_f: float, f_c: float, cp_fraction: float, c: float = SPEED_OF_LIGHT):
+    """(d_un, v_un) of Eq. 14."""
+    ts = symbol_time(delta_f, cp_fraction)
+    return c / (2.0 * delta_f), c / (2.0 * f_c * ts)
+
+
+def cp_max_range(delta_f: float, cp_fraction: float, c: float = SPEED_OF_LIGHT) -> float:
+    """Largest range whose round trip fits the cyclic prefix (Eq. 13): c T_cp / 2."""
+    return c * (cp_fraction / delta_f) / 2.0
+
+
+def bins_to_range_velocity(r: float, s: float, n_pad: int, m_pad: int, delta_f: float,
+                           f_c: float, cp_fraction: float, c: float = SPEED_OF_LIGHT):
+    """Eq. 19 read consistently with Eq. 14-15: d = c r/(2 N' df), v = c s/(2 f_c M' T_s).
+
+    The printed Eq. 19 swaps r and s and uses T_0 for T_s; this is the reading
+    that agrees with the resolution formulas.
+    """
+    ts = symbol_time(delta_f, cp_fraction)
+    return c * r / (2.0 * n_pad * delta_f), c * s / (2.0 * f_c * m_pad * ts)

@@ -1,0 +1,285 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: values the
+paper prints (tests/golden), closed forms, invariants, brute-force sums on tiny
+inputs, and the independent channel model of the synthetic frame generator.
+"""
+
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import radar_oracle as O
+from synth import frames as S
+
+
+def _load_table(path):
+    rows = {}
+    with open(path) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            parts = line.split()
+            rows[parts[0]] = (float(parts[1]), int(parts[3]))
+    return rows
+
+
+# ----------------------------------------------------------------- ZC (Eq. 23)
+def test_zc_worked_example(golden_dir):
+    data = np.loadtxt(os.path.join(golden_dir, "zc_n4_root1.txt"))
+    m = O.zc_phase_index(4, 1)
+    z = O.zc_sequence(4, 1)
+    np.testing.assert_array_equal(m, data[:, 1].astype(np.int64))
+    np.testing.assert_allclose(z.real, data[:, 2], atol=1e-15)
+    np.testing.assert_allclose(z.imag, data[:, 3], atol=1e-15)
+    # lag-1 cyclic autocorrelation of this sequence is zero
+    assert abs(np.sum(z * np.conj(np.roll(z, 1)))) < 1e-15
+
+
+@pytest.mark.parametrize("n,root", [(256, 1), (1024, 7), (2048, 7), (255, 2), (63, 5), (7, 3)])
+def test_zc_cazac(n, root):
+    z = O.zc_sequence(n, root)
+    np.testing.assert_allclose(np.abs(z), 1.0, atol=1e-14)
+    # periodic autocorrelation: N at lag 0, zero elsewhere (CAZAC, Sec. III-B)
+    ac = np.fft.ifft(np.abs(np.fft.fft(z)) ** 2) * 1.0
+    assert abs(ac[0] - n) < 1e-9 * n
+    assert np.max(np.abs(ac[1:])) < 1e-12 * n
+    # flat spectrum |DFT(z)| = sqrt(N)
+    np.testing.assert_allclose(np.abs(np.fft.fft(z)), math.sqrt(n), rtol=1e-11)
+
+
+def test_zc_phase_matches_definition_brute_force():
+    # Eq. 23 evaluated term by term in exact rational arithmetic of the phase.
+    for n, root, q in [(8, 3, 0), (8, 5, 2), (9, 2, 1), (16, 7, 3)]:
+        m = O.zc_phase_index(n, root, q)
+        for k in range(n):
+            if n % 2 == 0:
+                num = root * (k * k + 2 * q * k)       # 2*pi*r/L*(k^2/2+qk) = pi*num/L
+            else:
+                num = root * (k * (k + 1) + 2 * q * k)
+            assert (num - int(m[k])) % (2 * n) == 0
+
+
+def test_zc_root_must_be_coprime():
+    with pytest.raises(ValueError):
+        O.zc_phase_index(1024, 2)
+    with pytest.raises(ValueError):
+        O.zc_phase_index(9, 3)
+
+
+# ------------------------------------------------------- division (Eq. 16)
+def test_ls_estimate_recovers_generator_channel():
+    spec = S.FrameSpec(n_sub=64, n_sym=16, qam=16, zc_root=5, n_targets=2, noise=False,
+                       on_grid=False, rho_max=14, nu_abs_max=7, rayleigh=True)
+    f = S.make_frame(spec, 99, 0)
+    H = O.ls_estimate(f.Y, f.A, O.zc_sequence(64, 5))
+    k = np.arange(64)
+    l = np.arange(16)
+    ref = sum(f.b[p] * np.outer(np.exp(2j * np.pi * l * f.nu[p] / 16), np.exp(-2j * np.pi * k * f.rho[p] / 64))
+              for p in range(2))
+    np.testing.assert_allclose(H, ref, atol=1e-13)
+
+
+def test_ls_estimate_rejects_zero_symbol():
+    A = np.ones((2, 4), complex)
+    A[1, 2] = 0
+    with pytest.raises(ZeroDivisionError):
+        O.ls_estimate(np.ones((2, 4), complex), A)
+
+
+# -------------------------------------------------------- DFT-CE (Eq. 20-22)
+def test_dft_ce_identity_and_projection():
+    rng = np.random.default_rng(1)
+    H = rng.standard_normal((6, 32)) + 1j * rng.standard_normal((6, 32))
+    np.testing.assert_allclose(O.dft_ce(H, 32), H, atol=1e-13)
+    D = O.dft_ce(H, 8)
+    np.testing.assert_allclose(O.dft_ce(D, 8), D, atol=1e-13)       # idempotent
+    assert np.sum(np.abs(D) ** 2) <= np.sum(np.abs(H) ** 2) + 1e-9  # energy never grows
+    # orthogonal projection: residual is orthogonal to the kept part
+    assert abs(np.vdot(D, H - D)) < 1e-9
+
+
+def test_dft_ce_brute_force_tiny():
+    rng = np.random.default_rng(2)
+    n, n_cp = 8, 3
+    H = rng.standard_normal((2, n)) + 1j * rng.standard_normal((2, n))
+    out = O.dft_ce(H, n_cp)
+    for l in range(2):
+        taps = [sum(H[l, k] * np.exp(2j * np.pi * i * k / n) for k in range(n)) / n for i in range(n)]
+        for k in range(n):
+            ref = sum(taps[i] * np.exp(-2j * np.pi * i * k / n) for i in range(n_cp))
+            assert abs(out[l, k] - ref) < 1e-12
+
+
+def test_dft_ce_passes_target_inside_cp():
+    n, m = 64, 8
+    k = np.arange(n)
+    l = np.arange(m)
+    H = 0.7 * np.outer(np.exp(2j * np.pi * l * 3 / m), np.exp(-2j * np.pi * k * 11 / n))
+    np.testing.assert_allclose(O.dft_ce(H, 16), H, atol=1e-13)
+    # and removes one outside it
+    H2 = np.outer(np.ones(m), np.exp(-2j * np.pi * k * 40 / n))
+    assert np.max(np.abs(O.dft_ce(H2, 16))) < 1e-13
+
+
+def test_dft_ce_white_noise_energy_fraction():
+    rng = np.random.default_rng(3)
+    n, n_cp = 256, 64
+    W = (rng.standard_normal((400, n)) + 1j * rng.standard_normal((400, n))) / np.sqrt(2)
+    ratio = np.sum(np.abs(O.dft_ce(W, n_cp)) ** 2) / np.sum(np.abs(W) ** 2)
+    # ratio is a mean of 400*256 chi-square terms: expected n_cp/n, sd ~ 0.25/sqrt(400*64)
+    assert abs(ratio - n_cp / n) < 0.01
+
+
+# ----------------------------------------------------------- window
+def test_windows_periodic():
+    w = O.window(8, O.WINDOW_HANN)
+    np.testing.assert_allclose(w, [0, 0.14644660940672624, 0.5, 0.8535533905932737, 1.0,
+                                   0.8535533905932737, 0.5, 0.14644660940672624], atol=1e-15)
+    assert abs(O.window(64, O.WINDOW_HANN).sum() - 32) < 1e-12
+    assert abs(O.window(64, O.WINDOW_HAMMING).sum() - 0.54 * 64) < 1e-12
+    np.testing.assert_array_equal(O.window(5, O.WINDOW_RECT), np.ones(5))
+
+
+# --------------------------------------------------------- periodogram (Eq. 17)
+def _periodogram_brute(H, n_pad, m_pad, wk):
+    m, n = H.shape
+    w_l = O.window(m, wk)
+    w_k = O.window(n, wk)
+    P = np.zeros((m_pad, n_pad))
+    for s in range(-m_pad // 2, m_pad // 2):
+        for r in range(n_pad):
+            acc = 0j
+            for k in range(n):
+                inner = 0j
+                for l in range(m):
+                    inner += H[l, k] * w_k[k] * w_l[l] * np.exp(-2j * np.pi * l * s / m_pad)
+                acc += inner * np.exp(2j * np.pi * k * r / n_pad)
+            P[s + m_pad // 2, r] = abs(acc) ** 2 / (n * m)
+    return P
+
+
+@pytest.mark.parametrize("wk", [O.WINDOW_RECT, O.WINDOW_HANN, O.WINDOW_HAMMING])
+def test_periodogram_brute_force_tiny(wk):
+    rng = np.random.default_rng(4 + wk)
+    H = rng.standard_normal((4, 8)) + 1j * rng.standard_normal((4, 8))
+    P = O.periodogram(H, 32, 16, wk)
+    ref = _periodogram_brute(H, 32, 16, wk)
+    assert np.max(np.abs(P - ref)) < 1e-12 * np.max(ref)
+
+
+@pytest.mark.parametrize("wk,gain", [(O.WINDOW_RECT, 1.0), (O.WINDOW_HANN, 0.5), (O.WINDOW_HAMMING, 0.54)])
+def test_periodogram_single_target_closed_form(wk, gain):
+    n, m, n_pad, m_pad = 64, 32, 256, 128
+    rho, nu, b = 13, -5, 0.8 * np.exp(0.3j)
+    k = np.arange(n)
+    l = np.arange(m)
+    H = b * np.outer(np.exp(2j * np.pi * l * nu / m), np.exp(-2j * np.pi * k * rho / n))
+    P = O.periodogram(H, n_pad, m_pad, wk)
+    row, col = np.unravel_index(np.argmax(P), P.shape)
+    assert (row - m_pad // 2, col) == (nu * m_pad // m, rho * n_pad // n)
+    # P = |b|^2 (sum w_k)^2 (sum w_l)^2 / (N M) = |b|^2 g^4 N M
+    assert abs(P[row, col] - abs(b) ** 2 * gain ** 4 * n * m) < 1e-9 * P[row, col]
+
+
+def test_periodogram_parseval():
+    rng = np.random.default_rng(5)
+    H = rng.standard_normal((16, 32)) + 1j * rng.standard_normal((16, 32))
+    P = O.periodogram(H, 128, 64, O.WINDOW_HANN)
+    hw = H * O.window(16, 1)[:, None] * O.window(32, 1)[None, :]
+    assert abs(P.sum() - (128 * 64) / (32 * 16) * np.sum(np.abs(hw) ** 2)) < 1e-9 * P.sum()
+
+
+@pytest.mark.parametrize("wk", [O.WINDOW_HANN, O.WINDOW_HAMMING])
+def test_periodogram_dftce_zero_pattern(wk):
+    # After DFT-CE the taps live on [0, N_cp); a cosine window widens them to
+    # [-1, N_cp]; at N' = 4N the range samples r = 4q are those taps scaled,
+    # so P[:, 4q] vanishes for q in [N_cp+1, N-2].
+    rng = np.random.default_rng(6)
+    n, m, n_cp = 64, 16, 16
+    H = rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))
+    P = O.periodogram(O.dft_ce(H, n_cp), 4 * n, 2 * m, wk)
+    zero_cols = [4 * q for q in range(n_cp + 1, n - 1)]
+    assert np.max(P[:, zero_cols]) < 1e-13 * np.max(P)
+    assert np.min(np.max(P[:, [4 * q for q in range(0, n_cp)]], axis=0)) > 1e-6 * np.max(P)
+
+
+def test_frame_periodogram_finds_generator_targets():
+    f = S.make_frame(S.spec_small(snr_db=10.0), 1, 0)
+    P = O.frame_periodogram(f.Y, f.A, n_pad=1024, m_pad=256, n_cp=32, zc_root=1)
+    got = sorted((r - 128, c) for r, c, _ in O.find_peaks(P, 3))
+    want = sorted((int(v * 4), int(r * 4)) for r, v in zip(f.rho, f.nu))
+    assert got == want
+
+
+# ---------------------------------------------------------------- peaks
+def _peaks_brute(P, k):
+    R, C = P.shape
+    found = []
+    for i in range(R):
+        for j in range(C):
+            ok = True
+            for di in (-1, 0, 1):
+                for dj in (-1, 0, 1):
+                    if (di or dj) and P[(i + di) % R, (j + dj) % C] > P[i, j]:
+                        ok = False
+            if ok:
+                found.append((-P[i, j], i * C + j, i, j))
+    found.sort()
+    return [(i, j, -v) for v, _, i, j in found[:k]]
+
+
+def test_find_peaks_brute_force_with_ties_and_wrap():
+    rng = np.random.default_rng(7)
+    for trial in range(20):
+        P = np.round(rng.random((9, 12)) * 6) / 6      # many exact ties
+        P[0, 0] = 2.0                                   # corner peak, wraps both ways
+        P[8, 11] = 2.0                                  # its diagonal neighbour: a tie
+        P[4, 11] = 1.5                                  # wraps along columns
+        assert O.find_peaks(P, 10) == _peaks_brute(P, 10)
+
+
+def test_find_peaks_returns_fewer_when_few_peaks():
+    # a single cyclic "hill": every other cell has a strictly larger neighbour
+    i, j = np.meshgrid(np.arange(6), np.arange(8), indexing="ij")
+    di = np.minimum(np.abs(i - 1), 6 - np.abs(i - 1))
+    dj = np.minimum(np.abs(j - 2), 8 - np.abs(j - 2))
+    P = 10.0 - di - dj
+    assert O.find_peaks(P, 5) == [(1, 2, 10.0)]
+    # a flat plateau: every cell is >= its neighbours, so all are peaks,
+    # ranked by flat index
+    assert O.find_peaks(np.zeros((3, 3)), 4) == [(0, 0, 0.0), (0, 1, 0.0), (0, 2, 0.0), (1, 0, 0.0)]
+
+
+# ------------------------------------------------------- Table I numbers
+def test_table1_derived_numbers(golden_dir):
+    t = _load_table(os.path.join(golden_dir, "table1_parameters.txt"))
+    n, m = int(t["n_sub"][0]), int(t["n_sym"][0])
+    df, fc, cpf = t["delta_f"][0], t["f_c"][0], t["cp_fraction"][0]
+
+    def printed(name, value, scale=1.0):
+        want, dec = t[name]
+        assert round(value * scale, dec) == pytest.approx(want, abs=10 ** -(dec + 3)), name
+
+    dd, dv = O.resolution(n, m, df, fc, cpf)
+    printed("range_resolution_cm", dd, 100.0)
+    printed("velocity_resolution_cms", dv, 100.0)
+    printed("velocity_resolution", dv)
+    printed("max_range", O.cp_max_range(df, cpf))
+    assert n * df == t["bandwidth"][0]
+    d_un, v_un = O.unambiguous(df, fc, cpf)
+    assert d_un == pytest.approx(625.0)
+    assert v_un == pytest.approx(374.03, abs=5e-3)
+    assert dd == pytest.approx(d_un / n) and dv == pytest.approx(v_un / m)
+    # Sec. IV prints 43.73 m for the 7 % normal CP; c*0.07/(2*240 kHz) = 43.75 m.
+    assert abs(O.cp_max_range(df, t["normal_cp_fraction"][0]) - t["normal_cp_max_range"][0]) < 0.03
+
+
+def test_bins_to_units():
+    # one native bin maps to one resolution cell (Eq. 15 vs Eq. 19)
+    d, v = O.bins_to_range_velocity(4.0, 4.0, 4 * 2048, 4 * 560, 240e3, 77e9, 0.25)
+    dd, dv = O.resolution(2048, 560, 240e3, 77e9, 0.25)
+    assert d == pytest.approx(dd) and v == pytest.approx(dv)
