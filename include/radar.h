@@ -1,0 +1,186 @@
+/*
+ * radar.h -- C ABI of the MI355X (gfx950) OFDM monostatic radar receive path.
+ *
+ * The operations follow Delamou, Noubir, Dang, Amhoud, "An Efficient
+ * OFDM-Based Monostatic Radar Design for Multitarget Detection" (arXiv
+ * 2209.03883):
+ *   - Zadoff-Chu de-precoding (Sec. III-B, Eq. 23-24),
+ *   - spectral division / LS channel estimate (Sec. II-B.2, Eq. 16),
+ *   - DFT-CE denoising (Sec. III-A, Eq. 20-22),
+ *   - the windowed, zero-padded 2D periodogram (Sec. II-B.2, Eq. 17),
+ *   - extraction of its dominant peaks (Sec. II-B.2, Eq. 17-19).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.   Every array pointer is a DEVICE pointer owned by the caller
+ *           (for example a torch CUDA tensor).  Descriptors and the
+ *           radar_frame_desc struct are HOST pointers, read before the call
+ *           returns.  The library never allocates device memory inside a call:
+ *           scratch space is the caller's workspace `ws` of `ws_bytes` bytes,
+ *           sized by the matching *_workspace_size function.  The library's
+ *           only own device state is a read-only twiddle table, written once
+ *           per device by radar_init() (called implicitly by the first entry
+ *           point that runs on that device).
+ * Layout.   A frame is symbol-major: element (l, k) -- OFDM symbol l,
+ *           subcarrier k -- sits at  base + l*ld + k  (ld >= N).  Frame f of a
+ *           batch starts `frame_stride` elements after frame f-1.  The
+ *           periodogram P of a frame is float32 [M'][N'] row-major; row
+ *           s + M'/2 holds the signed Doppler index s in [-M'/2, M'/2) and
+ *           column r in [0, N') the range index.
+ * Streams.  `hip_stream` is a hipStream_t (NULL = the default stream).
+ *           Calls validate on the host, enqueue kernels and return; the
+ *           caller synchronises.  Calls on distinct streams with distinct
+ *           workspaces may run concurrently.
+ * Errors.   A negative return means the arguments were rejected and nothing
+ *           was enqueued (RADAR_E_*).  Data-dependent problems found on the
+ *           device (a zero transmitted symbol, a non-finite input) set bits in
+ *           the frame's `status` word (RADAR_ST_*); that frame's outputs are
+ *           then undefined, the others are unaffected.  Nothing throws across
+ *           this boundary.
+ * Sizes.    N, M: powers of two in [16, 4096].  N' = N * {1,2,4,8};
+ *           M' = M * 2^j with M' <= 16384.  1 <= n_cp <= N.
+ */
+#ifndef RADAR_H
+#define RADAR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  float re, im;                 /* same layout as torch.complex64 / hipFloatComplex */
+} radar_cf32;
+
+enum {
+  RADAR_OK = 0,
+  RADAR_E_ARG = -1,             /* null pointer, bad size, bad stride, bad enum */
+  RADAR_E_UNSUPPORTED = -2,     /* a size this build does not implement */
+  RADAR_E_WORKSPACE = -3,       /* ws_bytes smaller than the *_workspace_size result */
+  RADAR_E_HIP = -4,             /* a HIP runtime call failed */
+  RADAR_E_NOT_COPRIME = -5      /* ZC root not relatively prime to N (Sec. III-B) */
+};
+
+enum { RADAR_WIN_RECT = 0, RADAR_WIN_HANN = 1, RADAR_WIN_HAMMING = 2 };  /* periodic windows */
+enum { RADAR_ZC_NONE = 0, RADAR_ZC_DIAG = 1 };  /* ZC precoding along the subcarriers */
+enum { RADAR_ST_ZERO_SYMBOL = 1u, RADAR_ST_NONFINITE = 2u };
+
+/* One frame shape.  Names follow the paper: N subcarriers, M OFDM symbols,
+ * N' >= N and M' >= M the zero-padded periodogram sizes of Eq. 17, N_cp the
+ * DFT-CE taps kept by Eq. 21 (n_cp == N disables DFT-CE, i.e. plain LS-CE). */
+typedef struct {
+  int32_t n_sub;                /* N  */
+  int32_t n_sym;                /* M  */
+  int32_t n_pad;                /* N' */
+  int32_t m_pad;                /* M' */
+  int32_t n_cp;                 /* N_cp */
+  int32_t zc_mode;              /* RADAR_ZC_* */
+  int32_t zc_root;              /* r' of Eq. 23, relatively prime to N */
+  int32_t zc_shift;             /* q' of Eq. 23 */
+  int32_t window;               /* RADAR_WIN_*, applied separably over k and l */
+  int32_t reserved;             /* must be 0 */
+  int64_t ld;                   /* elements between consecutive OFDM symbols, >= N */
+} radar_frame_desc;
+
+/* One detected peak of P.  s is the signed Doppler index (row - M'/2), r the
+ * range index, p = P[s + M'/2][r].  s_off / r_off are sub-cell refinements
+ * (0 unless a refinement entry point filled them). */
+typedef struct {
+  int32_t s, r;
+  float p;
+  float s_off, r_off;
+} radar_peak;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int radar_version(void);
+
+/* Human-readable text for a RADAR_* return code. */
+const char *radar_status_string(int code);
+
+/* Upload the twiddle table to the current HIP device.  Idempotent and
+ * thread-safe; entry points call it themselves.  Call it once outside any
+ * stream capture before capturing radar calls into a graph. */
+int radar_init(void);
+
+/* ------------------------------------------------------------------------
+ * radar_frame_process -- the whole receive path for a batch of frames.
+ *
+ * For each frame f < n_frames (all sharing *d):
+ *   H = Y / (z_k * A)                 Eq. 16 with ZC de-precoding (Sec. III-B,
+ *                                     z = Eq. 23 sequence, diagonal reading)
+ *   H' = DFT_N(trunc_{N_cp}(IDFT_N(H)))   per symbol (Eq. 20-22)
+ *   P  = Eq. 17 on H' with the separable periodic window, zero padded to
+ *        N' x M', scaled by 1/(N M)
+ *   peaks = the k largest 3x3 cyclic local maxima of P, ranked by
+ *           (P descending, flat index row*N'+r ascending).
+ * Y, A:     input frames, frame f at Y + f*frame_stride (elements).
+ * P:        output, frame f at P + f*p_frame_stride (floats); must not be NULL;
+ *           p_frame_stride >= M'*N' and a multiple of 4; P 16-byte aligned.
+ * peaks:    output, k entries per frame at peaks + f*k; n_peaks[f] = number
+ *           written (< k only if P has fewer than k local maxima).
+ * status:   output, one word per frame (RADAR_ST_* bits; 0 = clean).
+ * 1 <= k <= 64.
+ * ------------------------------------------------------------------------ */
+size_t radar_frame_workspace_size(const radar_frame_desc *d, int32_t n_frames, int32_t k);
+int radar_frame_process(const radar_frame_desc *d, int32_t n_frames,
+                        const radar_cf32 *Y, const radar_cf32 *A, int64_t frame_stride,
+                        float *P, int64_t p_frame_stride,
+                        int32_t k, radar_peak *peaks, int32_t *n_peaks, uint32_t *status,
+                        void *ws, size_t ws_bytes, void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * radar_periodogram -- Eq. 17 from a channel estimate the caller already has.
+ *
+ * H is an LS estimate (Eq. 16) laid out like Y.  If d->n_cp < N the DFT-CE of
+ * Eq. 20-22 is applied first; d->zc_mode must be RADAR_ZC_NONE (H is already
+ * de-precoded).  P as for radar_frame_process.  The workspace size is
+ * radar_frame_workspace_size(d, n_frames, 1).
+ * ------------------------------------------------------------------------ */
+int radar_periodogram(const radar_frame_desc *d, int32_t n_frames,
+                      const radar_cf32 *H, int64_t frame_stride,
+                      float *P, int64_t p_frame_stride,
+                      void *ws, size_t ws_bytes, void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * radar_detect_topk -- dominant peaks of given periodograms.
+ *
+ * P: n_frames float32 arrays [m_pad][n_pad] (frame f at P + f*p_frame_stride,
+ * row m_pad/2 = Doppler 0).  Returns per frame the k largest 3x3 cyclic local
+ * maxima, ranked by (value descending, flat index ascending), exactly as
+ * radar_frame_process does.  m_pad, n_pad: powers of two in [4, 16384].
+ * ------------------------------------------------------------------------ */
+size_t radar_detect_workspace_size(int32_t m_pad, int32_t n_pad, int32_t n_frames, int32_t k);
+int radar_detect_topk(const float *P, int32_t m_pad, int32_t n_pad, int32_t n_frames,
+                      int64_t p_frame_stride, int32_t k,
+                      radar_peak *peaks, int32_t *n_peaks,
+                      void *ws, size_t ws_bytes, void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Stage timing -- a profiling aid, off by default.
+ *
+ * radar_timing_start(max_launches) creates HIP events for up to max_launches
+ * launches of each stage; until radar_timing_stop, every stage launch of the
+ * calls above records an event pair on its own stream around the kernel(s)
+ * of that stage.  radar_timing_stop waits for the recorded events, writes per
+ * stage the summed kernel time in milliseconds and the number of launches
+ * timed (arrays of RADAR_NUM_STAGES entries), and destroys the events.
+ * Launches beyond max_launches are not timed.  Not thread-safe: time one
+ * stream at a time.
+ * ------------------------------------------------------------------------ */
+enum {
+  RADAR_STAGE_TAPS = 0,         /* de-precode, divide, IDFT_N, truncate   (Eq. 16, 20-21) */
+  RADAR_STAGE_DOPPLER = 1,      /* M'-point Doppler DFT of the taps       (Eq. 17) */
+  RADAR_STAGE_RANGE = 2,        /* DFT_N back, window, N'-point range DFT, |.|^2 (Eq. 22, 17) */
+  RADAR_STAGE_PEAKS = 3,        /* local maxima and top-k */
+  RADAR_NUM_STAGES = 4
+};
+int radar_timing_start(int32_t max_launches);
+int radar_timing_stop(double *ms_total, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RADAR_H */

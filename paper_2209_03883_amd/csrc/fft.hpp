@@ -1,0 +1,168 @@
+// Register/LDS Stockham FFT used by every radar kernel.
+//
+// A transform of length L (a power of two, 16 <= L <= 4096) is computed by a
+// "team" of T = L/16 threads; each thread holds 16 complex values in
+// registers in the cyclic layout  v[e] = x[t + T*e].  The transform runs as a
+// sequence of Stockham stages of radix 16 (and one final stage of radix
+// 2, 4 or 8 when L is not a power of 16).  Between stages the team exchanges
+// data through its own LDS region; the last stage leaves its outputs in
+// registers, again in the cyclic layout, so X[t + T*e] = v[e] on return and
+// natural order needs no final reordering.
+//
+// Stage s with radix R and span NS (the product of the earlier radices):
+// butterfly j in [0, L/R) reads x[j + m*L/R] (m < R), multiplies element m by
+// W_{NS*R}^{(j mod NS)*m}, runs an R-point DFT and writes output m to
+// position (j - j mod NS)*R + (j mod NS) + m*NS.
+//
+// Forward transforms use exp(-2 pi i nk/L); INV transforms use exp(+2 pi i nk/L)
+// without the 1/L factor.
+#pragma once
+
+#include <utility>
+
+#include "device_common.hpp"
+
+namespace radar {
+
+// cos(2 pi q/16) and sin(2 pi q/16), q = 0..15.
+struct Tw16 {
+  static constexpr float c[16] = {
+    1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f,
+    0.0f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f,
+    -1.0f, -0.92387953251128674f, -0.70710678118654752f, -0.38268343236508977f,
+    0.0f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f};
+  static constexpr float s[16] = {
+    0.0f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f,
+    1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f,
+    0.0f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f,
+    -1.0f, -0.92387953251128674f, -0.70710678118654752f, -0.38268343236508977f};
+};
+
+// a * exp(-2 pi i Q/16) (forward) or a * exp(+2 pi i Q/16) (INV).
+template <int Q, bool INV>
+__device__ __forceinline__ float2 rot16(float2 a) {
+  constexpr int q = Q & 15;
+  if constexpr (q == 0) {
+    return a;
+  } else if constexpr (q == 4) {
+    return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+  } else if constexpr (q == 8) {
+    return make_float2(-a.x, -a.y);
+  } else if constexpr (q == 12) {
+    return INV ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
+  } else {
+    constexpr float c = Tw16::c[q];
+    constexpr float s = Tw16::s[q];
+    if constexpr (INV) {
+      return make_float2(a.x * c - a.y * s, a.y * c + a.x * s);
+    } else {
+      return make_float2(a.x * c + a.y * s, a.y * c - a.x * s);
+    }
+  }
+}
+
+// In-register R-point DFT (R = 1, 2, 4, 8, 16), decimation in time.
+template <int R, bool INV>
+struct Dft;
+
+template <bool INV>
+struct Dft<1, INV> {
+  static __device__ __forceinline__ void run(float2*) {}
+};
+
+template <int R, bool INV, int K>
+__device__ __forceinline__ void dit_combine_one(float2* x, const float2* e, const float2* o) {
+  const float2 t = rot16<K * (16 / R), INV>(o[K]);
+  x[K] = cadd(e[K], t);
+  x[K + R / 2] = csub(e[K], t);
+}
+
+template <int R, bool INV, int... K>
+__device__ __forceinline__ void dit_combine(float2* x, const float2* e, const float2* o,
+                                            std::integer_sequence<int, K...>) {
+  (dit_combine_one<R, INV, K>(x, e, o), ...);
+}
+
+template <int R, bool INV>
+struct Dft {
+  static_assert(R == 2 || R == 4 || R == 8 || R == 16, "radix");
+  static __device__ __forceinline__ void run(float2* x) {
+    float2 e[R / 2], o[R / 2];
+#pragma unroll
+    for (int i = 0; i < R / 2; ++i) {
+      e[i] = x[2 * i];
+      o[i] = x[2 * i + 1];
+    }
+    Dft<R / 2, INV>::run(e);
+    Dft<R / 2, INV>::run(o);
+    dit_combine<R, INV>(x, e, o, std::make_integer_sequence<int, R / 2>{});
+  }
+};
+
+// LDS index with one pad slot every 16 entries (limits bank conflicts of the
+// strided Stockham writes).
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
+template <int L>
+struct LdsSize {
+  static constexpr int value = L + L / 16;
+};
+
+template <int L, int T, int R, int NS, bool INV>
+__device__ __forceinline__ void stockham_stage(float2 (&v)[16], float2* lds, int t) {
+  constexpr int E = 16;
+  constexpr int NB = E / R;                 // butterflies per thread
+  constexpr bool LAST = (NS * R == L);
+  constexpr int TWSHIFT = RADAR_TW_LOG2 - __builtin_ctz(NS * R);
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    float2 x[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) x[m] = v[b + m * NB];
+    const int j = t + T * b;
+    const int k = j & (NS - 1);
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int m = 1; m < R; ++m) {
+        const float2 w = twiddle(k * m, TWSHIFT);
+        x[m] = INV ? cmulc(x[m], w) : cmul(x[m], w);
+      }
+    }
+    Dft<R, INV>::run(x);
+    if constexpr (LAST) {
+#pragma unroll
+      for (int m = 0; m < R; ++m) v[b + m * NB] = x[m];
+    } else {
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int m = 0; m < R; ++m) lds[lds_pad(base + m * NS)] = x[m];
+    }
+  }
+  if constexpr (!LAST) {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = lds[lds_pad(t + T * e)];
+    __syncthreads();
+  }
+}
+
+// Stages from span NS onward: radix 16 while at least 16 remains, then the
+// remainder (2, 4 or 8) as the last stage.
+template <int L, int T, int NS, bool INV>
+__device__ __forceinline__ void fft_stages(float2 (&v)[16], float2* lds, int t) {
+  constexpr int REM = L / NS;
+  if constexpr (REM > 1) {
+    constexpr int R = REM >= 16 ? 16 : REM;
+    stockham_stage<L, T, R, NS, INV>(v, lds, t);
+    fft_stages<L, T, NS * R, INV>(v, lds, t);
+  }
+}
+
+// Full L-point transform of the team's data (cyclic layout in and out).
+// Every thread of the work-group must call it (it contains barriers).
+template <int L, bool INV>
+__device__ __forceinline__ void team_fft(float2 (&v)[16], float2* lds, int t) {
+  static_assert(L >= 16 && L <= 4096 && (L & (L - 1)) == 0, "FFT length");
+  fft_stages<L, L / 16, 1, INV>(v, lds, t);
+}
+
+}  // namespace radar

@@ -1,0 +1,375 @@
+// Host side of libradar: argument validation, workspace carving, the twiddle
+// table, and kernel launches behind the C ABI declared in include/radar.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/radar.h"
+#include "device_common.hpp"
+
+__device__ float2 g_radar_tw[RADAR_TW_LMAX];
+
+#include "k_frame.hpp"
+#include "k_peaks.hpp"
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_init_mu;
+bool g_init_done[kMaxDevices];
+
+bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+int ilog2(int64_t x) {
+  int r = 0;
+  while ((int64_t(1) << r) < x) ++r;
+  return r;
+}
+int tw_shift(int length) { return RADAR_TW_LOG2 - ilog2(length); }
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int validate_desc(const radar_frame_desc* d) {
+  if (!d) return RADAR_E_ARG;
+  const int N = d->n_sub, M = d->n_sym;
+  if (N <= 0 || M <= 0 || d->n_pad <= 0 || d->m_pad <= 0) return RADAR_E_ARG;
+  if (d->n_pad < N || d->m_pad < M) return RADAR_E_ARG;
+  if (d->n_cp < 1 || d->n_cp > N) return RADAR_E_ARG;
+  if (d->window < RADAR_WIN_RECT || d->window > RADAR_WIN_HAMMING) return RADAR_E_ARG;
+  if (d->zc_mode != RADAR_ZC_NONE && d->zc_mode != RADAR_ZC_DIAG) return RADAR_E_ARG;
+  if (d->reserved != 0) return RADAR_E_ARG;
+  if (d->ld < N) return RADAR_E_ARG;
+  if (!is_pow2(N) || !is_pow2(M) || N < 16 || N > 4096 || M < 16 || M > 4096) return RADAR_E_UNSUPPORTED;
+  if (!is_pow2(d->n_pad) || !is_pow2(d->m_pad)) return RADAR_E_UNSUPPORTED;
+  if (d->n_pad / N > 8 || d->n_pad > RADAR_TW_LMAX || d->m_pad > RADAR_TW_LMAX) return RADAR_E_UNSUPPORTED;
+  if (d->zc_mode == RADAR_ZC_DIAG && (d->zc_root % 2) == 0) return RADAR_E_NOT_COPRIME;  // N is a power of two
+  return RADAR_OK;
+}
+
+struct FrameWs {
+  size_t taps, U, cand, total;
+};
+
+FrameWs frame_ws_layout(const radar_frame_desc* d, int n_frames, int k) {
+  FrameWs w;
+  const size_t F = (size_t)n_frames;
+  w.taps = align256(F * d->n_sym * d->n_cp * sizeof(float2));
+  w.U = align256(F * d->m_pad * d->n_cp * sizeof(float2));
+  w.cand = align256(F * d->m_pad * (size_t)k * sizeof(uint64_t));
+  w.total = w.taps + w.U + w.cand;
+  return w;
+}
+
+int ensure_init() { return radar_init(); }
+
+// ----------------------------------------------------------- stage timing
+struct StageTimer {
+  bool on = false;
+  int cap = 0;
+  int used[RADAR_NUM_STAGES] = {};
+  std::vector<hipEvent_t> ev[RADAR_NUM_STAGES];  // 2 per launch
+};
+StageTimer g_timer;
+
+// Records the opening event of a timed stage launch; returns the slot or -1.
+int timer_open(int stage, hipStream_t s) {
+  if (!g_timer.on || g_timer.used[stage] >= g_timer.cap) return -1;
+  const int slot = g_timer.used[stage]++;
+  hipEventRecord(g_timer.ev[stage][2 * slot], s);
+  return slot;
+}
+void timer_close(int stage, int slot, hipStream_t s) {
+  if (slot >= 0) hipEventRecord(g_timer.ev[stage][2 * slot + 1], s);
+}
+
+#define RADAR_HIP_CHECK(expr)                  \
+  do {                                         \
+    if ((expr) != hipSuccess) return RADAR_E_HIP; \
+  } while (0)
+
+// ----------------------------------------------------------------- dispatch
+template <int N>
+void launch_k1_n(const radar::K1Args& a, int M, int F, hipStream_t s) {
+  constexpr int TEAMS = radar::kBlock / (N / 16);
+  dim3 grid((M + TEAMS - 1) / TEAMS, F);
+  hipLaunchKernelGGL(radar::k1_taps<N>, grid, dim3(radar::kBlock), 0, s, a);
+}
+template <int M>
+void launch_k2_m(const radar::K2Args& a, int n_cp, int F, hipStream_t s) {
+  constexpr int TEAMS = radar::kBlock / (M / 16);
+  dim3 grid((n_cp + TEAMS - 1) / TEAMS, F);
+  hipLaunchKernelGGL(radar::k2_doppler<M>, grid, dim3(radar::kBlock), 0, s, a);
+}
+template <int N, int F2>
+void launch_k3_nf(const radar::K3Args& a, int m_pad, int F, hipStream_t s) {
+  constexpr int TEAMS = radar::kBlock / (N / 16);
+  dim3 grid((m_pad + TEAMS - 1) / TEAMS, F);
+  hipLaunchKernelGGL((radar::k3_range_power<N, F2>), grid, dim3(radar::kBlock), 0, s, a);
+}
+template <int N>
+void launch_k3_n(const radar::K3Args& a, int f2, int m_pad, int F, hipStream_t s) {
+  switch (f2) {
+    case 1: launch_k3_nf<N, 1>(a, m_pad, F, s); break;
+    case 2: launch_k3_nf<N, 2>(a, m_pad, F, s); break;
+    case 4: launch_k3_nf<N, 4>(a, m_pad, F, s); break;
+    default: launch_k3_nf<N, 8>(a, m_pad, F, s); break;
+  }
+}
+
+#define RADAR_SIZE_SWITCH(n, CALL) \
+  switch (n) {                     \
+    case 16: CALL(16); break;      \
+    case 32: CALL(32); break;      \
+    case 64: CALL(64); break;      \
+    case 128: CALL(128); break;    \
+    case 256: CALL(256); break;    \
+    case 512: CALL(512); break;    \
+    case 1024: CALL(1024); break;  \
+    case 2048: CALL(2048); break;  \
+    default: CALL(4096); break;    \
+  }
+
+// K1 -> K2 -> K3 for one batch of frames with a common descriptor.
+int enqueue_transforms(const radar_frame_desc* d, int F, const float2* in, const float2* A,
+                       int64_t frame_stride, int from_h, float* P, int64_t p_stride, uint32_t* status,
+                       const FrameWs& w, char* ws, hipStream_t s) {
+  const int N = d->n_sub, M = d->n_sym;
+  float2* taps = reinterpret_cast<float2*>(ws);
+  float2* U = reinterpret_cast<float2*>(ws + w.taps);
+
+  radar::K1Args a1{};
+  a1.Y = in;
+  a1.A = A;
+  a1.ld = d->ld;
+  a1.frame_stride = frame_stride;
+  a1.taps = taps;
+  a1.status = status;
+  a1.M = M;
+  a1.n_cp = d->n_cp;
+  a1.zc_on = d->zc_mode == RADAR_ZC_DIAG;
+  const int64_t two_n = 2 * (int64_t)N;
+  a1.zc_root = (uint32_t)(((d->zc_root % two_n) + two_n) % two_n);
+  a1.zc_shift = (uint32_t)(((d->zc_shift % two_n) + two_n) % two_n);
+  a1.window = d->window;
+  a1.from_h = from_h;
+  a1.tw_shift_2n = tw_shift(2 * N);
+  a1.tw_shift_m = tw_shift(M);
+  a1.inv_n = 1.0f / (float)N;
+  int slot = timer_open(RADAR_STAGE_TAPS, s);
+#define K1_CALL(n) launch_k1_n<n>(a1, M, F, s)
+  RADAR_SIZE_SWITCH(N, K1_CALL)
+#undef K1_CALL
+  timer_close(RADAR_STAGE_TAPS, slot, s);
+  RADAR_HIP_CHECK(hipGetLastError());
+
+  radar::K2Args a2{};
+  a2.taps = taps;
+  a2.U = U;
+  a2.M = M;
+  a2.m_pad = d->m_pad;
+  a2.n_cp = d->n_cp;
+  a2.fm = d->m_pad / M;
+  a2.tw_shift_mp = tw_shift(d->m_pad);
+  slot = timer_open(RADAR_STAGE_DOPPLER, s);
+#define K2_CALL(m) launch_k2_m<m>(a2, d->n_cp, F, s)
+  RADAR_SIZE_SWITCH(M, K2_CALL)
+#undef K2_CALL
+  timer_close(RADAR_STAGE_DOPPLER, slot, s);
+  RADAR_HIP_CHECK(hipGetLastError());
+
+  radar::K3Args a3{};
+  a3.U = U;
+  a3.P = P;
+  a3.p_stride = p_stride;
+  a3.m_pad = d->m_pad;
+  a3.n_pad = d->n_pad;
+  a3.n_cp = d->n_cp;
+  a3.window = d->window;
+  a3.tw_shift_n = tw_shift(N);
+  a3.tw_shift_np = tw_shift(d->n_pad);
+  a3.scale = (float)(1.0 / ((double)N * (double)M));
+  const int f2 = d->n_pad / N;
+  slot = timer_open(RADAR_STAGE_RANGE, s);
+#define K3_CALL(n) launch_k3_n<n>(a3, f2, d->m_pad, F, s)
+  RADAR_SIZE_SWITCH(N, K3_CALL)
+#undef K3_CALL
+  timer_close(RADAR_STAGE_RANGE, slot, s);
+  RADAR_HIP_CHECK(hipGetLastError());
+  return RADAR_OK;
+}
+
+int enqueue_peaks(const float* P, int64_t p_stride, int m_pad, int n_pad, int F, int k, uint64_t* cand,
+                  radar_peak* peaks, int32_t* n_peaks, hipStream_t s) {
+  const int slot = timer_open(RADAR_STAGE_PEAKS, s);
+  hipLaunchKernelGGL(radar::k_peak_rows, dim3(m_pad, F), dim3(256), n_pad * sizeof(uint32_t), s, P, p_stride,
+                     m_pad, n_pad, k, cand);
+  RADAR_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(radar::k_peak_merge, dim3(F), dim3(1024), 0, s, cand, m_pad, n_pad, k, peaks, n_peaks);
+  RADAR_HIP_CHECK(hipGetLastError());
+  timer_close(RADAR_STAGE_PEAKS, slot, s);
+  return RADAR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int radar_version(void) { return 100; }
+
+const char* radar_status_string(int code) {
+  switch (code) {
+    case RADAR_OK: return "ok";
+    case RADAR_E_ARG: return "invalid argument";
+    case RADAR_E_UNSUPPORTED: return "unsupported size";
+    case RADAR_E_WORKSPACE: return "workspace too small";
+    case RADAR_E_HIP: return "HIP runtime error";
+    case RADAR_E_NOT_COPRIME: return "ZC root not relatively prime to N";
+    default: return "unknown status code";
+  }
+}
+
+int radar_init(void) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return RADAR_E_HIP;
+  if (dev < 0 || dev >= kMaxDevices) return RADAR_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_init_mu);
+  if (g_init_done[dev]) return RADAR_OK;
+  std::vector<float2> tab(RADAR_TW_LMAX);
+  for (int t = 0; t < RADAR_TW_LMAX; ++t) {
+    // exp(-2 pi i t/L); reduce to the first quadrant so that symmetric entries
+    // are computed from the same double value.
+    const int q = t / (RADAR_TW_LMAX / 4);
+    const int rem = t % (RADAR_TW_LMAX / 4);
+    const double ang = 2.0 * M_PI * (double)rem / (double)RADAR_TW_LMAX;
+    const double c = std::cos(ang), sn = std::sin(ang);
+    double re, im;  // exp(-i(ang + q pi/2))
+    switch (q) {
+      case 0: re = c; im = -sn; break;
+      case 1: re = -sn; im = -c; break;
+      case 2: re = -c; im = sn; break;
+      default: re = sn; im = c; break;
+    }
+    tab[t] = make_float2((float)re, (float)im);
+  }
+  if (hipMemcpyToSymbol(HIP_SYMBOL(g_radar_tw), tab.data(), tab.size() * sizeof(float2), 0,
+                        hipMemcpyHostToDevice) != hipSuccess)
+    return RADAR_E_HIP;
+  g_init_done[dev] = true;
+  return RADAR_OK;
+}
+
+size_t radar_frame_workspace_size(const radar_frame_desc* d, int32_t n_frames, int32_t k) {
+  if (validate_desc(d) != RADAR_OK || n_frames < 1 || k < 1) return 0;
+  return frame_ws_layout(d, n_frames, k).total;
+}
+
+static int check_frame_common(const radar_frame_desc* d, int32_t n_frames, int64_t frame_stride,
+                              int64_t p_frame_stride, const void* P) {
+  const int rc = validate_desc(d);
+  if (rc != RADAR_OK) return rc;
+  if (n_frames < 1 || n_frames > 65535) return RADAR_E_ARG;
+  if (!P || (reinterpret_cast<uintptr_t>(P) & 15)) return RADAR_E_ARG;
+  const int64_t frame_elems = (int64_t)(d->n_sym - 1) * d->ld + d->n_sub;
+  if (n_frames > 1 && frame_stride < frame_elems) return RADAR_E_ARG;
+  if (p_frame_stride % 4 != 0) return RADAR_E_ARG;
+  if (n_frames > 1 && p_frame_stride < (int64_t)d->m_pad * d->n_pad) return RADAR_E_ARG;
+  return RADAR_OK;
+}
+
+int radar_frame_process(const radar_frame_desc* d, int32_t n_frames, const radar_cf32* Y, const radar_cf32* A,
+                        int64_t frame_stride, float* P, int64_t p_frame_stride, int32_t k, radar_peak* peaks,
+                        int32_t* n_peaks, uint32_t* status, void* ws, size_t ws_bytes, void* hip_stream) {
+  int rc = check_frame_common(d, n_frames, frame_stride, p_frame_stride, P);
+  if (rc != RADAR_OK) return rc;
+  if (!Y || !A || !peaks || !n_peaks || !status || !ws) return RADAR_E_ARG;
+  if (k < 1 || k > 64) return RADAR_E_ARG;
+  const FrameWs w = frame_ws_layout(d, n_frames, k);
+  if (ws_bytes < w.total) return RADAR_E_WORKSPACE;
+  if ((rc = ensure_init()) != RADAR_OK) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  hipLaunchKernelGGL(radar::k0_clear, dim3((n_frames + 255) / 256), dim3(256), 0, s, status, n_peaks, n_frames);
+  RADAR_HIP_CHECK(hipGetLastError());
+  char* wsb = static_cast<char*>(ws);
+  rc = enqueue_transforms(d, n_frames, reinterpret_cast<const float2*>(Y), reinterpret_cast<const float2*>(A),
+                          frame_stride, 0, P, p_frame_stride, status, w, wsb, s);
+  if (rc != RADAR_OK) return rc;
+  return enqueue_peaks(P, p_frame_stride, d->m_pad, d->n_pad, n_frames, k,
+                       reinterpret_cast<uint64_t*>(wsb + w.taps + w.U), peaks, n_peaks, s);
+}
+
+int radar_periodogram(const radar_frame_desc* d, int32_t n_frames, const radar_cf32* H, int64_t frame_stride,
+                      float* P, int64_t p_frame_stride, void* ws, size_t ws_bytes, void* hip_stream) {
+  int rc = check_frame_common(d, n_frames, frame_stride, p_frame_stride, P);
+  if (rc != RADAR_OK) return rc;
+  if (!H || !ws) return RADAR_E_ARG;
+  if (d->zc_mode != RADAR_ZC_NONE) return RADAR_E_ARG;
+  const FrameWs w = frame_ws_layout(d, n_frames, 1);
+  if (ws_bytes < w.total) return RADAR_E_WORKSPACE;
+  if ((rc = ensure_init()) != RADAR_OK) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  return enqueue_transforms(d, n_frames, reinterpret_cast<const float2*>(H), nullptr, frame_stride, 1, P,
+                            p_frame_stride, nullptr, w, static_cast<char*>(ws), s);
+}
+
+size_t radar_detect_workspace_size(int32_t m_pad, int32_t n_pad, int32_t n_frames, int32_t k) {
+  if (m_pad < 4 || n_pad < 4 || !is_pow2(m_pad) || !is_pow2(n_pad) || m_pad > 16384 || n_pad > 16384 ||
+      n_frames < 1 || k < 1)
+    return 0;
+  return align256((size_t)n_frames * m_pad * (size_t)k * sizeof(uint64_t));
+}
+
+int radar_detect_topk(const float* P, int32_t m_pad, int32_t n_pad, int32_t n_frames, int64_t p_frame_stride,
+                      int32_t k, radar_peak* peaks, int32_t* n_peaks, void* ws, size_t ws_bytes,
+                      void* hip_stream) {
+  if (!P || !peaks || !n_peaks || !ws) return RADAR_E_ARG;
+  if (m_pad < 4 || n_pad < 4 || !is_pow2(m_pad) || !is_pow2(n_pad)) return RADAR_E_UNSUPPORTED;
+  if (m_pad > 16384 || n_pad > 16384) return RADAR_E_UNSUPPORTED;
+  if (n_frames < 1 || n_frames > 65535 || k < 1 || k > 64) return RADAR_E_ARG;
+  if (n_frames > 1 && p_frame_stride < (int64_t)m_pad * n_pad) return RADAR_E_ARG;
+  if (ws_bytes < radar_detect_workspace_size(m_pad, n_pad, n_frames, k)) return RADAR_E_WORKSPACE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  hipLaunchKernelGGL(radar::k0_clear, dim3((n_frames + 255) / 256), dim3(256), 0, s, nullptr, n_peaks, n_frames);
+  RADAR_HIP_CHECK(hipGetLastError());
+  return enqueue_peaks(P, p_frame_stride, m_pad, n_pad, n_frames, k, static_cast<uint64_t*>(ws), peaks, n_peaks,
+                       s);
+}
+
+int radar_timing_start(int32_t max_launches) {
+  if (max_launches < 1 || max_launches > (1 << 20)) return RADAR_E_ARG;
+  if (g_timer.on) return RADAR_E_ARG;
+  for (int st = 0; st < RADAR_NUM_STAGES; ++st) {
+    g_timer.ev[st].assign(2 * (size_t)max_launches, nullptr);
+    for (auto& e : g_timer.ev[st])
+      if (hipEventCreate(&e) != hipSuccess) return RADAR_E_HIP;
+    g_timer.used[st] = 0;
+  }
+  g_timer.cap = max_launches;
+  g_timer.on = true;
+  return RADAR_OK;
+}
+
+int radar_timing_stop(double* ms_total, int64_t* launches) {
+  if (!g_timer.on) return RADAR_E_ARG;
+  g_timer.on = false;
+  int rc = RADAR_OK;
+  for (int st = 0; st < RADAR_NUM_STAGES; ++st) {
+    double tot = 0.0;
+    for (int i = 0; i < g_timer.used[st]; ++i) {
+      float ms = 0.0f;
+      if (hipEventSynchronize(g_timer.ev[st][2 * i + 1]) != hipSuccess ||
+          hipEventElapsedTime(&ms, g_timer.ev[st][2 * i], g_timer.ev[st][2 * i + 1]) != hipSuccess)
+        rc = RADAR_E_HIP;
+      tot += ms;
+    }
+    if (ms_total) ms_total[st] = tot;
+    if (launches) launches[st] = g_timer.used[st];
+    for (auto& e : g_timer.ev[st])
+      if (e) hipEventDestroy(e);
+    g_timer.ev[st].clear();
+    g_timer.used[st] = 0;
+  }
+  return rc;
+}
+
+}  // extern "C"

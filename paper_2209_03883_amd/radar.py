@@ -1,0 +1,259 @@
+"""Python binding of libradar (include/radar.h).
+
+Argument marshalling only: every step of the receive path runs in the HIP
+library.  torch supplies device memory and the stream; it computes nothing
+here.  The binding refuses to run when the library is not built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+PKG_DIR = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG_DIR, "libradar.so")
+
+RADAR_OK = 0
+RADAR_E_ARG = -1
+RADAR_E_UNSUPPORTED = -2
+RADAR_E_WORKSPACE = -3
+RADAR_E_HIP = -4
+RADAR_E_NOT_COPRIME = -5
+
+WIN_RECT, WIN_HANN, WIN_HAMMING = 0, 1, 2
+ZC_NONE, ZC_DIAG = 0, 1
+ST_ZERO_SYMBOL, ST_NONFINITE = 1, 2
+
+EXPORTED = (
+    "radar_version", "radar_status_string", "radar_init",
+    "radar_frame_workspace_size", "radar_frame_process", "radar_periodogram",
+    "radar_detect_workspace_size", "radar_detect_topk", "radar_timing_start", "radar_timing_stop",
+)
+STAGES = ("taps", "doppler", "range", "peaks")
+
+
+class RadarError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {status_string(code)} ({code})")
+
+
+class FrameDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_sub", ctypes.c_int32), ("n_sym", ctypes.c_int32),
+        ("n_pad", ctypes.c_int32), ("m_pad", ctypes.c_int32),
+        ("n_cp", ctypes.c_int32), ("zc_mode", ctypes.c_int32),
+        ("zc_root", ctypes.c_int32), ("zc_shift", ctypes.c_int32),
+        ("window", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("ld", ctypes.c_int64),
+    ]
+
+
+class Peak(ctypes.Structure):
+    _fields_ = [("s", ctypes.c_int32), ("r", ctypes.c_int32), ("p", ctypes.c_float),
+                ("s_off", ctypes.c_float), ("r_off", ctypes.c_float)]
+
+
+PEAK_WORDS = ctypes.sizeof(Peak) // 4  # 5 x 32-bit words
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libradar.so; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2209_03883_amd.build_lib")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    dp = ctypes.POINTER(FrameDesc)
+    L.radar_version.restype = ctypes.c_int
+    L.radar_status_string.restype = ctypes.c_char_p
+    L.radar_status_string.argtypes = [ctypes.c_int]
+    L.radar_init.restype = ctypes.c_int
+    L.radar_frame_workspace_size.restype = sz
+    L.radar_frame_workspace_size.argtypes = [dp, i32, i32]
+    L.radar_frame_process.restype = ctypes.c_int
+    L.radar_frame_process.argtypes = [dp, i32, vp, vp, i64, vp, i64, i32, vp, vp, vp, vp, sz, vp]
+    L.radar_periodogram.restype = ctypes.c_int
+    L.radar_periodogram.argtypes = [dp, i32, vp, i64, vp, i64, vp, sz, vp]
+    L.radar_detect_workspace_size.restype = sz
+    L.radar_detect_workspace_size.argtypes = [i32, i32, i32, i32]
+    L.radar_detect_topk.restype = ctypes.c_int
+    L.radar_detect_topk.argtypes = [vp, i32, i32, i32, i64, i32, vp, vp, vp, sz, vp]
+    L.radar_timing_start.restype = ctypes.c_int
+    L.radar_timing_start.argtypes = [i32]
+    L.radar_timing_stop.restype = ctypes.c_int
+    L.radar_timing_stop.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    _lib = L
+    return L
+
+
+def status_string(code: int) -> str:
+    return lib().radar_status_string(int(code)).decode()
+
+
+def _check(code: int, where: str):
+    if code != RADAR_OK:
+        raise RadarError(code, where)
+
+
+@dataclass
+class Config:
+    """One frame shape (the fields of radar_frame_desc)."""
+
+    n_sub: int
+    n_sym: int
+    n_pad: int
+    m_pad: int
+    n_cp: int
+    zc_root: int | None = None
+    zc_shift: int = 0
+    window: int = WIN_HANN
+
+    def desc(self, ld: int | None = None) -> FrameDesc:
+        return FrameDesc(self.n_sub, self.n_sym, self.n_pad, self.m_pad, self.n_cp,
+                         ZC_NONE if self.zc_root is None else ZC_DIAG,
+                         0 if self.zc_root is None else int(self.zc_root), int(self.zc_shift),
+                         int(self.window), 0, int(self.n_sub if ld is None else ld))
+
+
+def _stream_ptr(stream) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+def _as_frames(x: torch.Tensor, cfg: Config, name: str) -> torch.Tensor:
+    if not x.is_cuda or x.dtype != torch.complex64:
+        raise TypeError(f"{name} must be a complex64 CUDA tensor")
+    if x.dim() == 2:
+        x = x.unsqueeze(0)
+    if x.dim() != 3 or tuple(x.shape[1:]) != (cfg.n_sym, cfg.n_sub):
+        raise ValueError(f"{name} must have shape (F, {cfg.n_sym}, {cfg.n_sub})")
+    if x.stride(2) != 1 or x.stride(1) < cfg.n_sub:
+        raise ValueError(f"{name} must have contiguous subcarriers")
+    return x
+
+
+def _frame_stride(x: torch.Tensor) -> int:
+    return int(x.stride(0)) if x.shape[0] > 1 else int(x.shape[1] * x.stride(1))
+
+
+def workspace_bytes(cfg: Config, n_frames: int, k: int = 1) -> int:
+    n = lib().radar_frame_workspace_size(ctypes.byref(cfg.desc()), int(n_frames), int(k))
+    if n == 0:
+        raise RadarError(RADAR_E_ARG, "radar_frame_workspace_size")
+    return int(n)
+
+
+def new_workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def alloc_peaks(n_frames: int, k: int, device) -> torch.Tensor:
+    """Peaks buffer: int32 tensor (F, k, 5) holding radar_peak structs."""
+    return torch.zeros((n_frames, k, PEAK_WORDS), dtype=torch.int32, device=device)
+
+
+def unpack_peaks(peaks: torch.Tensor, n_peaks: torch.Tensor):
+    """Host list (per frame) of (s, r, p, s_off, r_off) tuples."""
+    pk = peaks.cpu()
+    fl = pk.view(torch.float32)
+    out = []
+    for f in range(pk.shape[0]):
+        n = int(n_peaks[f])
+        out.append([(int(pk[f, i, 0]), int(pk[f, i, 1]), float(fl[f, i, 2]), float(fl[f, i, 3]),
+                     float(fl[f, i, 4])) for i in range(n)])
+    return out
+
+
+def frame_process(Y: torch.Tensor, A: torch.Tensor, cfg: Config, k: int, *, P: torch.Tensor | None = None,
+                  workspace: torch.Tensor | None = None, peaks: torch.Tensor | None = None,
+                  n_peaks: torch.Tensor | None = None, status: torch.Tensor | None = None, stream=None):
+    """radar_frame_process on F frames: returns (P, peaks, n_peaks, status) device tensors."""
+    L = lib()
+    Y = _as_frames(Y, cfg, "Y")
+    A = _as_frames(A, cfg, "A")
+    if Y.stride() != A.stride() or Y.shape != A.shape:
+        raise ValueError("Y and A must share shape and strides")
+    F = Y.shape[0]
+    dev = Y.device
+    if P is None:
+        P = torch.empty((F, cfg.m_pad, cfg.n_pad), dtype=torch.float32, device=dev)
+    if peaks is None:
+        peaks = alloc_peaks(F, k, dev)
+    if n_peaks is None:
+        n_peaks = torch.zeros(F, dtype=torch.int32, device=dev)
+    if status is None:
+        status = torch.zeros(F, dtype=torch.int32, device=dev)
+    desc = cfg.desc(ld=Y.stride(1))
+    need = workspace_bytes(cfg, F, k)
+    if workspace is None or workspace.numel() < need:
+        workspace = new_workspace(need, dev)
+    rc = L.radar_frame_process(ctypes.byref(desc), F, Y.data_ptr(), A.data_ptr(), _frame_stride(Y),
+                               P.data_ptr(), int(P.stride(0)) if P.dim() == 3 else cfg.m_pad * cfg.n_pad,
+                               int(k), peaks.data_ptr(), n_peaks.data_ptr(), status.data_ptr(),
+                               workspace.data_ptr(), workspace.numel(), _stream_ptr(stream))
+    _check(rc, "radar_frame_process")
+    return P, peaks, n_peaks, status
+
+
+def periodogram(H: torch.Tensor, cfg: Config, *, P: torch.Tensor | None = None,
+                workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """radar_periodogram: Eq. 17 (with DFT-CE when n_cp < N) from an LS estimate H."""
+    L = lib()
+    if cfg.zc_root is not None:
+        raise ValueError("radar_periodogram takes a de-precoded estimate (zc_root=None)")
+    H = _as_frames(H, cfg, "H")
+    F = H.shape[0]
+    if P is None:
+        P = torch.empty((F, cfg.m_pad, cfg.n_pad), dtype=torch.float32, device=H.device)
+    need = workspace_bytes(cfg, F, 1)
+    if workspace is None or workspace.numel() < need:
+        workspace = new_workspace(need, H.device)
+    rc = L.radar_periodogram(ctypes.byref(cfg.desc(ld=H.stride(1))), F, H.data_ptr(), _frame_stride(H),
+                             P.data_ptr(), int(P.stride(0)), workspace.data_ptr(), workspace.numel(),
+                             _stream_ptr(stream))
+    _check(rc, "radar_periodogram")
+    return P
+
+
+def detect_topk(P: torch.Tensor, k: int, *, workspace: torch.Tensor | None = None, stream=None):
+    """radar_detect_topk on F periodograms (F, M', N'): returns (peaks, n_peaks)."""
+    L = lib()
+    if not P.is_cuda or P.dtype != torch.float32:
+        raise TypeError("P must be a float32 CUDA tensor")
+    if P.dim() == 2:
+        P = P.unsqueeze(0)
+    if P.stride(2) != 1 or P.stride(1) != P.shape[2]:
+        raise ValueError("P rows must be contiguous")
+    F, m_pad, n_pad = P.shape
+    need = L.radar_detect_workspace_size(m_pad, n_pad, F, int(k))
+    if need == 0:
+        raise RadarError(RADAR_E_UNSUPPORTED, "radar_detect_workspace_size")
+    if workspace is None or workspace.numel() < need:
+        workspace = new_workspace(need, P.device)
+    peaks = alloc_peaks(F, k, P.device)
+    n_peaks = torch.zeros(F, dtype=torch.int32, device=P.device)
+    rc = L.radar_detect_topk(P.data_ptr(), m_pad, n_pad, F, int(P.stride(0)), int(k), peaks.data_ptr(),
+                             n_peaks.data_ptr(), workspace.data_ptr(), workspace.numel(), _stream_ptr(stream))
+    _check(rc, "radar_detect_topk")
+    return peaks, n_peaks
+
+
+def timing_start(max_launches: int):
+    """Start per-stage HIP-event timing inside the library (profiling aid)."""
+    _check(lib().radar_timing_start(int(max_launches)), "radar_timing_start")
+
+
+def timing_stop():
+    """Stop stage timing; returns {stage: (total_ms, launches)}."""
+    ms = (ctypes.c_double * len(STAGES))()
+    cnt = (ctypes.c_int64 * len(STAGES))()
+    _check(lib().radar_timing_stop(ms, cnt), "radar_timing_stop")
+    return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(STAGES)}

@@ -1,0 +1,104 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared
+symbol, sizes workspaces, and rejects bad arguments before touching the GPU."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "radar.h")
+
+radar = pytest.importorskip("paper_2209_03883_amd.radar")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(radar_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for want in ("radar_frame_process", "radar_periodogram", "radar_detect_topk"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = radar.lib()
+    missing = [n for n in _declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+    assert radar.EXPORTED and set(radar.EXPORTED) <= set(_declared_functions())
+
+
+def test_status_strings():
+    assert radar.status_string(0) == "ok"
+    assert "coprime" in radar.status_string(radar.RADAR_E_NOT_COPRIME) or \
+        "prime" in radar.status_string(radar.RADAR_E_NOT_COPRIME)
+    assert radar.status_string(-99) == "unknown status code"
+
+
+def _ws(cfg, F=1, k=8):
+    return radar.lib().radar_frame_workspace_size(ctypes.byref(cfg.desc()), F, k)
+
+
+def test_workspace_size_arithmetic():
+    cfg = radar.Config(1024, 1024, 4096, 4096, 256, zc_root=7)
+    taps = 1024 * 256 * 8
+    U = 4096 * 256 * 8
+    cand = 4096 * 8 * 8
+    assert _ws(cfg, 1, 8) == taps + U + cand
+    assert _ws(cfg, 3, 8) == 3 * (taps + U + cand)
+    assert radar.lib().radar_detect_workspace_size(4096, 4096, 2, 8) == 2 * 4096 * 8 * 8
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(n_sub=1000), radar.RADAR_E_UNSUPPORTED),     # not a power of two
+    (dict(n_sub=8, n_cp=8, n_pad=64), radar.RADAR_E_UNSUPPORTED),  # below the smallest FFT
+    (dict(n_sym=8192, m_pad=8192), radar.RADAR_E_UNSUPPORTED),
+    (dict(n_pad=512), radar.RADAR_E_ARG),              # N' < N
+    (dict(n_pad=16384), radar.RADAR_E_UNSUPPORTED),    # N'/N = 16
+    (dict(n_cp=0), radar.RADAR_E_ARG),
+    (dict(n_cp=1025), radar.RADAR_E_ARG),
+    (dict(window=7), radar.RADAR_E_ARG),
+    (dict(zc_root=8), radar.RADAR_E_NOT_COPRIME),      # gcd(8, 1024) != 1
+])
+def test_validation_rejects(bad, code):
+    base = dict(n_sub=1024, n_sym=1024, n_pad=4096, m_pad=4096, n_cp=256, zc_root=7)
+    base.update(bad)
+    cfg = radar.Config(**base)
+    L = radar.lib()
+    assert L.radar_frame_workspace_size(ctypes.byref(cfg.desc()), 1, 8) == 0
+    # radar_frame_process validates before any HIP call: dummy non-null pointers are never touched
+    dummy = 256
+    rc = L.radar_frame_process(ctypes.byref(cfg.desc()), 1, dummy, dummy, 0, dummy, 0, 8, dummy, dummy,
+                               dummy, dummy, 1 << 40, None)
+    assert rc == code
+
+
+def test_process_rejects_bad_pointers_and_workspace():
+    cfg = radar.Config(256, 64, 1024, 256, 32, zc_root=1)
+    L = radar.lib()
+    d = ctypes.byref(cfg.desc())
+    need = L.radar_frame_workspace_size(d, 1, 3)
+    p = 256
+    assert L.radar_frame_process(d, 1, None, p, 0, p, 0, 3, p, p, p, p, need, None) == radar.RADAR_E_ARG
+    assert L.radar_frame_process(d, 1, p, p, 0, p + 4, 0, 3, p, p, p, p, need, None) == radar.RADAR_E_ARG  # P misaligned
+    assert L.radar_frame_process(d, 1, p, p, 0, p, 0, 0, p, p, p, p, need, None) == radar.RADAR_E_ARG     # k = 0
+    assert L.radar_frame_process(d, 1, p, p, 0, p, 0, 65, p, p, p, p, need, None) == radar.RADAR_E_ARG    # k > 64
+    assert L.radar_frame_process(d, 1, p, p, 0, p, 0, 3, p, p, p, p, need - 1, None) == radar.RADAR_E_WORKSPACE
+    assert L.radar_frame_process(d, 0, p, p, 0, p, 0, 3, p, p, p, p, need, None) == radar.RADAR_E_ARG     # no frames
+    # overlapping frames
+    assert L.radar_frame_process(d, 2, p, p, 100, p, 1024 * 256, 3, p, p, p, p, 10 * need, None) == radar.RADAR_E_ARG
+    # periodogram refuses ZC mode
+    assert L.radar_periodogram(d, 1, p, 0, p, 0, p, need, None) == radar.RADAR_E_ARG
+
+
+def test_detect_rejects():
+    L = radar.lib()
+    p = 256
+    assert L.radar_detect_topk(p, 100, 64, 1, 0, 3, p, p, p, 1 << 20, None) == radar.RADAR_E_UNSUPPORTED
+    assert L.radar_detect_topk(p, 64, 64, 1, 0, 0, p, p, p, 1 << 20, None) == radar.RADAR_E_ARG
+    assert L.radar_detect_topk(p, 64, 64, 1, 0, 3, p, p, p, 10, None) == radar.RADAR_E_WORKSPACE
+    assert L.radar_detect_topk(None, 64, 64, 1, 0, 3, p, p, p, 1 << 20, None) == radar.RADAR_E_ARG
