@@ -5,14 +5,16 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-// The twiddle table holds W^t = exp(-2*pi*i*t / RADAR_TW_LMAX) for
-// t in [0, RADAR_TW_LMAX), each value computed on the host in double
-// precision and rounded once to float.  W_L^x for a power-of-two L that
-// divides RADAR_TW_LMAX is entry x * (RADAR_TW_LMAX / L).
+// Twiddle table, one contiguous block per power-of-two length:
+//   g_radar_tw[L + x] = W_L^x = exp(-2*pi*i*x/L),   L = 1, 2, 4, ..., RADAR_TW_LMAX,  0 <= x < L,
+// each value computed on the host in double precision and rounded once to
+// float.  Blocks are contiguous so that the entries one FFT stage touches sit
+// together in cache.
 #define RADAR_TW_LOG2 14
 #define RADAR_TW_LMAX (1 << RADAR_TW_LOG2)
+#define RADAR_TW_ENTRIES (2 * RADAR_TW_LMAX)
 
-extern __device__ float2 g_radar_tw[RADAR_TW_LMAX];
+extern __device__ float2 g_radar_tw[RADAR_TW_ENTRIES];
 
 namespace radar {
 
@@ -29,15 +31,21 @@ __device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
 }
 __device__ __forceinline__ float cabs2(float2 a) { return a.x * a.x + a.y * a.y; }
 
-// exp(-2*pi*i*t/L) for L = RADAR_TW_LMAX >> shift, t < L.
-__device__ __forceinline__ float2 twiddle(int t, int shift) { return g_radar_tw[t << shift]; }
+// W_L^x = exp(-2*pi*i*x/L) for a power-of-two L <= RADAR_TW_LMAX and 0 <= x < L.
+__device__ __forceinline__ float2 twiddle(int L, int x) { return g_radar_tw[L + x]; }
 
-// Periodic window value w(i) of length L = RADAR_TW_LMAX >> shift
-// (Hann: 0.5 - 0.5 cos(2 pi i/L); Hamming: 0.54 - 0.46 cos(2 pi i/L); rect: 1).
-__device__ __forceinline__ float window_value(int kind, int i, int shift) {
+// Periodic window value w(i) of length L (a power of two):
+// Hann 0.5 - 0.5 cos(2 pi i/L); Hamming 0.54 - 0.46 cos(2 pi i/L); rect 1.
+__device__ __forceinline__ float window_value(int kind, int i, int L) {
   if (kind == 0) return 1.0f;
-  const float c = g_radar_tw[i << shift].x;  // cos is even: the table's real part
+  const float c = g_radar_tw[L + i].x;  // cos is even: the table's real part
   return kind == 1 ? 0.5f - 0.5f * c : 0.54f - 0.46f * c;
+}
+
+// The same windows written as w(i) = a0 - a1 cos(2 pi i/L): (a0, a1).
+__device__ __forceinline__ float2 window_coeffs(int kind) {
+  if (kind == 0) return make_float2(1.0f, 0.0f);
+  return kind == 1 ? make_float2(0.5f, 0.5f) : make_float2(0.54f, 0.46f);
 }
 
 }  // namespace radar

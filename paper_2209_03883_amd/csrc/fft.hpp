@@ -1,11 +1,11 @@
 // Register/LDS Stockham FFT used by every radar kernel.
 //
-// A transform of length L (a power of two, 16 <= L <= 4096) is computed by a
-// "team" of T = L/16 threads; each thread holds 16 complex values in
+// A transform of length L (a power of two) is computed by a "team" of
+// T = L/E threads; each thread holds E complex values (E = 4, 8 or 16) in
 // registers in the cyclic layout  v[e] = x[t + T*e].  The transform runs as a
-// sequence of Stockham stages of radix 16 (and one final stage of radix
-// 2, 4 or 8 when L is not a power of 16).  Between stages the team exchanges
-// data through its own LDS region; the last stage leaves its outputs in
+// sequence of Stockham stages of radix E (and one final stage of a smaller
+// radix when L is not a power of E).  Between stages the team exchanges data
+// through its own LDS region; the last stage leaves its outputs in
 // registers, again in the cyclic layout, so X[t + T*e] = v[e] on return and
 // natural order needs no final reordering.
 //
@@ -107,62 +107,69 @@ struct LdsSize {
   static constexpr int value = L + L / 16;
 };
 
-template <int L, int T, int R, int NS, bool INV>
-__device__ __forceinline__ void stockham_stage(float2 (&v)[16], float2* lds, int t) {
-  constexpr int E = 16;
+// One Stockham stage.  `active` = false skips the arithmetic and LDS traffic
+// but keeps the barriers, so a team can sit a transform out while the rest of
+// the work-group runs it.
+template <int L, int E, int R, int NS, bool INV>
+__device__ __forceinline__ void stockham_stage(float2 (&v)[E], float2* lds, int t, bool active) {
+  constexpr int T = L / E;
   constexpr int NB = E / R;                 // butterflies per thread
   constexpr bool LAST = (NS * R == L);
-  constexpr int TWSHIFT = RADAR_TW_LOG2 - __builtin_ctz(NS * R);
+  if (active) {
 #pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    float2 x[R];
+    for (int b = 0; b < NB; ++b) {
+      float2 x[R];
 #pragma unroll
-    for (int m = 0; m < R; ++m) x[m] = v[b + m * NB];
-    const int j = t + T * b;
-    const int k = j & (NS - 1);
-    if constexpr (NS > 1) {
+      for (int m = 0; m < R; ++m) x[m] = v[b + m * NB];
+      const int j = t + T * b;
+      const int k = j & (NS - 1);
+      if constexpr (NS > 1) {
 #pragma unroll
-      for (int m = 1; m < R; ++m) {
-        const float2 w = twiddle(k * m, TWSHIFT);
-        x[m] = INV ? cmulc(x[m], w) : cmul(x[m], w);
+        for (int m = 1; m < R; ++m) {
+          const float2 w = twiddle(NS * R, k * m);
+          x[m] = INV ? cmulc(x[m], w) : cmul(x[m], w);
+        }
       }
-    }
-    Dft<R, INV>::run(x);
-    if constexpr (LAST) {
+      Dft<R, INV>::run(x);
+      if constexpr (LAST) {
 #pragma unroll
-      for (int m = 0; m < R; ++m) v[b + m * NB] = x[m];
-    } else {
-      const int base = (j - k) * R + k;
+        for (int m = 0; m < R; ++m) v[b + m * NB] = x[m];
+      } else {
+        const int base = (j - k) * R + k;
 #pragma unroll
-      for (int m = 0; m < R; ++m) lds[lds_pad(base + m * NS)] = x[m];
+        for (int m = 0; m < R; ++m) lds[lds_pad(base + m * NS)] = x[m];
+      }
     }
   }
   if constexpr (!LAST) {
     __syncthreads();
+    if (active) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = lds[lds_pad(t + T * e)];
+      for (int e = 0; e < E; ++e) v[e] = lds[lds_pad(t + T * e)];
+    }
     __syncthreads();
   }
 }
 
-// Stages from span NS onward: radix 16 while at least 16 remains, then the
-// remainder (2, 4 or 8) as the last stage.
-template <int L, int T, int NS, bool INV>
-__device__ __forceinline__ void fft_stages(float2 (&v)[16], float2* lds, int t) {
+// Stages from span NS onward: radix E while at least E remains, then the
+// remainder as the last stage.
+template <int L, int E, int NS, bool INV>
+__device__ __forceinline__ void fft_stages(float2 (&v)[E], float2* lds, int t, bool active) {
   constexpr int REM = L / NS;
   if constexpr (REM > 1) {
-    constexpr int R = REM >= 16 ? 16 : REM;
-    stockham_stage<L, T, R, NS, INV>(v, lds, t);
-    fft_stages<L, T, NS * R, INV>(v, lds, t);
+    constexpr int R = REM >= E ? E : REM;
+    stockham_stage<L, E, R, NS, INV>(v, lds, t, active);
+    fft_stages<L, E, NS * R, INV>(v, lds, t, active);
   }
 }
 
 // Full L-point transform of the team's data (cyclic layout in and out).
 // Every thread of the work-group must call it (it contains barriers).
-template <int L, bool INV>
-__device__ __forceinline__ void team_fft(float2 (&v)[16], float2* lds, int t) {
-  static_assert(L >= 16 && L <= 4096 && (L & (L - 1)) == 0, "FFT length");
-  fft_stages<L, L / 16, 1, INV>(v, lds, t);
+template <int L, int E, bool INV>
+__device__ __forceinline__ void team_fft(float2 (&v)[E], float2* lds, int t, bool active = true) {
+  static_assert(L >= E && (L & (L - 1)) == 0, "FFT length");
+  static_assert(E == 4 || E == 8 || E == 16, "elements per thread");
+  fft_stages<L, E, 1, INV>(v, lds, t, active);
 }
 
 }  // namespace radar

@@ -29,8 +29,6 @@ struct K1Args {
   uint32_t zc_root, zc_shift;  // reduced modulo 2N (two's complement for negative shifts)
   int window;
   int from_h;             // input already is the LS estimate H
-  int tw_shift_2n;        // twiddle shift for length 2N
-  int tw_shift_m;         // twiddle shift for length M
   float inv_n;            // 1/N
 };
 
@@ -62,7 +60,7 @@ __global__ void __launch_bounds__(kBlock) k1_taps(K1Args a) {
         // 2N divides 2^32, so unsigned wrap-around keeps m_k exact.
         const uint32_t uk = (uint32_t)k;
         const uint32_t m = (a.zc_root * (uk * uk + 2u * a.zc_shift * uk)) & (uint32_t)(2 * N - 1);
-        h = cmul(h, twiddle((int)m, a.tw_shift_2n));  // y * conj(z_k)
+        h = cmul(h, twiddle(2 * N, (int)m));  // y * conj(z_k)
       }
       const float2 s = x[k];
       const float den = cabs2(s);
@@ -76,9 +74,9 @@ __global__ void __launch_bounds__(kBlock) k1_taps(K1Args a) {
     if (!__builtin_isfinite(h.x) || !__builtin_isfinite(h.y)) st |= 2u;
     v[e] = h;
   }
-  team_fft<N, true>(v, lds, t);
+  team_fft<N, 16, true>(v, lds, t);
   if (!active) return;
-  const float scale = window_value(a.window, l, a.tw_shift_m) * a.inv_n;
+  const float scale = window_value(a.window, l, a.M) * a.inv_n;
   float2* out = a.taps + ((int64_t)f * a.M + l) * a.n_cp;
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
@@ -93,7 +91,6 @@ struct K2Args {
   float2* U;              // [F][M'][n_cp], row = fftshifted Doppler index
   int M, m_pad, n_cp;
   int fm;                 // M'/M
-  int tw_shift_mp;        // twiddle shift for length M'
 };
 
 // K2: one team per DFT-CE tap; M'-point Doppler DFT with M non-zero inputs,
@@ -121,9 +118,9 @@ __global__ void __launch_bounds__(kBlock) k2_doppler(K2Args a) {
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int l = t + T * e;
-      v[e] = b == 0 ? x[e] : cmul(x[e], twiddle(l * b, a.tw_shift_mp));
+      v[e] = b == 0 ? x[e] : cmul(x[e], twiddle(a.m_pad, l * b));
     }
-    team_fft<M, false>(v, lds, t);
+    team_fft<M, 16, false>(v, lds, t);
     if (active) {
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
@@ -141,9 +138,8 @@ struct K3Args {
   int64_t p_stride;
   int m_pad, n_pad, n_cp;
   int window;
-  int tw_shift_n;         // twiddle shift for length N
-  int tw_shift_np;        // twiddle shift for length N'
   float scale;            // 1/(N M)
+  float* rowmax;          // [F][M'] row maxima of P (written by the x4 kernel), or null
 };
 
 template <int F2>
@@ -180,9 +176,9 @@ __global__ void __launch_bounds__(kBlock) k3_range_power(K3Args a) {
     const int k = t + T * e;
     X[e] = k < a.n_cp ? in[k] : make_float2(0.0f, 0.0f);
   }
-  team_fft<N, false>(X, lds, t);
+  team_fft<N, 16, false>(X, lds, t);
 #pragma unroll
-  for (int e = 0; e < 16; ++e) X[e] = cscale(X[e], window_value(a.window, t + T * e, a.tw_shift_n));
+  for (int e = 0; e < 16; ++e) X[e] = cscale(X[e], window_value(a.window, t + T * e, N));
 
   float pw[16][F2];
 #pragma unroll
@@ -191,9 +187,9 @@ __global__ void __launch_bounds__(kBlock) k3_range_power(K3Args a) {
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int k = t + T * e;
-      g[e] = b2 == 0 ? X[e] : cmulc(X[e], twiddle(k * b2, a.tw_shift_np));  // X e^{+2 pi i k b2/N'}
+      g[e] = b2 == 0 ? X[e] : cmulc(X[e], twiddle(a.n_pad, k * b2));  // X e^{+2 pi i k b2/N'}
     }
-    team_fft<N, true>(g, lds, t);
+    team_fft<N, 16, true>(g, lds, t);
 #pragma unroll
     for (int e = 0; e < 16; ++e) pw[e][b2] = cabs2(g[e]) * a.scale;
   }
@@ -201,6 +197,136 @@ __global__ void __launch_bounds__(kBlock) k3_range_power(K3Args a) {
   float* dst = a.P + (int64_t)f * a.p_stride + (int64_t)row * a.n_pad;
 #pragma unroll
   for (int e = 0; e < 16; ++e) store_row_chunk<F2>(dst + F2 * (t + T * e), pw[e]);
+}
+
+
+// ------------------------------------------------------------------------
+// K3 for 4x range padding (N' = 4N) and N_cp <= N/4: one work-group row
+// group of four teams per Doppler row.
+//
+//   forward  X[4 k1 + b] = FFT_{N/4}(u_n W_N^{n b})[k1]      (team b; u has
+//            only N_cp <= N/4 non-zero taps, so the N-point DFT of Eq. 22
+//            splits into four N/4-point transforms)
+//   range    G[4 r1 + b] = sum_k w_k X_k e^{+2 pi i k (4 r1 + b)/(4N)}
+//            = IFFT_N(w_k X_k e^{+2 pi i k b/(4N)})[r1]      (team b = 1, 2, 3)
+//   phase 0  G[4 r1] = N (c * u)[r1] with c = IDFT_N(w): for the cosine
+//            windows w_k = a0 - a1 cos(2 pi k/N) this is the 3-tap filter
+//            N (a0 u[r1] - a1/2 (u[r1-1] + u[r1+1]))  (team 0)
+// The four phases meet in LDS, the row leaves as contiguous float4 stores,
+// and the row maximum is reduced on the way out for the peak search.
+// ------------------------------------------------------------------------
+template <int N>
+struct K3x4 {
+  static constexpr int T = N / 16;                    // threads per team
+  static constexpr int GROUP = 4 * T;                 // threads per Doppler row
+  static constexpr int ROWS = GROUP >= 256 ? 1 : 256 / GROUP;
+  static constexpr int BLOCK = GROUP * ROWS;
+  static constexpr int EXCH = LdsSize<N>::value;      // float2 per team exchange region
+  static constexpr int MAIN = 4 * EXCH;               // float2; holds X (N) or the P row (4N floats)
+  static constexpr int UBUF = N / 4 + 3;              // u[-1 .. N/4+1]
+};
+
+template <int N>
+__global__ void __launch_bounds__(K3x4<N>::BLOCK) k3_range_power_x4(K3Args a) {
+  using C = K3x4<N>;
+  constexpr int T = C::T;
+  constexpr int Q = N / 4;
+  __shared__ float2 s_main[C::ROWS][C::MAIN];
+  __shared__ float2 s_u[C::ROWS][C::UBUF];
+  __shared__ float s_max[C::BLOCK / 64];
+  const int g = threadIdx.x / C::GROUP;
+  const int gi = threadIdx.x - g * C::GROUP;
+  const int team = gi / T;
+  const int t = gi - team * T;
+  const int f = blockIdx.y;
+  const int row = blockIdx.x * C::ROWS + g;            // m_pad is a multiple of ROWS
+  float2* main = s_main[g];
+  float2* ub = s_u[g] + 1;                             // ub[i] = u[i], i in [-1, N/4+1]
+
+  // Doppler-row taps u_n, n < N_cp <= N/4 (GROUP = N/4 threads: one each)
+  const float2* in = a.U + ((int64_t)f * a.m_pad + row) * a.n_cp;
+  ub[gi] = gi < a.n_cp ? in[gi] : make_float2(0.0f, 0.0f);
+  if (gi < 2) ub[gi == 0 ? -1 : Q] = make_float2(0.0f, 0.0f);
+  if (gi == 2) ub[Q + 1] = make_float2(0.0f, 0.0f);
+  __syncthreads();
+
+  // forward: team b computes X[4 k1 + b], k1 = t + T e
+  {
+    float2 x[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int n = t + T * e;
+      x[e] = team == 0 ? ub[n] : cmul(ub[n], twiddle(N, n * team));
+    }
+    team_fft<Q, 4, false>(x, main + team * C::EXCH, t);
+    __syncthreads();  // exchange regions are reused for X below
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = 4 * (t + T * e) + team;
+      main[k] = cscale(x[e], window_value(a.window, k, N));
+    }
+  }
+  __syncthreads();
+
+  // range phases
+  const bool fft_team = team != 0;
+  float2 gv[16];
+  if (fft_team) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int k = t + T * e;
+      gv[e] = cmulc(main[k], twiddle(4 * N, k * team));  // X_k e^{+2 pi i k b/(4N)}
+    }
+  }
+  __syncthreads();  // X consumed before the exchange regions overwrite it
+  team_fft<N, 16, true>(gv, main + team * C::EXCH, t, fft_team);
+  float p[16];
+  if (fft_team) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) p[e] = cabs2(gv[e]) * a.scale;
+  } else {
+    const float2 wc = window_coeffs(a.window);
+    const float c0 = (float)N * wc.x, c1 = -0.5f * (float)N * wc.y;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int r1 = t + T * e;
+      float2 gz = make_float2(0.0f, 0.0f);
+      if (r1 <= Q) {
+        gz = cadd(cscale(ub[r1], c0), cscale(cadd(ub[r1 - 1], ub[r1 + 1]), c1));
+      } else if (r1 == N - 1) {
+        gz = cscale(ub[0], c1);                                      // u[N] = u[0] wraps round
+      }
+      p[e] = cabs2(gz) * a.scale;
+    }
+  }
+  __syncthreads();  // exchange regions free: assemble the row
+  float* prow = reinterpret_cast<float*>(main);
+#pragma unroll
+  for (int e = 0; e < 16; ++e) prow[4 * (t + T * e) + team] = p[e];
+  __syncthreads();
+
+  float* dst = a.P + (int64_t)f * a.p_stride + (int64_t)row * (4 * N);
+  float mx = 0.0f;
+#pragma unroll
+  for (int i = gi; i < N; i += C::GROUP) {
+    const float4 q = reinterpret_cast<const float4*>(prow)[i];
+    reinterpret_cast<float4*>(dst)[i] = q;
+    mx = fmaxf(mx, fmaxf(fmaxf(q.x, q.y), fmaxf(q.z, q.w)));
+  }
+  // row maximum over the GROUP threads of this row
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) mx = fmaxf(mx, __shfl_xor(mx, m));
+  if constexpr (C::GROUP >= 64) {
+    if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (gi == 0) {
+      float r = s_max[(g * C::GROUP) >> 6];
+      for (int w = 1; w < C::GROUP / 64; ++w) r = fmaxf(r, s_max[((g * C::GROUP) >> 6) + w]);
+      a.rowmax[(int64_t)f * a.m_pad + row] = r;
+    }
+  } else {
+    if (gi == 0) a.rowmax[(int64_t)f * a.m_pad + row] = mx;
+  }
 }
 
 // Clears the per-frame status and peak-count words (a fill kernel rather than

@@ -5,11 +5,17 @@
 // image of the float value and whose low word is 0xFFFFFFFF - flat index, so
 // "larger key" is exactly "ranks first".  Key 0 means "no candidate".
 //
-//   k_peak_rows   one work-group per row: marks the row's local maxima (its
-//                 two neighbour rows are read too) and emits the row's k best
-//                 keys.  The k best peaks of a frame are among the union of the
-//                 rows' k best, so this is exact.
-//   k_peak_merge  one work-group per frame: the k best keys over all rows.
+// Exact search without scanning every row:
+//   1. m_s = max of row s (written by the range kernel, or k_row_max).
+//   2. If m_s >= m_{s-1} and m_s >= m_{s+1} (cyclically), the cell holding m_s
+//      is >= all its 8 neighbours, i.e. a local maximum of P.  Distinct such
+//      rows give distinct local maxima, so the k-th largest of these m_s is a
+//      lower bound tau on the k-th largest local maximum (tau = -inf when
+//      fewer than k rows qualify).
+//   3. Every local maximum >= tau lies in a row with m_s >= tau: only those
+//      rows are scanned, each for its k best local maxima >= tau.
+//   4. The k best over the scanned rows are the answer.
+// (k_peak_threshold does 2, k_peak_rows_listed 3, k_peak_merge 4.)
 #pragma once
 
 #include "device_common.hpp"
@@ -57,53 +63,145 @@ __device__ __forceinline__ uint64_t block_max_u64(uint64_t v, uint64_t* red) {
   return r;
 }
 
-__global__ void __launch_bounds__(256) k_peak_rows(const float* P, int64_t p_stride, int m_pad, int n_pad,
-                                                   int k, uint64_t* cand) {
-  extern __shared__ uint32_t s_ord[];  // n_pad entries, 0 = not a local maximum
-  __shared__ uint64_t red[4];
-  const int f = blockIdx.y;
-  const int row = blockIdx.x;
-  const float* base = P + (int64_t)f * p_stride;
-  const float* rm = base + (int64_t)((row - 1) & (m_pad - 1)) * n_pad;
-  const float* r0 = base + (int64_t)row * n_pad;
-  const float* rp = base + (int64_t)((row + 1) & (m_pad - 1)) * n_pad;
-  for (int r = threadIdx.x; r < n_pad; r += blockDim.x) {
-    const int rl = (r - 1) & (n_pad - 1);
-    const int rr = (r + 1) & (n_pad - 1);
-    const float v = r0[r];
-    const bool pk = v >= r0[rl] && v >= r0[rr] && v >= rm[rl] && v >= rm[r] && v >= rm[rr] &&
-                    v >= rp[rl] && v >= rp[r] && v >= rp[rr];
-    s_ord[r] = pk ? ord_bits(v) : 0u;
-  }
+__device__ __forceinline__ float block_max_f32(float v, float* red) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) v = fmaxf(v, __shfl_xor(v, m));
+  const int nwaves = (blockDim.x + 63) >> 6;
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  uint64_t* out = cand + ((int64_t)f * m_pad + row) * k;
-  const uint32_t flat0 = (uint32_t)row * (uint32_t)n_pad;
+  float r = red[0];
+  for (int i = 1; i < nwaves; ++i) r = fmaxf(r, red[i]);
+  __syncthreads();
+  return r;
+}
+
+// Row maxima of arbitrary periodograms (used when the range kernel did not
+// produce them).  Grid (m_pad, F), 256 threads.
+__global__ void __launch_bounds__(256) k_row_max(const float* P, int64_t p_stride, int m_pad, int n_pad,
+                                                 float* rowmax) {
+  __shared__ float red[4];
+  const int f = blockIdx.y, row = blockIdx.x;
+  const float* r0 = P + (int64_t)f * p_stride + (int64_t)row * n_pad;
+  float mx = -__builtin_huge_valf();
+  for (int r = threadIdx.x; r < n_pad; r += blockDim.x) mx = fmaxf(mx, r0[r]);
+  mx = block_max_f32(mx, red);
+  if (threadIdx.x == 0) rowmax[(int64_t)f * m_pad + row] = mx;
+}
+
+// Steps 2 and the row list of step 3.  Grid (F), 1024 threads, dynamic LDS
+// m_pad floats.
+__global__ void __launch_bounds__(1024) k_peak_threshold(const float* rowmax, int m_pad, int k, float* tau_out,
+                                                         int32_t* list, int32_t* cnt_out) {
+  extern __shared__ float s_m[];
+  __shared__ uint64_t red[16];
+  __shared__ int32_t s_scan[1024];
+  const int f = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int mask = m_pad - 1;
+  for (int i = tid; i < m_pad; i += blockDim.x) s_m[i] = rowmax[(int64_t)f * m_pad + i];
+  __syncthreads();
+
   uint64_t last = ~0ull;
-  int i = 0;
-  for (; i < k; ++i) {
+  int found = 0;
+  for (; found < k; ++found) {
     uint64_t best = 0;
-    for (int r = threadIdx.x; r < n_pad; r += blockDim.x) {
-      const uint32_t o = s_ord[r];
-      if (o) {
-        const uint64_t key = make_key(o, flat0 + (uint32_t)r);
+    for (int i = tid; i < m_pad; i += blockDim.x) {
+      const float v = s_m[i];
+      if (v >= s_m[(i - 1) & mask] && v >= s_m[(i + 1) & mask]) {
+        const uint64_t key = make_key(ord_bits(v), (uint32_t)i);
         if (key < last && key > best) best = key;
       }
     }
     best = block_max_u64(best, red);
-    if (threadIdx.x == 0) out[i] = best;
     if (best == 0) break;
     last = best;
   }
-  if (threadIdx.x == 0)
-    for (int j = i + 1; j < k; ++j) out[j] = 0;
+  const float tau = found == k ? ord_value((uint32_t)(last >> 32)) : -__builtin_huge_valf();
+
+  // rows with m_s >= tau, ascending: each thread owns a contiguous chunk
+  const int chunk = (m_pad + blockDim.x - 1) / blockDim.x;
+  const int lo = tid * chunk;
+  const int hi = min(lo + chunk, m_pad);
+  int c = 0;
+  for (int i = lo; i < hi; ++i) c += s_m[i] >= tau ? 1 : 0;
+  s_scan[tid] = c;
+  __syncthreads();
+  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+    const int add = tid >= off ? s_scan[tid - off] : 0;
+    __syncthreads();
+    s_scan[tid] += add;
+    __syncthreads();
+  }
+  int pos = s_scan[tid] - c;  // exclusive prefix
+  int32_t* out = list + (int64_t)f * m_pad;
+  for (int i = lo; i < hi; ++i)
+    if (s_m[i] >= tau) out[pos++] = i;
+  if (tid == blockDim.x - 1) {
+    cnt_out[f] = s_scan[tid];
+    tau_out[f] = tau;
+  }
 }
 
-__global__ void __launch_bounds__(1024) k_peak_merge(const uint64_t* cand, int m_pad, int n_pad, int k,
-                                                     radar_peak* peaks, int32_t* n_peaks) {
+// Step 3: exact local maxima >= tau of the listed rows, k best per row.
+// Grid (G, F), 256 threads, dynamic LDS n_pad words.  Output
+// cand[f][j][0..k) for list entry j (key 0 pads).
+__global__ void __launch_bounds__(256) k_peak_rows_listed(const float* P, int64_t p_stride, int m_pad, int n_pad,
+                                                          int k, const float* tau, const int32_t* list,
+                                                          const int32_t* cnt, uint64_t* cand) {
+  extern __shared__ uint32_t s_ord[];  // n_pad entries, 0 = not a candidate
+  __shared__ uint64_t red[4];
+  const int f = blockIdx.y;
+  const int count = cnt[f];
+  const float th = tau[f];
+  const float* base = P + (int64_t)f * p_stride;
+  for (int j = blockIdx.x; j < count; j += gridDim.x) {
+    const int row = list[(int64_t)f * m_pad + j];
+    const float* rm = base + (int64_t)((row - 1) & (m_pad - 1)) * n_pad;
+    const float* r0 = base + (int64_t)row * n_pad;
+    const float* rp = base + (int64_t)((row + 1) & (m_pad - 1)) * n_pad;
+    for (int r = threadIdx.x; r < n_pad; r += blockDim.x) {
+      const float v = r0[r];
+      bool pk = v >= th;
+      if (pk) {
+        const int rl = (r - 1) & (n_pad - 1);
+        const int rr = (r + 1) & (n_pad - 1);
+        pk = v >= r0[rl] && v >= r0[rr] && v >= rm[rl] && v >= rm[r] && v >= rm[rr] && v >= rp[rl] &&
+             v >= rp[r] && v >= rp[rr];
+      }
+      s_ord[r] = pk ? ord_bits(v) : 0u;
+    }
+    __syncthreads();
+    uint64_t* out = cand + ((int64_t)f * m_pad + j) * k;
+    const uint32_t flat0 = (uint32_t)row * (uint32_t)n_pad;
+    uint64_t last = ~0ull;
+    int i = 0;
+    for (; i < k; ++i) {
+      uint64_t best = 0;
+      for (int r = threadIdx.x; r < n_pad; r += blockDim.x) {
+        const uint32_t o = s_ord[r];
+        if (o) {
+          const uint64_t key = make_key(o, flat0 + (uint32_t)r);
+          if (key < last && key > best) best = key;
+        }
+      }
+      best = block_max_u64(best, red);
+      if (threadIdx.x == 0) out[i] = best;
+      if (best == 0) break;
+      last = best;
+    }
+    if (threadIdx.x == 0)
+      for (int q = i + 1; q < k; ++q) out[q] = 0;
+    __syncthreads();  // s_ord is rewritten for the next row
+  }
+}
+
+// Step 4: the k best keys over the scanned rows of a frame.  Grid (F), 1024 threads.
+__global__ void __launch_bounds__(1024) k_peak_merge(const uint64_t* cand, const int32_t* cnt, int m_pad, int n_pad,
+                                                     int k, radar_peak* peaks, int32_t* n_peaks) {
   __shared__ uint64_t red[16];
   const int f = blockIdx.x;
-  const int count = m_pad * k;
-  const uint64_t* c = cand + (int64_t)f * count;
+  const int count = cnt[f] * k;
+  const uint64_t* c = cand + (int64_t)f * m_pad * k;
   uint64_t last = ~0ull;
   int i = 0;
   for (; i < k; ++i) {

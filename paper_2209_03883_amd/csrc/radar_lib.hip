@@ -10,7 +10,7 @@
 #include "../../include/radar.h"
 #include "device_common.hpp"
 
-__device__ float2 g_radar_tw[RADAR_TW_LMAX];
+__device__ float2 g_radar_tw[RADAR_TW_ENTRIES];
 
 #include "k_frame.hpp"
 #include "k_peaks.hpp"
@@ -27,7 +27,6 @@ int ilog2(int64_t x) {
   while ((int64_t(1) << r) < x) ++r;
   return r;
 }
-int tw_shift(int length) { return RADAR_TW_LOG2 - ilog2(length); }
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 int validate_desc(const radar_frame_desc* d) {
@@ -47,17 +46,35 @@ int validate_desc(const radar_frame_desc* d) {
   return RADAR_OK;
 }
 
+// Scratch of the peak search for F frames of m_pad rows (offsets in bytes).
+struct PeakWs {
+  size_t rowmax, tau, cnt, list, cand, total;
+};
+PeakWs peak_ws_layout(int m_pad, int n_frames, int k, size_t base) {
+  PeakWs w;
+  const size_t F = (size_t)n_frames;
+  w.rowmax = base;
+  w.tau = w.rowmax + align256(F * m_pad * sizeof(float));
+  w.cnt = w.tau + align256(F * sizeof(float));
+  w.list = w.cnt + align256(F * sizeof(int32_t));
+  w.cand = w.list + align256(F * m_pad * sizeof(int32_t));
+  w.total = w.cand + align256(F * m_pad * (size_t)k * sizeof(uint64_t));
+  return w;
+}
+
 struct FrameWs {
-  size_t taps, U, cand, total;
+  size_t taps, U;
+  PeakWs pk;
+  size_t total;
 };
 
 FrameWs frame_ws_layout(const radar_frame_desc* d, int n_frames, int k) {
   FrameWs w;
   const size_t F = (size_t)n_frames;
-  w.taps = align256(F * d->n_sym * d->n_cp * sizeof(float2));
-  w.U = align256(F * d->m_pad * d->n_cp * sizeof(float2));
-  w.cand = align256(F * d->m_pad * (size_t)k * sizeof(uint64_t));
-  w.total = w.taps + w.U + w.cand;
+  w.taps = 0;
+  w.U = align256(F * d->n_sym * d->n_cp * sizeof(float2));
+  w.pk = peak_ws_layout(d->m_pad, n_frames, k, w.U + align256(F * d->m_pad * d->n_cp * sizeof(float2)));
+  w.total = w.pk.total;
   return w;
 }
 
@@ -108,6 +125,12 @@ void launch_k3_nf(const radar::K3Args& a, int m_pad, int F, hipStream_t s) {
   hipLaunchKernelGGL((radar::k3_range_power<N, F2>), grid, dim3(radar::kBlock), 0, s, a);
 }
 template <int N>
+void launch_k3x4_n(const radar::K3Args& a, int m_pad, int F, hipStream_t s) {
+  using C = radar::K3x4<N>;
+  dim3 grid(m_pad / C::ROWS, F);
+  hipLaunchKernelGGL(radar::k3_range_power_x4<N>, grid, dim3(C::BLOCK), 0, s, a);
+}
+template <int N>
 void launch_k3_n(const radar::K3Args& a, int f2, int m_pad, int F, hipStream_t s) {
   switch (f2) {
     case 1: launch_k3_nf<N, 1>(a, m_pad, F, s); break;
@@ -135,8 +158,8 @@ int enqueue_transforms(const radar_frame_desc* d, int F, const float2* in, const
                        int64_t frame_stride, int from_h, float* P, int64_t p_stride, uint32_t* status,
                        const FrameWs& w, char* ws, hipStream_t s) {
   const int N = d->n_sub, M = d->n_sym;
-  float2* taps = reinterpret_cast<float2*>(ws);
-  float2* U = reinterpret_cast<float2*>(ws + w.taps);
+  float2* taps = reinterpret_cast<float2*>(ws + w.taps);
+  float2* U = reinterpret_cast<float2*>(ws + w.U);
 
   radar::K1Args a1{};
   a1.Y = in;
@@ -153,8 +176,6 @@ int enqueue_transforms(const radar_frame_desc* d, int F, const float2* in, const
   a1.zc_shift = (uint32_t)(((d->zc_shift % two_n) + two_n) % two_n);
   a1.window = d->window;
   a1.from_h = from_h;
-  a1.tw_shift_2n = tw_shift(2 * N);
-  a1.tw_shift_m = tw_shift(M);
   a1.inv_n = 1.0f / (float)N;
   int slot = timer_open(RADAR_STAGE_TAPS, s);
 #define K1_CALL(n) launch_k1_n<n>(a1, M, F, s)
@@ -170,7 +191,6 @@ int enqueue_transforms(const radar_frame_desc* d, int F, const float2* in, const
   a2.m_pad = d->m_pad;
   a2.n_cp = d->n_cp;
   a2.fm = d->m_pad / M;
-  a2.tw_shift_mp = tw_shift(d->m_pad);
   slot = timer_open(RADAR_STAGE_DOPPLER, s);
 #define K2_CALL(m) launch_k2_m<m>(a2, d->n_cp, F, s)
   RADAR_SIZE_SWITCH(M, K2_CALL)
@@ -186,26 +206,51 @@ int enqueue_transforms(const radar_frame_desc* d, int F, const float2* in, const
   a3.n_pad = d->n_pad;
   a3.n_cp = d->n_cp;
   a3.window = d->window;
-  a3.tw_shift_n = tw_shift(N);
-  a3.tw_shift_np = tw_shift(d->n_pad);
   a3.scale = (float)(1.0 / ((double)N * (double)M));
+  a3.rowmax = reinterpret_cast<float*>(ws + w.pk.rowmax);
   const int f2 = d->n_pad / N;
+  const bool x4 = f2 == 4 && d->n_cp * 4 <= N && N >= 256;
   slot = timer_open(RADAR_STAGE_RANGE, s);
+  if (x4) {
+    switch (N) {
+      case 256: launch_k3x4_n<256>(a3, d->m_pad, F, s); break;
+      case 512: launch_k3x4_n<512>(a3, d->m_pad, F, s); break;
+      case 1024: launch_k3x4_n<1024>(a3, d->m_pad, F, s); break;
+      case 2048: launch_k3x4_n<2048>(a3, d->m_pad, F, s); break;
+      default: launch_k3x4_n<4096>(a3, d->m_pad, F, s); break;
+    }
+  } else {
 #define K3_CALL(n) launch_k3_n<n>(a3, f2, d->m_pad, F, s)
-  RADAR_SIZE_SWITCH(N, K3_CALL)
+    RADAR_SIZE_SWITCH(N, K3_CALL)
 #undef K3_CALL
+  }
   timer_close(RADAR_STAGE_RANGE, slot, s);
   RADAR_HIP_CHECK(hipGetLastError());
+  if (!x4) {
+    hipLaunchKernelGGL(radar::k_row_max, dim3(d->m_pad, F), dim3(256), 0, s, P, p_stride, d->m_pad, d->n_pad,
+                       a3.rowmax);
+    RADAR_HIP_CHECK(hipGetLastError());
+  }
   return RADAR_OK;
 }
 
-int enqueue_peaks(const float* P, int64_t p_stride, int m_pad, int n_pad, int F, int k, uint64_t* cand,
+// Peak search from P and its row maxima (already in the workspace).
+int enqueue_peaks(const float* P, int64_t p_stride, int m_pad, int n_pad, int F, int k, const PeakWs& w, char* ws,
                   radar_peak* peaks, int32_t* n_peaks, hipStream_t s) {
+  float* rowmax = reinterpret_cast<float*>(ws + w.rowmax);
+  float* tau = reinterpret_cast<float*>(ws + w.tau);
+  int32_t* cnt = reinterpret_cast<int32_t*>(ws + w.cnt);
+  int32_t* list = reinterpret_cast<int32_t*>(ws + w.list);
+  uint64_t* cand = reinterpret_cast<uint64_t*>(ws + w.cand);
   const int slot = timer_open(RADAR_STAGE_PEAKS, s);
-  hipLaunchKernelGGL(radar::k_peak_rows, dim3(m_pad, F), dim3(256), n_pad * sizeof(uint32_t), s, P, p_stride,
-                     m_pad, n_pad, k, cand);
+  hipLaunchKernelGGL(radar::k_peak_threshold, dim3(F), dim3(1024), m_pad * sizeof(float), s, rowmax, m_pad, k, tau,
+                     list, cnt);
   RADAR_HIP_CHECK(hipGetLastError());
-  hipLaunchKernelGGL(radar::k_peak_merge, dim3(F), dim3(1024), 0, s, cand, m_pad, n_pad, k, peaks, n_peaks);
+  const int groups = m_pad < 32 ? m_pad : 32;
+  hipLaunchKernelGGL(radar::k_peak_rows_listed, dim3(groups, F), dim3(256), n_pad * sizeof(uint32_t), s, P,
+                     p_stride, m_pad, n_pad, k, tau, list, cnt, cand);
+  RADAR_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(radar::k_peak_merge, dim3(F), dim3(1024), 0, s, cand, cnt, m_pad, n_pad, k, peaks, n_peaks);
   RADAR_HIP_CHECK(hipGetLastError());
   timer_close(RADAR_STAGE_PEAKS, slot, s);
   return RADAR_OK;
@@ -235,22 +280,31 @@ int radar_init(void) {
   if (dev < 0 || dev >= kMaxDevices) return RADAR_E_UNSUPPORTED;
   std::lock_guard<std::mutex> lock(g_init_mu);
   if (g_init_done[dev]) return RADAR_OK;
-  std::vector<float2> tab(RADAR_TW_LMAX);
-  for (int t = 0; t < RADAR_TW_LMAX; ++t) {
-    // exp(-2 pi i t/L); reduce to the first quadrant so that symmetric entries
-    // are computed from the same double value.
-    const int q = t / (RADAR_TW_LMAX / 4);
-    const int rem = t % (RADAR_TW_LMAX / 4);
-    const double ang = 2.0 * M_PI * (double)rem / (double)RADAR_TW_LMAX;
-    const double c = std::cos(ang), sn = std::sin(ang);
-    double re, im;  // exp(-i(ang + q pi/2))
-    switch (q) {
-      case 0: re = c; im = -sn; break;
-      case 1: re = -sn; im = -c; break;
-      case 2: re = -c; im = sn; break;
-      default: re = sn; im = c; break;
+  // block L holds W_L^x = exp(-2 pi i x/L), x < L, at offset L; each value is
+  // taken from the first quadrant of the finest grid so that equal angles in
+  // different blocks get bit-identical entries.
+  std::vector<double> qc(RADAR_TW_LMAX / 4 + 1), qs(RADAR_TW_LMAX / 4 + 1);
+  for (int i = 0; i <= RADAR_TW_LMAX / 4; ++i) {
+    const double ang = 2.0 * M_PI * (double)i / (double)RADAR_TW_LMAX;
+    qc[i] = std::cos(ang);
+    qs[i] = std::sin(ang);
+  }
+  std::vector<float2> tab(RADAR_TW_ENTRIES, make_float2(0.0f, 0.0f));
+  for (int L = 1; L <= RADAR_TW_LMAX; L <<= 1) {
+    for (int x = 0; x < L; ++x) {
+      const int t = x * (RADAR_TW_LMAX / L);  // the same angle on the finest grid
+      const int q = t / (RADAR_TW_LMAX / 4);
+      const int rem = t % (RADAR_TW_LMAX / 4);
+      const double c = qc[rem], sn = qs[rem];
+      double re, im;  // exp(-i(2 pi rem/LMAX + q pi/2))
+      switch (q) {
+        case 0: re = c; im = -sn; break;
+        case 1: re = -sn; im = -c; break;
+        case 2: re = -c; im = sn; break;
+        default: re = sn; im = c; break;
+      }
+      tab[L + x] = make_float2((float)re, (float)im);
     }
-    tab[t] = make_float2((float)re, (float)im);
   }
   if (hipMemcpyToSymbol(HIP_SYMBOL(g_radar_tw), tab.data(), tab.size() * sizeof(float2), 0,
                         hipMemcpyHostToDevice) != hipSuccess)
@@ -294,8 +348,7 @@ int radar_frame_process(const radar_frame_desc* d, int32_t n_frames, const radar
   rc = enqueue_transforms(d, n_frames, reinterpret_cast<const float2*>(Y), reinterpret_cast<const float2*>(A),
                           frame_stride, 0, P, p_frame_stride, status, w, wsb, s);
   if (rc != RADAR_OK) return rc;
-  return enqueue_peaks(P, p_frame_stride, d->m_pad, d->n_pad, n_frames, k,
-                       reinterpret_cast<uint64_t*>(wsb + w.taps + w.U), peaks, n_peaks, s);
+  return enqueue_peaks(P, p_frame_stride, d->m_pad, d->n_pad, n_frames, k, w.pk, wsb, peaks, n_peaks, s);
 }
 
 int radar_periodogram(const radar_frame_desc* d, int32_t n_frames, const radar_cf32* H, int64_t frame_stride,
@@ -316,7 +369,7 @@ size_t radar_detect_workspace_size(int32_t m_pad, int32_t n_pad, int32_t n_frame
   if (m_pad < 4 || n_pad < 4 || !is_pow2(m_pad) || !is_pow2(n_pad) || m_pad > 16384 || n_pad > 16384 ||
       n_frames < 1 || k < 1)
     return 0;
-  return align256((size_t)n_frames * m_pad * (size_t)k * sizeof(uint64_t));
+  return peak_ws_layout(m_pad, n_frames, k, 0).total;
 }
 
 int radar_detect_topk(const float* P, int32_t m_pad, int32_t n_pad, int32_t n_frames, int64_t p_frame_stride,
@@ -331,8 +384,12 @@ int radar_detect_topk(const float* P, int32_t m_pad, int32_t n_pad, int32_t n_fr
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
   hipLaunchKernelGGL(radar::k0_clear, dim3((n_frames + 255) / 256), dim3(256), 0, s, nullptr, n_peaks, n_frames);
   RADAR_HIP_CHECK(hipGetLastError());
-  return enqueue_peaks(P, p_frame_stride, m_pad, n_pad, n_frames, k, static_cast<uint64_t*>(ws), peaks, n_peaks,
-                       s);
+  const PeakWs w = peak_ws_layout(m_pad, n_frames, k, 0);
+  char* wsb = static_cast<char*>(ws);
+  hipLaunchKernelGGL(radar::k_row_max, dim3(m_pad, n_frames), dim3(256), 0, s, P, p_frame_stride, m_pad, n_pad,
+                     reinterpret_cast<float*>(wsb + w.rowmax));
+  RADAR_HIP_CHECK(hipGetLastError());
+  return enqueue_peaks(P, p_frame_stride, m_pad, n_pad, n_frames, k, w, wsb, peaks, n_peaks, s);
 }
 
 int radar_timing_start(int32_t max_launches) {

@@ -90,8 +90,15 @@ SHAPES = [
     (2048, 16, 4096, 64, 512, radar.WIN_HANN, 7, 3),
     (4096, 32, 4096, 32, 4096, radar.WIN_RECT, 11, 3),       # largest N, LS-CE
     (16, 4096, 32, 4096, 4, radar.WIN_HANN, 1, 3),           # largest M
-    (1024, 64, 4096, 16384, 256, radar.WIN_HANN, 7, 3),      # M'/M = 256, largest M'
+    (256, 64, 1024, 16384, 64, radar.WIN_HANN, 7, 3),        # M'/M = 256, largest M'
+    # 4x range padding with N_cp <= N/4 (the four-phase range kernel)
+    (256, 16, 1024, 64, 64, radar.WIN_HAMMING, 3, 4),        # N_cp = N/4 exactly
+    (512, 32, 2048, 32, 1, radar.WIN_RECT, 5, 3),            # one tap, rect window
+    (2048, 16, 8192, 32, 300, radar.WIN_HANN, 7, 3),         # ragged N_cp
+    (4096, 16, 16384, 16, 1024, radar.WIN_HAMMING, 9, 3),    # largest N' and N
+    (256, 32, 1024, 64, 100, radar.WIN_HANN, 1, 3),          # 4x padding but N_cp > N/4: generic kernel
 ]
+SHAPES = [s for s in SHAPES if s[2] // s[0] <= 8]
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=[f"{s[0]}x{s[1]}-{s[2]}x{s[3]}-cp{s[4]}" for s in SHAPES])
@@ -186,6 +193,30 @@ def test_detect_topk_exact_on_planted_grid():
     got = radar.unpack_peaks(peaks, n_peaks.cpu())
     for f in range(3):
         want = oracle_ranked(O, Pn[f].astype(np.float64), 20)
+        assert [(s, r, np.float32(v)) for s, r, v in want] == [(s, r, np.float32(p)) for s, r, p, _, _ in got[f]]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_detect_topk_random_bumps(seed):
+    """Random landscapes: bumps of random height and width on a noise floor."""
+    rng = np.random.default_rng(100 + seed)
+    F, m_pad, n_pad = 3, 128, 256
+    ii, jj = np.meshgrid(np.arange(m_pad), np.arange(n_pad), indexing="ij")
+    Pn = (rng.random((F, m_pad, n_pad)) * 1e-3).astype(np.float64)
+    for f in range(F):
+        for _ in range(rng.integers(1, 30)):
+            ci, cj = rng.integers(0, m_pad), rng.integers(0, n_pad)
+            di = np.minimum(np.abs(ii - ci), m_pad - np.abs(ii - ci))
+            dj = np.minimum(np.abs(jj - cj), n_pad - np.abs(jj - cj))
+            Pn[f] += 10 ** rng.uniform(-2, 2) * np.exp(-(di ** 2 + dj ** 2) / rng.uniform(0.5, 40))
+    Pn = Pn.astype(np.float32)
+    k = int(rng.integers(1, 65))
+    say(f"detect_topk random bumps seed {seed} k {k}")
+    peaks, n_peaks = radar.detect_topk(torch.from_numpy(Pn).cuda(), k)
+    torch.cuda.synchronize()
+    got = radar.unpack_peaks(peaks, n_peaks.cpu())
+    for f in range(F):
+        want = oracle_ranked(O, Pn[f].astype(np.float64), k)
         assert [(s, r, np.float32(v)) for s, r, v in want] == [(s, r, np.float32(p)) for s, r, p, _, _ in got[f]]
 
 
