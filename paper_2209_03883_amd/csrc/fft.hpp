@@ -107,64 +107,140 @@ struct LdsSize {
   static constexpr int value = L + L / 16;
 };
 
-// One Stockham stage.  `active` = false skips the arithmetic and LDS traffic
-// but keeps the barriers, so a team can sit a transform out while the rest of
-// the work-group runs it.
-template <int L, int E, int R, int NS, bool INV>
-__device__ __forceinline__ void stockham_stage(float2 (&v)[E], float2* lds, int t, bool active) {
-  constexpr int T = L / E;
-  constexpr int NB = E / R;                 // butterflies per thread
-  constexpr bool LAST = (NS * R == L);
-  if (active) {
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      float2 x[R];
-#pragma unroll
-      for (int m = 0; m < R; ++m) x[m] = v[b + m * NB];
-      const int j = t + T * b;
-      const int k = j & (NS - 1);
-      if constexpr (NS > 1) {
-#pragma unroll
-        for (int m = 1; m < R; ++m) {
-          const float2 w = twiddle(NS * R, k * m);
-          x[m] = INV ? cmulc(x[m], w) : cmul(x[m], w);
-        }
-      }
-      Dft<R, INV>::run(x);
-      if constexpr (LAST) {
-#pragma unroll
-        for (int m = 0; m < R; ++m) v[b + m * NB] = x[m];
-      } else {
-        const int base = (j - k) * R + k;
-#pragma unroll
-        for (int m = 0; m < R; ++m) lds[lds_pad(base + m * NS)] = x[m];
-      }
-    }
+// Synchronisation of one team around an LDS exchange.  A team inside one
+// wavefront only needs its LDS writes to land before its reads: the LDS
+// serves a wave's instructions in order, so a compiler-level fence plus a wait
+// for the wave's own LDS operations suffices and leaves global loads in
+// flight.  Wider teams use the work-group barrier.
+template <int T>
+__device__ __forceinline__ void team_sync() {
+  if constexpr (T <= 64) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
   }
-  if constexpr (!LAST) {
-    __syncthreads();
-    if (active) {
+}
+
+// Where a stage's twiddles come from: the global stage section, or a copy of
+// the stages a kernel needs in LDS (Layout::off<NS, R>() gives each block's
+// offset there, same [m][k] layout).
+struct TwGlobal {
+  template <int NS, int R>
+  __device__ __forceinline__ float2 stage(int k, int m) const {
+    return stage_twiddle<NS, R>(k, m);
+  }
+};
+
+template <class Layout>
+struct TwLds {
+  const float2* base;
+  template <int NS, int R>
+  __device__ __forceinline__ float2 stage(int k, int m) const {
+    return base[Layout::template off<NS, R>() + m * NS + k];
+  }
+};
+
+// Shape of the Stockham stage that starts at span NS.
+template <int L, int E, int NS>
+struct StagePlan {
+  static constexpr int T = L / E;
+  static constexpr int REM = L / NS;
+  static constexpr int R = REM >= E ? E : REM;
+  static constexpr int NB = E / R;                       // butterflies per thread
+  static constexpr int NTW = NS > 1 ? NB * (R - 1) : 0;  // twiddles per thread
+  static constexpr bool LAST = NS * R == L;
+};
+
+template <int L, int E, int NS>
+struct StageTw {
+  float2 w[StagePlan<L, E, NS>::NTW > 0 ? StagePlan<L, E, NS>::NTW : 1];
+};
+
+// Loads the twiddles of the stage starting at span NS (from the stage section,
+// contiguous across the lanes of a wave).
+template <int L, int E, int NS, class TS>
+__device__ __forceinline__ void load_stage_tw(StageTw<L, E, NS>& tw, int t, bool active, const TS& ts) {
+  using P = StagePlan<L, E, NS>;
+  if constexpr (P::NTW > 0) {
+    if (!active) return;
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = lds[lds_pad(t + T * e)];
+    for (int b = 0; b < P::NB; ++b) {
+      const int k = (t + P::T * b) & (NS - 1);
+#pragma unroll
+      for (int m = 1; m < P::R; ++m) tw.w[b * (P::R - 1) + m - 1] = ts.template stage<NS, P::R>(k, m);
     }
-    __syncthreads();
   }
 }
 
 // Stages from span NS onward: radix E while at least E remains, then the
-// remainder as the last stage.
-template <int L, int E, int NS, bool INV>
-__device__ __forceinline__ void fft_stages(float2 (&v)[E], float2* lds, int t, bool active) {
-  constexpr int REM = L / NS;
-  if constexpr (REM > 1) {
-    constexpr int R = REM >= E ? E : REM;
-    stockham_stage<L, E, R, NS, INV>(v, lds, t, active);
-    fft_stages<L, E, NS * R, INV>(v, lds, t, active);
+// remainder as the last stage.  `tw` holds this stage's twiddles; the next
+// stage's are fetched before the LDS exchange so their latency overlaps it.
+// `active` = false skips arithmetic and LDS traffic but keeps the barriers.
+template <int L, int E, int NS, bool INV, class TS>
+__device__ __forceinline__ void fft_stages_tw(float2 (&v)[E], float2* lds, int t, bool active,
+                                              const StageTw<L, E, NS>& tw, const TS& ts) {
+  using P = StagePlan<L, E, NS>;
+  constexpr int T = P::T, R = P::R, NB = P::NB;
+  if constexpr (L / NS > 1) {
+    if (active) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        float2 x[R];
+#pragma unroll
+        for (int m = 0; m < R; ++m) x[m] = v[b + m * NB];
+        const int j = t + T * b;
+        const int k = j & (NS - 1);
+        if constexpr (NS > 1) {
+#pragma unroll
+          for (int m = 1; m < R; ++m) {
+            const float2 w = tw.w[b * (R - 1) + m - 1];
+            x[m] = INV ? cmulc(x[m], w) : cmul(x[m], w);
+          }
+        }
+        Dft<R, INV>::run(x);
+        if constexpr (P::LAST) {
+#pragma unroll
+          for (int m = 0; m < R; ++m) v[b + m * NB] = x[m];
+        } else {
+          const int base = (j - k) * R + k;
+#pragma unroll
+          for (int m = 0; m < R; ++m) lds[lds_pad(base + m * NS)] = x[m];
+        }
+      }
+    }
+    if constexpr (!P::LAST) {
+      StageTw<L, E, NS * R> next;
+      load_stage_tw<L, E, NS * R>(next, t, active, ts);
+      team_sync<T>();
+      if (active) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = lds[lds_pad(t + T * e)];
+      }
+      if constexpr (T > 64) {
+        __syncthreads();
+      } else {
+        // keep the next stage's LDS writes after these reads (the LDS then
+        // serves them in order)
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      }
+      fft_stages_tw<L, E, NS * R, INV>(v, lds, t, active, next, ts);
+    }
   }
 }
 
+template <int L, int E, int NS, bool INV, class TS = TwGlobal>
+__device__ __forceinline__ void fft_stages(float2 (&v)[E], float2* lds, int t, bool active, const TS& ts = TS{}) {
+  StageTw<L, E, NS> tw;
+  load_stage_tw<L, E, NS>(tw, t, active, ts);
+  fft_stages_tw<L, E, NS, INV>(v, lds, t, active, tw, ts);
+}
+
 // Full L-point transform of the team's data (cyclic layout in and out).
-// Every thread of the work-group must call it (it contains barriers).
+// Every thread of the work-group must call it when teams span several waves
+// (it then contains work-group barriers).
 template <int L, int E, bool INV>
 __device__ __forceinline__ void team_fft(float2 (&v)[E], float2* lds, int t, bool active = true) {
   static_assert(L >= E && (L & (L - 1)) == 0, "FFT length");

@@ -51,29 +51,31 @@ __global__ void __launch_bounds__(kBlock) k1_taps(K1Args a) {
   uint32_t st = 0;
   float2 v[16];
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int k = t + T * e;
-    float2 h = y[k];
-    if (!a.from_h) {
+  for (int e = 0; e < 16; ++e) v[e] = y[t + T * e];
+  if (!a.from_h) {
+    float2 s[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) s[e] = x[t + T * e];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int k = t + T * e;
+      float2 h = v[e];
       if (a.zc_on) {
         // z_k = exp(+i pi m_k / N) with m_k = root*(k^2 + 2 q k) mod 2N (Eq. 23, even N);
         // 2N divides 2^32, so unsigned wrap-around keeps m_k exact.
         const uint32_t uk = (uint32_t)k;
         const uint32_t m = (a.zc_root * (uk * uk + 2u * a.zc_shift * uk)) & (uint32_t)(2 * N - 1);
-        h = cmul(h, twiddle(2 * N, (int)m));  // y * conj(z_k)
+        h = cmul(h, twiddle_split(2 * N, (int)m));  // y * conj(z_k)
       }
-      const float2 s = x[k];
-      const float den = cabs2(s);
-      if (den == 0.0f) {
-        st |= 1u;
-        h = make_float2(0.0f, 0.0f);
-      } else {
-        h = cscale(cmulc(h, s), 1.0f / den);        // y conj(z) conj(a) / |a|^2
-      }
+      const float den = cabs2(s[e]);
+      st |= den == 0.0f ? 1u : 0u;
+      const float inv = den == 0.0f ? 0.0f : __builtin_amdgcn_rcpf(den);
+      v[e] = cscale(cmulc(h, s[e]), inv);            // y conj(z) conj(a) / |a|^2
     }
-    if (!__builtin_isfinite(h.x) || !__builtin_isfinite(h.y)) st |= 2u;
-    v[e] = h;
   }
+#pragma unroll
+  for (int e = 0; e < 16; ++e)
+    st |= (__builtin_isfinite(v[e].x) && __builtin_isfinite(v[e].y)) ? 0u : 2u;
   team_fft<N, 16, true>(v, lds, t);
   if (!active) return;
   const float scale = window_value(a.window, l, a.M) * a.inv_n;
@@ -91,6 +93,7 @@ struct K2Args {
   float2* U;              // [F][M'][n_cp], row = fftshifted Doppler index
   int M, m_pad, n_cp;
   int fm;                 // M'/M
+  int ph_off;             // phase-section offset of W_{M'}^{l b} (layout [b][l]), or -1: power section
 };
 
 // K2: one team per DFT-CE tap; M'-point Doppler DFT with M non-zero inputs,
@@ -118,7 +121,8 @@ __global__ void __launch_bounds__(kBlock) k2_doppler(K2Args a) {
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int l = t + T * e;
-      v[e] = b == 0 ? x[e] : cmul(x[e], twiddle(a.m_pad, l * b));
+      const float2 w = a.ph_off >= 0 ? g_radar_tw[(unsigned)(a.ph_off + b * M + l)] : twiddle(a.m_pad, l * b);
+      v[e] = b == 0 ? x[e] : cmul(x[e], w);
     }
     team_fft<M, 16, false>(v, lds, t);
     if (active) {
@@ -128,6 +132,68 @@ __global__ void __launch_bounds__(kBlock) k2_doppler(K2Args a) {
         const int row = (su + half) & (a.m_pad - 1);    // fftshift
         out[(int64_t)row * a.n_cp] = v[e];
       }
+    }
+  }
+}
+
+
+// K2, tiled: one team per (tap, Doppler sub-transform b); a work-group covers
+// TW adjacent taps for one b.  The taps come in as rows of TW contiguous
+// elements through an LDS tile, and the results leave the same way, so every
+// global access is a contiguous row segment.
+//   U[M'/M * s1 + b][n] = FFT_M(t_l[n] W_{M'}^{l b})[s1]   (fftshifted row index)
+template <int M, int TW>
+struct K2Tile {
+  static constexpr int T = M / 16;
+  static constexpr int BLOCK = TW * T;
+  static constexpr int EXCH = LdsSize<M>::value;
+  static constexpr int LD = TW + 1;  // padded tile row (limits bank conflicts)
+  static constexpr int SH = TW * EXCH > M * LD ? TW * EXCH : M * LD;
+};
+
+template <int M, int TW>
+__global__ void __launch_bounds__((K2Tile<M, TW>::BLOCK)) k2_doppler_tiled(K2Args a) {
+  using C = K2Tile<M, TW>;
+  constexpr int T = C::T, BLOCK = C::BLOCK, LD = C::LD;
+  __shared__ float2 sh[C::SH];
+  const int team = threadIdx.x / T;
+  const int t = threadIdx.x - team * T;
+  const int b = blockIdx.y;
+  const int f = blockIdx.z;
+  const int n0 = blockIdx.x * TW;
+  const int ntap = min(TW, a.n_cp - n0);
+
+  // tile of taps [l][n0 .. n0+TW)
+  const float2* in = a.taps + (int64_t)f * M * a.n_cp + n0;
+  for (int i = threadIdx.x; i < M * TW; i += BLOCK) {
+    const int l = i / TW, c = i - l * TW;
+    sh[l * LD + c] = c < ntap ? in[(int64_t)l * a.n_cp + c] : make_float2(0.0f, 0.0f);
+  }
+  __syncthreads();
+  float2 v[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) v[e] = sh[(t + T * e) * LD + team];
+  if (b != 0) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int l = t + T * e;
+      const float2 w = a.ph_off >= 0 ? g_radar_tw[(unsigned)(a.ph_off + b * M + l)] : twiddle(a.m_pad, l * b);
+      v[e] = cmul(v[e], w);
+    }
+  }
+  __syncthreads();  // the tile is reused as exchange space
+  team_fft<M, 16, false>(v, sh + team * C::EXCH, t);
+  __syncthreads();  // every team is done with its exchange region
+#pragma unroll
+  for (int e = 0; e < 16; ++e) sh[(t + T * e) * LD + team] = v[e];
+  __syncthreads();
+  float2* out = a.U + (int64_t)f * a.m_pad * a.n_cp + n0;
+  const int half = a.m_pad >> 1;
+  for (int i = threadIdx.x; i < M * TW; i += BLOCK) {
+    const int s1 = i / TW, c = i - s1 * TW;
+    if (c < ntap) {
+      const int row = (a.fm * s1 + b + half) & (a.m_pad - 1);
+      out[(int64_t)row * a.n_cp + c] = sh[s1 * LD + c];
     }
   }
 }
@@ -187,7 +253,7 @@ __global__ void __launch_bounds__(kBlock) k3_range_power(K3Args a) {
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int k = t + T * e;
-      g[e] = b2 == 0 ? X[e] : cmulc(X[e], twiddle(a.n_pad, k * b2));  // X e^{+2 pi i k b2/N'}
+      g[e] = b2 == 0 ? X[e] : cmulc(X[e], phase_twiddle<N, F2>(b2, k));  // X e^{+2 pi i k b2/N'}
     }
     team_fft<N, 16, true>(g, lds, t);
 #pragma unroll
@@ -256,7 +322,7 @@ __global__ void __launch_bounds__(K3x4<N>::BLOCK) k3_range_power_x4(K3Args a) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int n = t + T * e;
-      x[e] = team == 0 ? ub[n] : cmul(ub[n], twiddle(N, n * team));
+      x[e] = team == 0 ? ub[n] : cmul(ub[n], phase_twiddle<Q, 4>(team, n));
     }
     team_fft<Q, 4, false>(x, main + team * C::EXCH, t);
     __syncthreads();  // exchange regions are reused for X below
@@ -275,7 +341,7 @@ __global__ void __launch_bounds__(K3x4<N>::BLOCK) k3_range_power_x4(K3Args a) {
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int k = t + T * e;
-      gv[e] = cmulc(main[k], twiddle(4 * N, k * team));  // X_k e^{+2 pi i k b/(4N)}
+      gv[e] = cmulc(main[k], phase_twiddle<N, 4>(team, k));  // X_k e^{+2 pi i k b/(4N)}
     }
   }
   __syncthreads();  // X consumed before the exchange regions overwrite it
@@ -326,6 +392,290 @@ __global__ void __launch_bounds__(K3x4<N>::BLOCK) k3_range_power_x4(K3Args a) {
     }
   } else {
     if (gi == 0) a.rowmax[(int64_t)f * a.m_pad + row] = mx;
+  }
+}
+
+// ------------------------------------------------------------------------
+// K3 for 4x range padding and N_cp <= N/4, N <= 1024: one wavefront per
+// Doppler row (four rows per wave at N = 256), all four phases in sequence.
+//   forward  DFT_N of u (N_cp <= N/4 taps): the first radix-4 Stockham stage
+//            of a zero-padded input only copies, y[i] = u[i >> 2], so the
+//            transform starts at span 4 straight from the taps.
+//   phases   b = 1, 2, 3: IFFT_N(w_k X_k e^{+2 pi i k b/(4N)}) in turn;
+//            b = 0: the 3-tap filter N (a0 u[r1] - a1/2 (u[r1-1] + u[r1+1])).
+// The four |G|^2 values of each r1 stay in registers and leave as one float4.
+// ------------------------------------------------------------------------
+template <int N>
+struct K3w {
+  static constexpr int T = N / 16;               // threads per row
+  static constexpr int ROWS = 64 / T;            // rows per wave
+  static constexpr int EXCH = LdsSize<N>::value;
+  static constexpr int UBUF = N / 4 + 3;         // u[-1 .. N/4+1]
+};
+
+template <int N>
+__global__ void __launch_bounds__(64) k3_range_power_x4w(K3Args a) {
+  using C = K3w<N>;
+  constexpr int T = C::T;
+  constexpr int Q = N / 4;
+  static_assert(T <= 64, "one wave per row at most");
+  __shared__ float2 s_x[C::ROWS][C::EXCH];
+  __shared__ float2 s_u[C::ROWS][C::UBUF];
+  const int g = threadIdx.x / T;
+  const int t = threadIdx.x - g * T;
+  const int f = blockIdx.y;
+  const int row = blockIdx.x * C::ROWS + g;
+  float2* lds = s_x[g];
+  float2* ub = s_u[g] + 1;
+
+  const float2* in = a.U + ((int64_t)f * a.m_pad + row) * a.n_cp;
+  {
+    float2 uv[Q / T];
+#pragma unroll
+    for (int e = 0; e < Q / T; ++e) {
+      const int n = t + T * e;
+      uv[e] = in[n < a.n_cp ? n : 0];  // in-bounds load, zeroed below
+    }
+#pragma unroll
+    for (int e = 0; e < Q / T; ++e) {
+      const int n = t + T * e;
+      ub[n] = n < a.n_cp ? uv[e] : make_float2(0.0f, 0.0f);
+    }
+  }
+  if (t < 3) ub[t == 0 ? -1 : Q + t - 1] = make_float2(0.0f, 0.0f);
+  team_sync<64>();
+
+  // forward DFT_N, then the range window w_k = a0 - a1 cos(2 pi k/N)
+  const float2 wc = window_coeffs(a.window);
+  float cw[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) cw[e] = twiddle(N, t + T * e).x;
+  float2 X[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) X[e] = ub[(t + T * e) >> 2];
+  fft_stages<N, 16, 4, false>(X, lds, t, true);
+#pragma unroll
+  for (int e = 0; e < 16; ++e) X[e] = cscale(X[e], wc.x - wc.y * cw[e]);
+
+  // Phases 2 and 3 first (stored as float2 pairs), then phase 1 and the
+  // filtered phase 0 (the other pair).  Each phase's twiddle loads are tied to
+  // the previous phase's result so the compiler cannot hoist them all to the
+  // top and run out of registers.
+  float* dst = a.P + (int64_t)f * a.p_stride + (int64_t)row * (4 * N);
+  float mx = 0.0f;
+  float dep = 0.0f;
+  float p_first[16];
+#pragma unroll
+  for (int b = 2; b <= 4; ++b) {
+    const int phase = b == 4 ? 1 : b;
+    float2 gv[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      int idx = t + T * e;
+      asm volatile("" : "+v"(idx) : "v"(dep));
+      gv[e] = cmulc(X[e], phase_twiddle<N, 4>(phase, idx));
+    }
+    fft_stages<N, 16, 1, true>(gv, lds, t, true);
+    if (phase == 2) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) p_first[e] = cabs2(gv[e]) * a.scale;
+      dep = p_first[0];
+    } else if (phase == 3) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const float p3 = cabs2(gv[e]) * a.scale;
+        reinterpret_cast<float2*>(dst)[2 * (t + T * e) + 1] = make_float2(p_first[e], p3);
+        mx = fmaxf(mx, fmaxf(p_first[e], p3));
+      }
+      dep = mx;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) p_first[e] = cabs2(gv[e]) * a.scale;
+    }
+  }
+
+  const float c0 = (float)N * wc.x, c1 = -0.5f * (float)N * wc.y;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int r1 = t + T * e;
+    float2 gz = make_float2(0.0f, 0.0f);
+    if (r1 <= Q) {
+      gz = cadd(cscale(ub[r1], c0), cscale(cadd(ub[r1 - 1], ub[r1 + 1]), c1));
+    } else if (r1 == N - 1) {
+      gz = cscale(ub[0], c1);  // u[N] = u[0]
+    }
+    const float p0 = cabs2(gz) * a.scale;
+    reinterpret_cast<float2*>(dst)[2 * r1] = make_float2(p0, p_first[e]);
+    mx = fmaxf(mx, fmaxf(p0, p_first[e]));
+  }
+#pragma unroll
+  for (int m = T / 2; m > 0; m >>= 1) mx = fmaxf(mx, __shfl_xor(mx, m));
+  if (t == 0) a.rowmax[(int64_t)f * a.m_pad + row] = mx;
+}
+
+// ------------------------------------------------------------------------
+// K3, persistent form of the one-wave-per-row kernel above (N' = 4N,
+// N_cp <= N/4, N <= 1024).  Every twiddle a row needs is the same for all
+// rows, so each work-group copies the stage blocks of its two FFT plans, the
+// phase twiddles W_{4N}^{k b} (b = 1..3) and the window cosines into LDS once,
+// and its waves then loop over rows independently.  Twiddle reads become LDS
+// reads instead of vector-memory instructions.
+// ------------------------------------------------------------------------
+template <int L, int E, int NS0>
+struct PlanTable {
+  static constexpr int r_at(int ns) { return L / ns >= E ? E : L / ns; }
+  // entries of the twiddle blocks of the stages from NS0 up to (not incl.) NS
+  static constexpr int off(int NS) {
+    int tot = 0;
+    for (int ns = NS0; ns < NS && ns < L; ns *= r_at(ns))
+      if (ns > 1) tot += ns * r_at(ns);
+    return tot;
+  }
+  static constexpr int size() { return off(L); }
+};
+
+template <int N, int BASE, int NS0>
+struct PlanLayout {
+  template <int NS, int R>
+  static constexpr int off() {
+    return BASE + PlanTable<N, 16, NS0>::off(NS);
+  }
+};
+
+template <int L, int E, int NS0>
+__device__ __forceinline__ void copy_plan_twiddles(float2* dst, int tid, int nthreads) {
+  using PT = PlanTable<L, E, NS0>;
+  int pos = 0;
+  for (int ns = NS0; ns < L; ns *= PT::r_at(ns)) {
+    const int r = PT::r_at(ns);
+    if (ns > 1) {
+      const int src = stage_offset(ilog2c(ns), ilog2c(r));
+      for (int i = tid; i < ns * r; i += nthreads) dst[pos + i] = g_radar_tw[(unsigned)(src + i)];
+      pos += ns * r;
+    }
+  }
+}
+
+template <int N>
+struct K3p {
+  static constexpr int T = N / 16;
+  static constexpr int ROWS = 64 / T;                   // rows per wave per pass
+  static constexpr int WAVES = 8;
+  static constexpr int BLOCK = 64 * WAVES;
+  static constexpr int FWD = 0;                         // forward plan (from span 4)
+  static constexpr int INV = PlanTable<N, 16, 4>::size();  // inverse plan (from span 1)
+  static constexpr int PH = INV + PlanTable<N, 16, 1>::size();  // W_{4N}^{k b}, b = 1..3
+  static constexpr int WIN = PH + 3 * N;                // N window cosines (as floats)
+  static constexpr int TAB = WIN + N / 2;
+  static constexpr int EXCH = LdsSize<N>::value;
+  static constexpr int UBUF = N / 4 + 3;
+  using Fwd = PlanLayout<N, FWD, 4>;
+  using Inv = PlanLayout<N, INV, 1>;
+};
+
+template <int N>
+__global__ void __launch_bounds__(K3p<N>::BLOCK) k3_range_power_x4p(K3Args a, int total_groups) {
+  using C = K3p<N>;
+  constexpr int T = C::T;
+  constexpr int Q = N / 4;
+  __shared__ float2 tab[C::TAB];
+  __shared__ float2 xch[C::WAVES][C::ROWS][C::EXCH];
+  __shared__ float2 ubuf[C::WAVES][C::ROWS][C::UBUF];
+
+  copy_plan_twiddles<N, 16, 4>(tab + C::FWD, threadIdx.x, C::BLOCK);
+  copy_plan_twiddles<N, 16, 1>(tab + C::INV, threadIdx.x, C::BLOCK);
+  {
+    constexpr int poff = phase_offset(ilog2c(N), 2);
+    for (int i = threadIdx.x; i < 3 * N; i += C::BLOCK) tab[C::PH + i] = g_radar_tw[(unsigned)(poff + N + i)];
+    float* cw = reinterpret_cast<float*>(tab + C::WIN);
+    for (int i = threadIdx.x; i < N; i += C::BLOCK) cw[i] = g_radar_tw[(unsigned)(N + i)].x;
+  }
+  __syncthreads();
+
+  const TwLds<typename C::Fwd> tw_fwd{tab};
+  const TwLds<typename C::Inv> tw_inv{tab};
+  const float* cwin = reinterpret_cast<const float*>(tab + C::WIN);
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int g = lane / T;
+  const int t = lane - g * T;
+  float2* lds = xch[wave][g];
+  float2* ub = ubuf[wave][g] + 1;                        // ub[i] = u[i], i in [-1, N/4+1]
+  const float2 wc = window_coeffs(a.window);
+  const float c0 = (float)N * wc.x, c1 = -0.5f * (float)N * wc.y;
+
+  for (int grp = blockIdx.x * C::WAVES + wave; grp < total_groups; grp += gridDim.x * C::WAVES) {
+    const int grow = grp * C::ROWS + g;                   // row over all frames
+    const int f = grow / a.m_pad;
+    const int row = grow - f * a.m_pad;
+    const float2* in = a.U + (int64_t)grow * a.n_cp;
+    {
+      float2 uv[Q / T];
+#pragma unroll
+      for (int e = 0; e < Q / T; ++e) {
+        const int n = t + T * e;
+        uv[e] = in[n < a.n_cp ? n : 0];
+      }
+#pragma unroll
+      for (int e = 0; e < Q / T; ++e) {
+        const int n = t + T * e;
+        ub[n] = n < a.n_cp ? uv[e] : make_float2(0.0f, 0.0f);
+      }
+    }
+    if (t < 3) ub[t == 0 ? -1 : Q + t - 1] = make_float2(0.0f, 0.0f);
+    team_sync<64>();
+
+    // forward DFT_N from span 4 (the zero-padded first radix-4 stage only copies)
+    float2 X[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) X[e] = ub[(t + T * e) >> 2];
+    fft_stages<N, 16, 4, false>(X, lds, t, true, tw_fwd);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) X[e] = cscale(X[e], wc.x - wc.y * cwin[t + T * e]);
+
+    float* dst = a.P + (int64_t)f * a.p_stride + (int64_t)row * (4 * N);
+    float mx = 0.0f;
+    float p_first[16];
+#pragma unroll
+    for (int b = 2; b <= 4; ++b) {
+      const int phase = b == 4 ? 1 : b;
+      float2 gv[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) gv[e] = cmulc(X[e], tab[C::PH + (phase - 1) * N + t + T * e]);
+      fft_stages<N, 16, 1, true>(gv, lds, t, true, tw_inv);
+      if (phase == 2) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) p_first[e] = cabs2(gv[e]) * a.scale;
+      } else if (phase == 3) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const float p3 = cabs2(gv[e]) * a.scale;
+          reinterpret_cast<float2*>(dst)[2 * (t + T * e) + 1] = make_float2(p_first[e], p3);
+          mx = fmaxf(mx, fmaxf(p_first[e], p3));
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) p_first[e] = cabs2(gv[e]) * a.scale;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int r1 = t + T * e;
+      float2 gz = make_float2(0.0f, 0.0f);
+      if (r1 <= Q) {
+        gz = cadd(cscale(ub[r1], c0), cscale(cadd(ub[r1 - 1], ub[r1 + 1]), c1));
+      } else if (r1 == N - 1) {
+        gz = cscale(ub[0], c1);  // u[N] = u[0]
+      }
+      const float p0 = cabs2(gz) * a.scale;
+      reinterpret_cast<float2*>(dst)[2 * r1] = make_float2(p0, p_first[e]);
+      mx = fmaxf(mx, fmaxf(p0, p_first[e]));
+    }
+#pragma unroll
+    for (int m = T / 2; m > 0; m >>= 1) mx = fmaxf(mx, __shfl_xor(mx, m));
+    if (t == 0) a.rowmax[grow] = mx;
+    // the next row's tap writes must follow this row's reads of ub
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   }
 }
 

@@ -114,9 +114,12 @@ void launch_k1_n(const radar::K1Args& a, int M, int F, hipStream_t s) {
 }
 template <int M>
 void launch_k2_m(const radar::K2Args& a, int n_cp, int F, hipStream_t s) {
-  constexpr int TEAMS = radar::kBlock / (M / 16);
-  dim3 grid((n_cp + TEAMS - 1) / TEAMS, F);
-  hipLaunchKernelGGL(radar::k2_doppler<M>, grid, dim3(radar::kBlock), 0, s, a);
+  // tiles of TW taps: at most 64, at most 1024 threads, padded tile M*(TW+1) <= 17408 entries
+  constexpr int T = M / 16;
+  constexpr int TW0 = 1024 / T < 64 ? 1024 / T : 64;
+  constexpr int TW = M * (TW0 + 1) <= 17408 ? TW0 : 17408 / M - 1;
+  dim3 grid((n_cp + TW - 1) / TW, a.fm, F);
+  hipLaunchKernelGGL((radar::k2_doppler_tiled<M, TW>), grid, dim3(radar::K2Tile<M, TW>::BLOCK), 0, s, a);
 }
 template <int N, int F2>
 void launch_k3_nf(const radar::K3Args& a, int m_pad, int F, hipStream_t s) {
@@ -129,6 +132,22 @@ void launch_k3x4_n(const radar::K3Args& a, int m_pad, int F, hipStream_t s) {
   using C = radar::K3x4<N>;
   dim3 grid(m_pad / C::ROWS, F);
   hipLaunchKernelGGL(radar::k3_range_power_x4<N>, grid, dim3(C::BLOCK), 0, s, a);
+}
+template <int N>
+void launch_k3x4w_n(const radar::K3Args& a, int m_pad, int F, hipStream_t s) {
+  using C = radar::K3w<N>;
+  dim3 grid(m_pad / C::ROWS, F);
+  hipLaunchKernelGGL(radar::k3_range_power_x4w<N>, grid, dim3(64), 0, s, a);
+}
+int g_num_cus = 0;
+template <int N>
+void launch_k3x4p_n(const radar::K3Args& a, int m_pad, int F, hipStream_t s) {
+  using C = radar::K3p<N>;
+  const int total = (int)((int64_t)F * m_pad / C::ROWS);
+  const int per_wg = C::WAVES;
+  int grid = g_num_cus > 0 ? g_num_cus : 256;
+  if (grid * per_wg > total) grid = (total + per_wg - 1) / per_wg;
+  hipLaunchKernelGGL(radar::k3_range_power_x4p<N>, dim3(grid), dim3(C::BLOCK), 0, s, a, total);
 }
 template <int N>
 void launch_k3_n(const radar::K3Args& a, int f2, int m_pad, int F, hipStream_t s) {
@@ -191,6 +210,7 @@ int enqueue_transforms(const radar_frame_desc* d, int F, const float2* in, const
   a2.m_pad = d->m_pad;
   a2.n_cp = d->n_cp;
   a2.fm = d->m_pad / M;
+  a2.ph_off = (a2.fm == 2 || a2.fm == 4 || a2.fm == 8) ? radar::phase_offset(ilog2(M), ilog2(a2.fm)) : -1;
   slot = timer_open(RADAR_STAGE_DOPPLER, s);
 #define K2_CALL(m) launch_k2_m<m>(a2, d->n_cp, F, s)
   RADAR_SIZE_SWITCH(M, K2_CALL)
@@ -213,9 +233,19 @@ int enqueue_transforms(const radar_frame_desc* d, int F, const float2* in, const
   slot = timer_open(RADAR_STAGE_RANGE, s);
   if (x4) {
     switch (N) {
+#ifdef RADAR_K3_FOURWAVE
       case 256: launch_k3x4_n<256>(a3, d->m_pad, F, s); break;
       case 512: launch_k3x4_n<512>(a3, d->m_pad, F, s); break;
       case 1024: launch_k3x4_n<1024>(a3, d->m_pad, F, s); break;
+#elif defined(RADAR_K3_ONEWAVE)
+      case 256: launch_k3x4w_n<256>(a3, d->m_pad, F, s); break;
+      case 512: launch_k3x4w_n<512>(a3, d->m_pad, F, s); break;
+      case 1024: launch_k3x4w_n<1024>(a3, d->m_pad, F, s); break;
+#else
+      case 256: launch_k3x4p_n<256>(a3, d->m_pad, F, s); break;
+      case 512: launch_k3x4p_n<512>(a3, d->m_pad, F, s); break;
+      case 1024: launch_k3x4p_n<1024>(a3, d->m_pad, F, s); break;
+#endif
       case 2048: launch_k3x4_n<2048>(a3, d->m_pad, F, s); break;
       default: launch_k3x4_n<4096>(a3, d->m_pad, F, s); break;
     }
@@ -280,32 +310,50 @@ int radar_init(void) {
   if (dev < 0 || dev >= kMaxDevices) return RADAR_E_UNSUPPORTED;
   std::lock_guard<std::mutex> lock(g_init_mu);
   if (g_init_done[dev]) return RADAR_OK;
-  // block L holds W_L^x = exp(-2 pi i x/L), x < L, at offset L; each value is
-  // taken from the first quadrant of the finest grid so that equal angles in
-  // different blocks get bit-identical entries.
+  {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+      g_num_cus = cus;
+  }
+  // Every entry is exp(-2 pi i x/L) for some x < L, L a power of two <= LMAX;
+  // it is taken from the same angle on the finest grid (LMAX points) in the
+  // first quadrant, so equal angles get bit-identical entries.
   std::vector<double> qc(RADAR_TW_LMAX / 4 + 1), qs(RADAR_TW_LMAX / 4 + 1);
   for (int i = 0; i <= RADAR_TW_LMAX / 4; ++i) {
     const double ang = 2.0 * M_PI * (double)i / (double)RADAR_TW_LMAX;
     qc[i] = std::cos(ang);
     qs[i] = std::sin(ang);
   }
-  std::vector<float2> tab(RADAR_TW_ENTRIES, make_float2(0.0f, 0.0f));
-  for (int L = 1; L <= RADAR_TW_LMAX; L <<= 1) {
-    for (int x = 0; x < L; ++x) {
-      const int t = x * (RADAR_TW_LMAX / L);  // the same angle on the finest grid
-      const int q = t / (RADAR_TW_LMAX / 4);
-      const int rem = t % (RADAR_TW_LMAX / 4);
-      const double c = qc[rem], sn = qs[rem];
-      double re, im;  // exp(-i(2 pi rem/LMAX + q pi/2))
-      switch (q) {
-        case 0: re = c; im = -sn; break;
-        case 1: re = -sn; im = -c; break;
-        case 2: re = -c; im = sn; break;
-        default: re = sn; im = c; break;
-      }
-      tab[L + x] = make_float2((float)re, (float)im);
+  auto w = [&](long long x, long long L) {  // W_L^x, any integer x
+    const long long t = ((x % L + L) % L) * (RADAR_TW_LMAX / L);
+    const int q = (int)(t / (RADAR_TW_LMAX / 4));
+    const int rem = (int)(t % (RADAR_TW_LMAX / 4));
+    const double c = qc[rem], sn = qs[rem];
+    double re, im;  // exp(-i(2 pi rem/LMAX + q pi/2))
+    switch (q) {
+      case 0: re = c; im = -sn; break;
+      case 1: re = -sn; im = -c; break;
+      case 2: re = -c; im = sn; break;
+      default: re = sn; im = c; break;
     }
-  }
+    return make_float2((float)re, (float)im);
+  };
+  std::vector<float2> tab(RADAR_TW_ENTRIES, make_float2(0.0f, 0.0f));
+  for (int L = 1; L <= RADAR_TW_LMAX; L <<= 1)
+    for (int x = 0; x < L; ++x) tab[L + x] = w(x, L);
+  for (int a = 0; a <= RADAR_TW_LOG2; ++a)
+    for (int r = 1; r <= 4; ++r) {
+      if (radar::stage_block(a, r) == 0) continue;
+      const int NS = 1 << a, R = 1 << r, off = radar::stage_offset(a, r);
+      for (int m = 0; m < R; ++m)
+        for (int k = 0; k < NS; ++k) tab[off + m * NS + k] = w((long long)k * m, (long long)NS * R);
+    }
+  for (int n = 4; n <= 12; ++n)
+    for (int p = 1; p <= 3; ++p) {
+      const int N = 1 << n, F = 1 << p, off = radar::phase_offset(n, p);
+      for (int b = 0; b < F; ++b)
+        for (int k = 0; k < N; ++k) tab[off + b * N + k] = w((long long)k * b, (long long)F * N);
+    }
   if (hipMemcpyToSymbol(HIP_SYMBOL(g_radar_tw), tab.data(), tab.size() * sizeof(float2), 0,
                         hipMemcpyHostToDevice) != hipSuccess)
     return RADAR_E_HIP;

@@ -14,7 +14,7 @@ from dataclasses import dataclass
 import torch
 
 PKG_DIR = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG_DIR, "libradar.so")
+LIB_PATH = os.environ.get("RADAR_LIB_PATH") or os.path.join(PKG_DIR, "libradar.so")
 
 RADAR_OK = 0
 RADAR_E_ARG = -1
