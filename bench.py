@@ -34,10 +34,26 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--frames", type=int, default=16, help="frames per step")
+    ap.add_argument("--frames", type=int, default=32, help="frames per step")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="CPU work budget for the oracle baseline (0 disables it)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 3 plain device copies of MIB MiB (calibrates HBM byte counters) and exit")
     return ap.parse_args()
+
+
+def copy_calibration(mib):
+    """Three device-to-device copies of a known size: the FETCH_SIZE / WRITE_SIZE
+    counters of this copy kernel convert counter units into bytes."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    src = torch.rand(n, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_mib": mib, "bytes_per_copy_each_way": n * 4}))
 
 
 def kernel_source_hash():
@@ -88,6 +104,9 @@ def cpu_baseline(frames, budget_s):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the radar path runs one "
               "frame per GPU without collectives, so multi-GPU throughput is N x this figure by design "

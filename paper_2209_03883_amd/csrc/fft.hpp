@@ -248,4 +248,41 @@ __device__ __forceinline__ void team_fft(float2 (&v)[E], float2* lds, int t, boo
   fft_stages<L, E, 1, INV>(v, lds, t, active);
 }
 
+// Twiddle blocks of one FFT plan (the stages of team_fft from span NS0 on,
+// radix E), packed one after another: used to copy a plan's twiddles into LDS.
+template <int L, int E, int NS0>
+struct PlanTable {
+  static constexpr int r_at(int ns) { return L / ns >= E ? E : L / ns; }
+  // entries of the twiddle blocks of the stages from NS0 up to (not incl.) NS
+  static constexpr int off(int NS) {
+    int tot = 0;
+    for (int ns = NS0; ns < NS && ns < L; ns *= r_at(ns))
+      if (ns > 1) tot += ns * r_at(ns);
+    return tot;
+  }
+  static constexpr int size() { return off(L); }
+};
+
+template <int N, int BASE, int NS0>
+struct PlanLayout {
+  template <int NS, int R>
+  static constexpr int off() {
+    return BASE + PlanTable<N, 16, NS0>::off(NS);
+  }
+};
+
+template <int L, int E, int NS0>
+__device__ __forceinline__ void copy_plan_twiddles(float2* dst, int tid, int nthreads) {
+  using PT = PlanTable<L, E, NS0>;
+  int pos = 0;
+  for (int ns = NS0; ns < L; ns *= PT::r_at(ns)) {
+    const int r = PT::r_at(ns);
+    if (ns > 1) {
+      const int src = stage_offset(ilog2c(ns), ilog2c(r));
+      for (int i = tid; i < ns * r; i += nthreads) dst[pos + i] = g_radar_tw[(unsigned)(src + i)];
+      pos += ns * r;
+    }
+  }
+}
+
 }  // namespace radar

@@ -25,8 +25,7 @@ struct K1Args {
   float2* taps;           // [F][M][n_cp]
   uint32_t* status;       // [F] or null
   int M, n_cp;
-  int zc_on;              // apply conj(z_k)
-  uint32_t zc_root, zc_shift;  // reduced modulo 2N (two's complement for negative shifts)
+  uint32_t zc_root, zc_shift;  // reduced modulo 2N; root 0 = no precoding
   int window;
   int from_h;             // input already is the LS estimate H
   float inv_n;            // 1/N
@@ -59,14 +58,12 @@ __global__ void __launch_bounds__(kBlock) k1_taps(K1Args a) {
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int k = t + T * e;
-      float2 h = v[e];
-      if (a.zc_on) {
-        // z_k = exp(+i pi m_k / N) with m_k = root*(k^2 + 2 q k) mod 2N (Eq. 23, even N);
-        // 2N divides 2^32, so unsigned wrap-around keeps m_k exact.
-        const uint32_t uk = (uint32_t)k;
-        const uint32_t m = (a.zc_root * (uk * uk + 2u * a.zc_shift * uk)) & (uint32_t)(2 * N - 1);
-        h = cmul(h, twiddle_split(2 * N, (int)m));  // y * conj(z_k)
-      }
+      // z_k = exp(+i pi m_k / N) with m_k = root*(k^2 + 2 q k) mod 2N (Eq. 23, even N);
+      // 2N divides 2^32, so unsigned wrap-around keeps m_k exact.  Without
+      // precoding root = 0 and the factor is exactly 1.
+      const uint32_t uk = (uint32_t)k;
+      const uint32_t m = (a.zc_root * (uk * uk + 2u * a.zc_shift * uk)) & (uint32_t)(2 * N - 1);
+      const float2 h = cmul(v[e], twiddle_split(2 * N, (int)m));  // y * conj(z_k)
       const float den = cabs2(s[e]);
       st |= den == 0.0f ? 1u : 0u;
       const float inv = den == 0.0f ? 0.0f : __builtin_amdgcn_rcpf(den);
@@ -86,6 +83,82 @@ __global__ void __launch_bounds__(kBlock) k1_taps(K1Args a) {
     if (n < a.n_cp) out[n] = cscale(v[e], scale);
   }
   if (st && a.status) atomicOr(a.status + f, st);
+}
+
+
+// K1, persistent form (N <= 1024): each work-group copies the ZC phase table
+// W_{2N}^m (m < 2N) and the twiddle blocks of the inverse FFT plan into LDS
+// once; its waves then loop over OFDM symbols, one symbol per wave.
+template <int N>
+struct K1p {
+  static constexpr int T = N / 16;
+  static constexpr int ROWS = 64 / T;                      // symbols per wave per pass
+  static constexpr int WAVES = 8;
+  static constexpr int BLOCK = 64 * WAVES;
+  static constexpr int ZC = 0;                             // W_{2N}^m, m < 2N
+  static constexpr int INV = 2 * N;
+  static constexpr int TAB = INV + PlanTable<N, 16, 1>::size();
+  static constexpr int EXCH = LdsSize<N>::value;
+  using Inv = PlanLayout<N, INV, 1>;
+};
+
+template <int N>
+__global__ void __launch_bounds__(K1p<N>::BLOCK) k1_taps_p(K1Args a, int total_groups) {
+  using C = K1p<N>;
+  constexpr int T = C::T;
+  __shared__ float2 tab[C::TAB];
+  __shared__ float2 xch[C::WAVES][C::ROWS][C::EXCH];
+  for (int i = threadIdx.x; i < 2 * N; i += C::BLOCK) tab[C::ZC + i] = g_radar_tw[(unsigned)(2 * N + i)];
+  copy_plan_twiddles<N, 16, 1>(tab + C::INV, threadIdx.x, C::BLOCK);
+  __syncthreads();
+  const TwLds<typename C::Inv> tw_inv{tab};
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int g = lane / T;
+  const int t = lane - g * T;
+  float2* lds = xch[wave][g];
+
+  for (int grp = blockIdx.x * C::WAVES + wave; grp < total_groups; grp += gridDim.x * C::WAVES) {
+    const int gsym = grp * C::ROWS + g;                     // symbol over all frames
+    const int f = gsym / a.M;
+    const int l = gsym - f * a.M;
+    const float2* y = a.Y + f * a.frame_stride + l * a.ld;
+    const float2* x = a.A + f * a.frame_stride + l * a.ld;
+    uint32_t st = 0;
+    float2 v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) v[e] = y[t + T * e];
+    if (!a.from_h) {
+      float2 sv[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) sv[e] = x[t + T * e];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int k = t + T * e;
+        // z_k = exp(+i pi m_k / N), m_k = root*(k^2 + 2 q k) mod 2N (Eq. 23, even N);
+        // without precoding root = 0, so m_k = 0 and the factor is exactly 1
+        const uint32_t uk = (uint32_t)k;
+        const uint32_t m = (a.zc_root * (uk * uk + 2u * a.zc_shift * uk)) & (uint32_t)(2 * N - 1);
+        const float2 h = cmul(v[e], tab[C::ZC + m]);  // y * conj(z_k)
+        const float den = cabs2(sv[e]);
+        st |= den == 0.0f ? 1u : 0u;
+        const float inv = den == 0.0f ? 0.0f : __builtin_amdgcn_rcpf(den);
+        v[e] = cscale(cmulc(h, sv[e]), inv);          // y conj(z) conj(a) / |a|^2
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+      st |= (__builtin_isfinite(v[e].x) && __builtin_isfinite(v[e].y)) ? 0u : 2u;
+    fft_stages<N, 16, 1, true>(v, lds, t, true, tw_inv);
+    const float scale = window_value(a.window, l, a.M) * a.inv_n;
+    float2* out = a.taps + (int64_t)gsym * a.n_cp;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int n = t + T * e;
+      if (n < a.n_cp) out[n] = cscale(v[e], scale);
+    }
+    if (st && a.status) atomicOr(a.status + f, st);
+  }
 }
 
 struct K2Args {
@@ -396,166 +469,22 @@ __global__ void __launch_bounds__(K3x4<N>::BLOCK) k3_range_power_x4(K3Args a) {
 }
 
 // ------------------------------------------------------------------------
-// K3 for 4x range padding and N_cp <= N/4, N <= 1024: one wavefront per
-// Doppler row (four rows per wave at N = 256), all four phases in sequence.
+// K3 for 4x range padding and N_cp <= N/4, N <= 1024: persistent waves, one
+// wavefront per Doppler row (four rows per wave at N = 256), all four phases
+// of the row in sequence.
 //   forward  DFT_N of u (N_cp <= N/4 taps): the first radix-4 Stockham stage
 //            of a zero-padded input only copies, y[i] = u[i >> 2], so the
 //            transform starts at span 4 straight from the taps.
-//   phases   b = 1, 2, 3: IFFT_N(w_k X_k e^{+2 pi i k b/(4N)}) in turn;
+//   phases   b = 2, 3, 1: IFFT_N(w_k X_k e^{+2 pi i k b/(4N)});
 //            b = 0: the 3-tap filter N (a0 u[r1] - a1/2 (u[r1-1] + u[r1+1])).
-// The four |G|^2 values of each r1 stay in registers and leave as one float4.
+//   output   the four |G|^2 values of each r1 leave as two float2 pairs
+//            (holding all four phases in registers would spill).
+// Every twiddle a row needs is the same for all rows, so each work-group
+// copies the stage blocks of its two FFT plans, the phase twiddles
+// W_{4N}^{k b} (b = 1..3) and the window cosines into LDS once, and its waves
+// then loop over rows independently: twiddle reads are LDS reads, not
+// vector-memory instructions.
 // ------------------------------------------------------------------------
-template <int N>
-struct K3w {
-  static constexpr int T = N / 16;               // threads per row
-  static constexpr int ROWS = 64 / T;            // rows per wave
-  static constexpr int EXCH = LdsSize<N>::value;
-  static constexpr int UBUF = N / 4 + 3;         // u[-1 .. N/4+1]
-};
-
-template <int N>
-__global__ void __launch_bounds__(64) k3_range_power_x4w(K3Args a) {
-  using C = K3w<N>;
-  constexpr int T = C::T;
-  constexpr int Q = N / 4;
-  static_assert(T <= 64, "one wave per row at most");
-  __shared__ float2 s_x[C::ROWS][C::EXCH];
-  __shared__ float2 s_u[C::ROWS][C::UBUF];
-  const int g = threadIdx.x / T;
-  const int t = threadIdx.x - g * T;
-  const int f = blockIdx.y;
-  const int row = blockIdx.x * C::ROWS + g;
-  float2* lds = s_x[g];
-  float2* ub = s_u[g] + 1;
-
-  const float2* in = a.U + ((int64_t)f * a.m_pad + row) * a.n_cp;
-  {
-    float2 uv[Q / T];
-#pragma unroll
-    for (int e = 0; e < Q / T; ++e) {
-      const int n = t + T * e;
-      uv[e] = in[n < a.n_cp ? n : 0];  // in-bounds load, zeroed below
-    }
-#pragma unroll
-    for (int e = 0; e < Q / T; ++e) {
-      const int n = t + T * e;
-      ub[n] = n < a.n_cp ? uv[e] : make_float2(0.0f, 0.0f);
-    }
-  }
-  if (t < 3) ub[t == 0 ? -1 : Q + t - 1] = make_float2(0.0f, 0.0f);
-  team_sync<64>();
-
-  // forward DFT_N, then the range window w_k = a0 - a1 cos(2 pi k/N)
-  const float2 wc = window_coeffs(a.window);
-  float cw[16];
-#pragma unroll
-  for (int e = 0; e < 16; ++e) cw[e] = twiddle(N, t + T * e).x;
-  float2 X[16];
-#pragma unroll
-  for (int e = 0; e < 16; ++e) X[e] = ub[(t + T * e) >> 2];
-  fft_stages<N, 16, 4, false>(X, lds, t, true);
-#pragma unroll
-  for (int e = 0; e < 16; ++e) X[e] = cscale(X[e], wc.x - wc.y * cw[e]);
-
-  // Phases 2 and 3 first (stored as float2 pairs), then phase 1 and the
-  // filtered phase 0 (the other pair).  Each phase's twiddle loads are tied to
-  // the previous phase's result so the compiler cannot hoist them all to the
-  // top and run out of registers.
-  float* dst = a.P + (int64_t)f * a.p_stride + (int64_t)row * (4 * N);
-  float mx = 0.0f;
-  float dep = 0.0f;
-  float p_first[16];
-#pragma unroll
-  for (int b = 2; b <= 4; ++b) {
-    const int phase = b == 4 ? 1 : b;
-    float2 gv[16];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      int idx = t + T * e;
-      asm volatile("" : "+v"(idx) : "v"(dep));
-      gv[e] = cmulc(X[e], phase_twiddle<N, 4>(phase, idx));
-    }
-    fft_stages<N, 16, 1, true>(gv, lds, t, true);
-    if (phase == 2) {
-#pragma unroll
-      for (int e = 0; e < 16; ++e) p_first[e] = cabs2(gv[e]) * a.scale;
-      dep = p_first[0];
-    } else if (phase == 3) {
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const float p3 = cabs2(gv[e]) * a.scale;
-        reinterpret_cast<float2*>(dst)[2 * (t + T * e) + 1] = make_float2(p_first[e], p3);
-        mx = fmaxf(mx, fmaxf(p_first[e], p3));
-      }
-      dep = mx;
-    } else {
-#pragma unroll
-      for (int e = 0; e < 16; ++e) p_first[e] = cabs2(gv[e]) * a.scale;
-    }
-  }
-
-  const float c0 = (float)N * wc.x, c1 = -0.5f * (float)N * wc.y;
-#pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int r1 = t + T * e;
-    float2 gz = make_float2(0.0f, 0.0f);
-    if (r1 <= Q) {
-      gz = cadd(cscale(ub[r1], c0), cscale(cadd(ub[r1 - 1], ub[r1 + 1]), c1));
-    } else if (r1 == N - 1) {
-      gz = cscale(ub[0], c1);  // u[N] = u[0]
-    }
-    const float p0 = cabs2(gz) * a.scale;
-    reinterpret_cast<float2*>(dst)[2 * r1] = make_float2(p0, p_first[e]);
-    mx = fmaxf(mx, fmaxf(p0, p_first[e]));
-  }
-#pragma unroll
-  for (int m = T / 2; m > 0; m >>= 1) mx = fmaxf(mx, __shfl_xor(mx, m));
-  if (t == 0) a.rowmax[(int64_t)f * a.m_pad + row] = mx;
-}
-
-// ------------------------------------------------------------------------
-// K3, persistent form of the one-wave-per-row kernel above (N' = 4N,
-// N_cp <= N/4, N <= 1024).  Every twiddle a row needs is the same for all
-// rows, so each work-group copies the stage blocks of its two FFT plans, the
-// phase twiddles W_{4N}^{k b} (b = 1..3) and the window cosines into LDS once,
-// and its waves then loop over rows independently.  Twiddle reads become LDS
-// reads instead of vector-memory instructions.
-// ------------------------------------------------------------------------
-template <int L, int E, int NS0>
-struct PlanTable {
-  static constexpr int r_at(int ns) { return L / ns >= E ? E : L / ns; }
-  // entries of the twiddle blocks of the stages from NS0 up to (not incl.) NS
-  static constexpr int off(int NS) {
-    int tot = 0;
-    for (int ns = NS0; ns < NS && ns < L; ns *= r_at(ns))
-      if (ns > 1) tot += ns * r_at(ns);
-    return tot;
-  }
-  static constexpr int size() { return off(L); }
-};
-
-template <int N, int BASE, int NS0>
-struct PlanLayout {
-  template <int NS, int R>
-  static constexpr int off() {
-    return BASE + PlanTable<N, 16, NS0>::off(NS);
-  }
-};
-
-template <int L, int E, int NS0>
-__device__ __forceinline__ void copy_plan_twiddles(float2* dst, int tid, int nthreads) {
-  using PT = PlanTable<L, E, NS0>;
-  int pos = 0;
-  for (int ns = NS0; ns < L; ns *= PT::r_at(ns)) {
-    const int r = PT::r_at(ns);
-    if (ns > 1) {
-      const int src = stage_offset(ilog2c(ns), ilog2c(r));
-      for (int i = tid; i < ns * r; i += nthreads) dst[pos + i] = g_radar_tw[(unsigned)(src + i)];
-      pos += ns * r;
-    }
-  }
-}
-
 template <int N>
 struct K3p {
   static constexpr int T = N / 16;

@@ -88,27 +88,32 @@ __global__ void __launch_bounds__(256) k_row_max(const float* P, int64_t p_strid
   if (threadIdx.x == 0) rowmax[(int64_t)f * m_pad + row] = mx;
 }
 
-// Steps 2 and the row list of step 3.  Grid (F), 1024 threads, dynamic LDS
-// m_pad floats.
-__global__ void __launch_bounds__(1024) k_peak_threshold(const float* rowmax, int m_pad, int k, float* tau_out,
-                                                         int32_t* list, int32_t* cnt_out) {
-  extern __shared__ float s_m[];
-  __shared__ uint64_t red[16];
-  __shared__ int32_t s_scan[1024];
+// Step 2 and the row list of step 3 (grid F, 256 threads, dynamic LDS m_pad
+// words).  Profile peaks are marked in LDS with strided (coalesced) row
+// ownership; the k-th largest comes from k rounds of work-group maxima; the
+// row list is written in ascending order from contiguous row chunks.
+__global__ void __launch_bounds__(256) k_peak_threshold(const float* rowmax, int m_pad, int k, float* tau_out,
+                                                        int32_t* list, int32_t* cnt_out) {
+  extern __shared__ uint32_t s_prof[];  // ord bits of profile peaks, 0 elsewhere
+  __shared__ uint64_t red[4];
+  __shared__ int s_cnt[4];
   const int f = blockIdx.x;
   const int tid = threadIdx.x;
   const int mask = m_pad - 1;
-  for (int i = tid; i < m_pad; i += blockDim.x) s_m[i] = rowmax[(int64_t)f * m_pad + i];
+  const float* m = rowmax + (int64_t)f * m_pad;
+  for (int i = tid; i < m_pad; i += 256) {
+    const float v = m[i];
+    s_prof[i] = (v >= m[(i - 1) & mask] && v >= m[(i + 1) & mask]) ? ord_bits(v) : 0u;
+  }
   __syncthreads();
-
   uint64_t last = ~0ull;
   int found = 0;
   for (; found < k; ++found) {
     uint64_t best = 0;
-    for (int i = tid; i < m_pad; i += blockDim.x) {
-      const float v = s_m[i];
-      if (v >= s_m[(i - 1) & mask] && v >= s_m[(i + 1) & mask]) {
-        const uint64_t key = make_key(ord_bits(v), (uint32_t)i);
+    for (int i = tid; i < m_pad; i += 256) {
+      const uint32_t o = s_prof[i];
+      if (o) {
+        const uint64_t key = make_key(o, (uint32_t)i);
         if (key < last && key > best) best = key;
       }
     }
@@ -118,26 +123,30 @@ __global__ void __launch_bounds__(1024) k_peak_threshold(const float* rowmax, in
   }
   const float tau = found == k ? ord_value((uint32_t)(last >> 32)) : -__builtin_huge_valf();
 
-  // rows with m_s >= tau, ascending: each thread owns a contiguous chunk
-  const int chunk = (m_pad + blockDim.x - 1) / blockDim.x;
-  const int lo = tid * chunk;
-  const int hi = min(lo + chunk, m_pad);
+  const int chunk = (m_pad + 255) / 256;
+  const int lo = tid * chunk < m_pad ? tid * chunk : m_pad;
+  const int hi = lo + chunk <= m_pad ? lo + chunk : m_pad;
   int c = 0;
-  for (int i = lo; i < hi; ++i) c += s_m[i] >= tau ? 1 : 0;
-  s_scan[tid] = c;
-  __syncthreads();
-  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-    const int add = tid >= off ? s_scan[tid - off] : 0;
-    __syncthreads();
-    s_scan[tid] += add;
-    __syncthreads();
+  for (int i = lo; i < hi; ++i) c += m[i] >= tau ? 1 : 0;
+  int incl = c;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int up = __shfl_up(incl, off);
+    if ((tid & 63) >= off) incl += up;
   }
-  int pos = s_scan[tid] - c;  // exclusive prefix
+  if ((tid & 63) == 63) s_cnt[tid >> 6] = incl;
+  __syncthreads();
+  int before = 0, total = 0;
+  for (int w = 0; w < 4; ++w) {
+    if (w < (tid >> 6)) before += s_cnt[w];
+    total += s_cnt[w];
+  }
+  int pos = before + incl - c;
   int32_t* out = list + (int64_t)f * m_pad;
   for (int i = lo; i < hi; ++i)
-    if (s_m[i] >= tau) out[pos++] = i;
-  if (tid == blockDim.x - 1) {
-    cnt_out[f] = s_scan[tid];
+    if (m[i] >= tau) out[pos++] = i;
+  if (tid == 0) {
+    cnt_out[f] = total;
     tau_out[f] = tau;
   }
 }
@@ -150,6 +159,7 @@ __global__ void __launch_bounds__(256) k_peak_rows_listed(const float* P, int64_
                                                           const int32_t* cnt, uint64_t* cand) {
   extern __shared__ uint32_t s_ord[];  // n_pad entries, 0 = not a candidate
   __shared__ uint64_t red[4];
+  __shared__ int s_cnt[4];
   const int f = blockIdx.y;
   const int count = cnt[f];
   const float th = tau[f];
@@ -170,24 +180,49 @@ __global__ void __launch_bounds__(256) k_peak_rows_listed(const float* P, int64_
       }
       s_ord[r] = pk ? ord_bits(v) : 0u;
     }
-    __syncthreads();
     uint64_t* out = cand + ((int64_t)f * m_pad + j) * k;
     const uint32_t flat0 = (uint32_t)row * (uint32_t)n_pad;
-    uint64_t last = ~0ull;
+    // how many candidates does the row hold?
+    int mine = 0;
+    for (int r = threadIdx.x; r < n_pad; r += blockDim.x) mine += s_ord[r] ? 1 : 0;
+    __syncthreads();
+    int incl = mine;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int up = __shfl_up(incl, off);
+      if ((threadIdx.x & 63) >= off) incl += up;
+    }
+    if ((threadIdx.x & 63) == 63) s_cnt[threadIdx.x >> 6] = incl;
+    __syncthreads();
+    int total = 0, before = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      if (w < (int)(threadIdx.x >> 6)) before += s_cnt[w];
+      total += s_cnt[w];
+    }
     int i = 0;
-    for (; i < k; ++i) {
-      uint64_t best = 0;
-      for (int r = threadIdx.x; r < n_pad; r += blockDim.x) {
-        const uint32_t o = s_ord[r];
-        if (o) {
-          const uint64_t key = make_key(o, flat0 + (uint32_t)r);
-          if (key < last && key > best) best = key;
+    if (total <= k) {
+      // few candidates: write them all (the merge ranks them), pad with 0
+      int pos = before + incl - mine;
+      for (int r = threadIdx.x; r < n_pad; r += blockDim.x)
+        if (s_ord[r]) out[pos++] = make_key(s_ord[r], flat0 + (uint32_t)r);
+      for (int q = total + (int)threadIdx.x; q < k; q += blockDim.x) out[q] = 0;
+      i = k;  // nothing left to pad below
+    } else {
+      uint64_t last = ~0ull;
+      for (; i < k; ++i) {
+        uint64_t best = 0;
+        for (int r = threadIdx.x; r < n_pad; r += blockDim.x) {
+          const uint32_t o = s_ord[r];
+          if (o) {
+            const uint64_t key = make_key(o, flat0 + (uint32_t)r);
+            if (key < last && key > best) best = key;
+          }
         }
+        best = block_max_u64(best, red);
+        if (threadIdx.x == 0) out[i] = best;
+        if (best == 0) break;
+        last = best;
       }
-      best = block_max_u64(best, red);
-      if (threadIdx.x == 0) out[i] = best;
-      if (best == 0) break;
-      last = best;
     }
     if (threadIdx.x == 0)
       for (int q = i + 1; q < k; ++q) out[q] = 0;
@@ -195,10 +230,10 @@ __global__ void __launch_bounds__(256) k_peak_rows_listed(const float* P, int64_
   }
 }
 
-// Step 4: the k best keys over the scanned rows of a frame.  Grid (F), 1024 threads.
-__global__ void __launch_bounds__(1024) k_peak_merge(const uint64_t* cand, const int32_t* cnt, int m_pad, int n_pad,
-                                                     int k, radar_peak* peaks, int32_t* n_peaks) {
-  __shared__ uint64_t red[16];
+// Step 4: the k best keys over the scanned rows of a frame, one wavefront per
+// frame (grid F, 64 threads).
+__global__ void __launch_bounds__(64) k_peak_merge(const uint64_t* cand, const int32_t* cnt, int m_pad, int n_pad,
+                                                   int k, radar_peak* peaks, int32_t* n_peaks) {
   const int f = blockIdx.x;
   const int count = cnt[f] * k;
   const uint64_t* c = cand + (int64_t)f * m_pad * k;
@@ -206,11 +241,11 @@ __global__ void __launch_bounds__(1024) k_peak_merge(const uint64_t* cand, const
   int i = 0;
   for (; i < k; ++i) {
     uint64_t best = 0;
-    for (int j = threadIdx.x; j < count; j += blockDim.x) {
+    for (int j = threadIdx.x; j < count; j += 64) {
       const uint64_t key = c[j];
       if (key < last && key > best) best = key;
     }
-    best = block_max_u64(best, red);
+    best = wave_max_u64(best);
     if (best == 0) break;
     if (threadIdx.x == 0) {
       const uint32_t flat = 0xFFFFFFFFu - (uint32_t)best;

@@ -107,7 +107,13 @@ void timer_close(int stage, int slot, hipStream_t s) {
 
 // ----------------------------------------------------------------- dispatch
 template <int N>
+void launch_k1p_n(const radar::K1Args& a, int M, int F, hipStream_t s);
+template <int N>
 void launch_k1_n(const radar::K1Args& a, int M, int F, hipStream_t s) {
+  if constexpr (N >= 256 && N <= 1024) {
+    launch_k1p_n<N>(a, M, F, s);
+    return;
+  }
   constexpr int TEAMS = radar::kBlock / (N / 16);
   dim3 grid((M + TEAMS - 1) / TEAMS, F);
   hipLaunchKernelGGL(radar::k1_taps<N>, grid, dim3(radar::kBlock), 0, s, a);
@@ -133,13 +139,15 @@ void launch_k3x4_n(const radar::K3Args& a, int m_pad, int F, hipStream_t s) {
   dim3 grid(m_pad / C::ROWS, F);
   hipLaunchKernelGGL(radar::k3_range_power_x4<N>, grid, dim3(C::BLOCK), 0, s, a);
 }
-template <int N>
-void launch_k3x4w_n(const radar::K3Args& a, int m_pad, int F, hipStream_t s) {
-  using C = radar::K3w<N>;
-  dim3 grid(m_pad / C::ROWS, F);
-  hipLaunchKernelGGL(radar::k3_range_power_x4w<N>, grid, dim3(64), 0, s, a);
-}
 int g_num_cus = 0;
+template <int N>
+void launch_k1p_n(const radar::K1Args& a, int M, int F, hipStream_t s) {
+  using C = radar::K1p<N>;
+  const int total = (int)((int64_t)F * M / C::ROWS);
+  int grid = g_num_cus > 0 ? g_num_cus : 256;
+  if (grid * C::WAVES > total) grid = (total + C::WAVES - 1) / C::WAVES;
+  hipLaunchKernelGGL(radar::k1_taps_p<N>, dim3(grid), dim3(C::BLOCK), 0, s, a, total);
+}
 template <int N>
 void launch_k3x4p_n(const radar::K3Args& a, int m_pad, int F, hipStream_t s) {
   using C = radar::K3p<N>;
@@ -189,10 +197,10 @@ int enqueue_transforms(const radar_frame_desc* d, int F, const float2* in, const
   a1.status = status;
   a1.M = M;
   a1.n_cp = d->n_cp;
-  a1.zc_on = d->zc_mode == RADAR_ZC_DIAG;
   const int64_t two_n = 2 * (int64_t)N;
-  a1.zc_root = (uint32_t)(((d->zc_root % two_n) + two_n) % two_n);
-  a1.zc_shift = (uint32_t)(((d->zc_shift % two_n) + two_n) % two_n);
+  const bool zc_on = d->zc_mode == RADAR_ZC_DIAG;
+  a1.zc_root = zc_on ? (uint32_t)(((d->zc_root % two_n) + two_n) % two_n) : 0u;
+  a1.zc_shift = zc_on ? (uint32_t)(((d->zc_shift % two_n) + two_n) % two_n) : 0u;
   a1.window = d->window;
   a1.from_h = from_h;
   a1.inv_n = 1.0f / (float)N;
@@ -233,19 +241,9 @@ int enqueue_transforms(const radar_frame_desc* d, int F, const float2* in, const
   slot = timer_open(RADAR_STAGE_RANGE, s);
   if (x4) {
     switch (N) {
-#ifdef RADAR_K3_FOURWAVE
-      case 256: launch_k3x4_n<256>(a3, d->m_pad, F, s); break;
-      case 512: launch_k3x4_n<512>(a3, d->m_pad, F, s); break;
-      case 1024: launch_k3x4_n<1024>(a3, d->m_pad, F, s); break;
-#elif defined(RADAR_K3_ONEWAVE)
-      case 256: launch_k3x4w_n<256>(a3, d->m_pad, F, s); break;
-      case 512: launch_k3x4w_n<512>(a3, d->m_pad, F, s); break;
-      case 1024: launch_k3x4w_n<1024>(a3, d->m_pad, F, s); break;
-#else
       case 256: launch_k3x4p_n<256>(a3, d->m_pad, F, s); break;
       case 512: launch_k3x4p_n<512>(a3, d->m_pad, F, s); break;
       case 1024: launch_k3x4p_n<1024>(a3, d->m_pad, F, s); break;
-#endif
       case 2048: launch_k3x4_n<2048>(a3, d->m_pad, F, s); break;
       default: launch_k3x4_n<4096>(a3, d->m_pad, F, s); break;
     }
@@ -273,14 +271,14 @@ int enqueue_peaks(const float* P, int64_t p_stride, int m_pad, int n_pad, int F,
   int32_t* list = reinterpret_cast<int32_t*>(ws + w.list);
   uint64_t* cand = reinterpret_cast<uint64_t*>(ws + w.cand);
   const int slot = timer_open(RADAR_STAGE_PEAKS, s);
-  hipLaunchKernelGGL(radar::k_peak_threshold, dim3(F), dim3(1024), m_pad * sizeof(float), s, rowmax, m_pad, k, tau,
+  hipLaunchKernelGGL(radar::k_peak_threshold, dim3(F), dim3(256), m_pad * sizeof(uint32_t), s, rowmax, m_pad, k, tau,
                      list, cnt);
   RADAR_HIP_CHECK(hipGetLastError());
   const int groups = m_pad < 32 ? m_pad : 32;
   hipLaunchKernelGGL(radar::k_peak_rows_listed, dim3(groups, F), dim3(256), n_pad * sizeof(uint32_t), s, P,
                      p_stride, m_pad, n_pad, k, tau, list, cnt, cand);
   RADAR_HIP_CHECK(hipGetLastError());
-  hipLaunchKernelGGL(radar::k_peak_merge, dim3(F), dim3(1024), 0, s, cand, cnt, m_pad, n_pad, k, peaks, n_peaks);
+  hipLaunchKernelGGL(radar::k_peak_merge, dim3(F), dim3(64), 0, s, cand, cnt, m_pad, n_pad, k, peaks, n_peaks);
   RADAR_HIP_CHECK(hipGetLastError());
   timer_close(RADAR_STAGE_PEAKS, slot, s);
   return RADAR_OK;

@@ -43,14 +43,22 @@ def _ws(cfg, F=1, k=8):
     return radar.lib().radar_frame_workspace_size(ctypes.byref(cfg.desc()), F, k)
 
 
+def _al(x):
+    return (x + 255) // 256 * 256
+
+
+def _peak_ws(F, m_pad, k):
+    # row maxima, tau, row count, row list, per-row candidates
+    return _al(F * m_pad * 4) + _al(F * 4) + _al(F * 4) + _al(F * m_pad * 4) + _al(F * m_pad * k * 8)
+
+
 def test_workspace_size_arithmetic():
     cfg = radar.Config(1024, 1024, 4096, 4096, 256, zc_root=7)
-    taps = 1024 * 256 * 8
-    U = 4096 * 256 * 8
-    cand = 4096 * 8 * 8
-    assert _ws(cfg, 1, 8) == taps + U + cand
-    assert _ws(cfg, 3, 8) == 3 * (taps + U + cand)
-    assert radar.lib().radar_detect_workspace_size(4096, 4096, 2, 8) == 2 * 4096 * 8 * 8
+    for F in (1, 3):
+        taps = F * 1024 * 256 * 8
+        U = F * 4096 * 256 * 8
+        assert _ws(cfg, F, 8) == _al(taps) + _al(U) + _peak_ws(F, 4096, 8)
+    assert radar.lib().radar_detect_workspace_size(4096, 4096, 2, 8) == _peak_ws(2, 4096, 8)
 
 
 @pytest.mark.parametrize("bad,code", [
