@@ -228,3 +228,93 @@ def bins_to_range_velocity(r: float, s: float, n_pad: int, m_pad: int, delta_f: 
     """
     ts = symbol_time(delta_f, cp_fraction)
     return c * r / (2.0 * n_pad * delta_f), c * s / (2.0 * f_c * m_pad * ts)
+
+
+# --------------------------------------------------------------------------
+# Sub-bin refinement (Sec. II-B.2: the padded sizes N', M' "improve the
+# precision" of the estimate; the refinement evaluates a 16x-padded
+# periodogram locally and interpolates)
+# --------------------------------------------------------------------------
+FINE = 16  # the local grid is the periodogram padded 16x in both axes
+
+
+def windowed_estimate(Y, A, *, n_cp, window_kind=WINDOW_HANN, zc_root=None, zc_shift=0):
+    """The windowed DFT-CE estimate that Eq. 17 transforms: w_k w_l H'_{l,k}."""
+    n = np.asarray(Y).shape[1]
+    m = np.asarray(Y).shape[0]
+    z = None if zc_root is None else zc_sequence(n, zc_root, zc_shift)
+    Hd = dft_ce(ls_estimate(Y, A, z), n_cp)
+    return Hd * window(m, window_kind)[:, None] * window(n, window_kind)[None, :]
+
+
+def local_periodogram(Hw: np.ndarray, sigma: np.ndarray, rho: np.ndarray) -> np.ndarray:
+    """Eq. 17 evaluated off the DFT grid, at fractional native bins.
+
+        P(sigma, rho) = 1/(N M) | sum_l sum_k Hw[l,k] e^{-j 2 pi l sigma/M} e^{+j 2 pi k rho/N} |^2
+
+    sigma (Doppler) and rho (range) are 1-D arrays of native-bin positions;
+    returns P with shape (len(sigma), len(rho)).  At sigma = s M/M' and
+    rho = r N/N' this is exactly P(s, r) of the N' x M' periodogram.
+    """
+    Hw = np.asarray(Hw, dtype=np.complex128)
+    m, n = Hw.shape
+    es = np.exp(-2j * np.pi * np.outer(np.asarray(sigma, float), np.arange(m)) / m)   # (S, M)
+    er = np.exp(+2j * np.pi * np.outer(np.arange(n), np.asarray(rho, float)) / n)     # (N, R)
+    G = es @ Hw @ er
+    return (G.real ** 2 + G.imag ** 2) / (n * m)
+
+
+def quadratic_peak_offset(F: np.ndarray):
+    """Stationary point of the least-squares quadratic through a 3x3 patch.
+
+    F[i, j] holds ln P at (x, y) = (i-1, j-1).  Fits
+    a + b x + c y + d x^2 + e x y + f y^2 and solves grad = 0.  If the fitted
+    Hessian is not negative definite or the point lies more than one cell
+    away, falls back to the separable 3-point parabolas along x and y.
+    The result is clamped to [-0.5, 0.5] per axis.
+    """
+    F = np.asarray(F, dtype=np.float64)
+    x = np.array([-1.0, 0.0, 1.0])[:, None] * np.ones((1, 3))
+    y = np.ones((3, 1)) * np.array([-1.0, 0.0, 1.0])[None, :]
+    b = np.sum(x * F) / 6.0
+    c = np.sum(y * F) / 6.0
+    e = np.sum(x * y * F) / 4.0
+    d = np.sum((x * x - 2.0 / 3.0) * F) / 2.0
+    f = np.sum((y * y - 2.0 / 3.0) * F) / 2.0
+    det = 4.0 * d * f - e * e
+    if d < 0 and det > 0:
+        ox = -(2.0 * f * b - e * c) / det
+        oy = -(2.0 * d * c - e * b) / det
+        if abs(ox) <= 1.0 and abs(oy) <= 1.0:
+            return float(np.clip(ox, -0.5, 0.5)), float(np.clip(oy, -0.5, 0.5))
+
+    def parabola(m1, z0, p1):
+        den = m1 - 2.0 * z0 + p1
+        return 0.0 if den >= 0 else float(np.clip(0.5 * (m1 - p1) / den, -0.5, 0.5))
+
+    return parabola(F[0, 1], F[1, 1], F[2, 1]), parabola(F[1, 0], F[1, 1], F[1, 2])
+
+
+def refine_peak(Hw: np.ndarray, s: int, r: int, n_pad: int, m_pad: int):
+    """Sub-cell refinement of a peak at signed Doppler index s and range index r.
+
+    The 16x-padded periodogram is evaluated on the 7 x 7 fine cells centred on
+    the peak (fine cell = 1/16 native bin), the best cell of the inner 5 x 5
+    is taken, and the quadratic of ln P through its 3 x 3 neighbourhood gives
+    the sub-cell offset.  Returns (s_off, r_off) in cells of the N' x M' grid.
+    """
+    m, n = np.asarray(Hw).shape
+    fs = FINE * m // m_pad          # fine cells per padded cell (Doppler)
+    fr = FINE * n // n_pad          # fine cells per padded cell (range)
+    cs, cr = s * fs, r * fr         # fine index of the peak
+    off = np.arange(-3, 4)
+    P = local_periodogram(Hw, (cs + off) / FINE, (cr + off) / FINE)
+    tiny = np.finfo(np.float64).tiny
+    inner = P[1:6, 1:6]
+    bi, bj = np.unravel_index(np.argmax(inner), inner.shape)
+    bi, bj = bi + 1, bj + 1
+    patch = np.log(np.maximum(P[bi - 1:bi + 2, bj - 1:bj + 2], tiny))
+    ox, oy = quadratic_peak_offset(patch)
+    fine_s = (bi - 3) + ox
+    fine_r = (bj - 3) + oy
+    return fine_s / fs, fine_r / fr

@@ -283,3 +283,94 @@ def test_bins_to_units():
     d, v = O.bins_to_range_velocity(4.0, 4.0, 4 * 2048, 4 * 560, 240e3, 77e9, 0.25)
     dd, dv = O.resolution(2048, 560, 240e3, 77e9, 0.25)
     assert d == pytest.approx(dd) and v == pytest.approx(dv)
+
+
+# ------------------------------------------------- sub-cell refinement
+def test_local_periodogram_on_grid_equals_padded_fft():
+    # At sigma = s M/M', rho = r N/N' the off-grid sum is the N' x M'
+    # periodogram of Eq. 17 (FFT route, pinned by brute force above).
+    rng = np.random.default_rng(21)
+    m, n, mp, nq = 16, 32, 64, 128
+    H = rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))
+    Hd = O.dft_ce(H, 8)
+    Pfft = O.periodogram(Hd, nq, mp, O.WINDOW_HANN)
+    Hw = Hd * O.window(m, O.WINDOW_HANN)[:, None] * O.window(n, O.WINDOW_HANN)[None, :]
+    s = np.arange(-mp // 2, mp // 2)
+    r = np.arange(nq)
+    Ploc = O.local_periodogram(Hw, s * m / mp, r * n / nq)
+    np.testing.assert_allclose(Ploc, Pfft, rtol=1e-10, atol=1e-12 * Pfft.max())
+
+
+def test_local_periodogram_brute_force_off_grid():
+    rng = np.random.default_rng(22)
+    m, n = 3, 5
+    Hw = rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))
+    sig, rho = [0.3, -1.7], [2.25, 0.0, 4.9]
+    got = O.local_periodogram(Hw, sig, rho)
+    for a, sv in enumerate(sig):
+        for b_, rv in enumerate(rho):
+            g = 0j
+            for l in range(m):
+                for k in range(n):
+                    g += Hw[l, k] * complex(math.cos(-2 * math.pi * l * sv / m), math.sin(-2 * math.pi * l * sv / m)) \
+                        * complex(math.cos(2 * math.pi * k * rv / n), math.sin(2 * math.pi * k * rv / n))
+            assert got[a, b_] == pytest.approx(abs(g) ** 2 / (n * m), rel=1e-12)
+
+
+def _quad_patch(x0, y0, hxx, hxy, hyy, a=1.0):
+    x = np.array([-1.0, 0.0, 1.0])[:, None]
+    y = np.array([-1.0, 0.0, 1.0])[None, :]
+    dx, dy = x - x0, y - y0
+    return a + 0.5 * (hxx * dx * dx + 2 * hxy * dx * dy + hyy * dy * dy)
+
+
+def test_quadratic_offset_exact_on_quadratics():
+    # a concave quadratic is its own least-squares fit: the stationary point
+    # comes back exactly (also with a cross term)
+    for x0, y0, hxy in [(0.2, -0.35, 0.0), (-0.45, 0.1, 0.3), (0.0, 0.0, -0.5), (0.5, -0.5, 0.2)]:
+        ox, oy = O.quadratic_peak_offset(_quad_patch(x0, y0, -2.0, hxy, -1.5))
+        assert ox == pytest.approx(x0, abs=1e-12) and oy == pytest.approx(y0, abs=1e-12)
+
+
+def test_quadratic_offset_clamps_and_falls_back():
+    # stationary point 0.8 cells away: accepted (within one cell) and clamped
+    ox, oy = O.quadratic_peak_offset(_quad_patch(0.8, -0.2, -2.0, 0.0, -2.0))
+    assert ox == 0.5 and oy == pytest.approx(-0.2, abs=1e-12)
+    # a saddle (no maximum): 3-point parabola along x, none along y
+    F = _quad_patch(0.2, 0.0, -2.0, 0.0, 2.0)
+    ox, oy = O.quadratic_peak_offset(F)
+    assert ox == pytest.approx(0.2, abs=1e-12) and oy == 0.0
+
+
+@pytest.mark.parametrize("rho,nu", [(10.37, -5.61), (3.58, 7.44), (20.03, 0.96)])
+def test_refine_recovers_noiseless_off_grid_target(rho, nu):
+    # a single target whose taps all lie inside N_cp: the refined peak lands on
+    # the generator's (rho, nu) within a small fraction of a fine cell
+    spec = S.FrameSpec(n_sub=128, n_sym=64, qam=16, zc_root=3, n_targets=1, noise=False, on_grid=False)
+    f = S.make_frame(spec, 90, 0)
+    f.rho[:] = rho
+    f.nu[:] = nu
+    k = np.arange(128)
+    l = np.arange(64)
+    echo = f.b[0] * np.outer(np.exp(2j * np.pi * l * nu / 64), np.exp(-2j * np.pi * k * rho / 128))
+    Y = f.A * S.tx_precoding_sequence(128, 3)[None, :] * echo
+    n_pad, m_pad = 512, 256
+    Hw = O.windowed_estimate(Y, f.A, n_cp=128, zc_root=3)
+    P = O.frame_periodogram(Y, f.A, n_pad=n_pad, m_pad=m_pad, n_cp=128, zc_root=3)
+    row, r, _ = O.find_peaks(P, 1)[0]
+    s = row - m_pad // 2
+    s_off, r_off = O.refine_peak(Hw, s, r, n_pad, m_pad)
+    assert abs((s + s_off) * 64 / m_pad - nu) < 2e-3
+    assert abs((r + r_off) * 128 / n_pad - rho) < 2e-3
+    # the grid peak alone is off by up to half a padded cell
+    assert abs(s * 64 / m_pad - nu) + abs(r * 128 / n_pad - rho) > 1e-2
+
+
+def test_refine_peak_on_exact_fine_cell_gives_zero_offset():
+    # target exactly on a padded cell: the symmetric lobe puts the fit at 0
+    spec = S.FrameSpec(n_sub=64, n_sym=32, qam=4, zc_root=None, n_targets=1, noise=False)
+    f = S.make_frame(spec, 91, 0)
+    Hw = O.windowed_estimate(f.Y, f.A, n_cp=64)
+    s, r = int(f.nu[0] * 4), int(f.rho[0] * 4)
+    s_off, r_off = O.refine_peak(Hw, s, r, 256, 128)
+    assert abs(s_off) < 1e-9 and abs(r_off) < 1e-9
