@@ -66,6 +66,7 @@ enum {
 enum { RADAR_WIN_RECT = 0, RADAR_WIN_HANN = 1, RADAR_WIN_HAMMING = 2 };  /* periodic windows */
 enum { RADAR_ZC_NONE = 0, RADAR_ZC_DIAG = 1 };  /* ZC precoding along the subcarriers */
 enum { RADAR_ST_ZERO_SYMBOL = 1u, RADAR_ST_NONFINITE = 2u };
+enum { RADAR_FLAG_REFINE = 1 };  /* radar_frame_desc.flags */
 
 /* One frame shape.  Names follow the paper: N subcarriers, M OFDM symbols,
  * N' >= N and M' >= M the zero-padded periodogram sizes of Eq. 17, N_cp the
@@ -80,7 +81,7 @@ typedef struct {
   int32_t zc_root;              /* r' of Eq. 23, relatively prime to N */
   int32_t zc_shift;             /* q' of Eq. 23 */
   int32_t window;               /* RADAR_WIN_*, applied separably over k and l */
-  int32_t reserved;             /* must be 0 */
+  int32_t flags;                /* RADAR_FLAG_* bits, 0 for none */
   int64_t ld;                   /* elements between consecutive OFDM symbols, >= N */
 } radar_frame_desc;
 
@@ -115,6 +116,14 @@ int radar_init(void);
  *        N' x M', scaled by 1/(N M)
  *   peaks = the k largest 3x3 cyclic local maxima of P, ranked by
  *           (P descending, flat index row*N'+r ascending).
+ *   With RADAR_FLAG_REFINE each peak also gets sub-cell offsets (s_off,
+ *   r_off, in cells of the N' x M' grid): the 16x-padded periodogram is
+ *   evaluated on the 7 x 7 fine cells around the peak directly from the DFT-CE
+ *   taps (FP32 Doppler sums, FP64 range sums), the best fine cell of the inner
+ *   5 x 5 is taken and a least-squares quadratic of ln P through its 3 x 3
+ *   neighbourhood is solved in FP64 (separable parabolas when that quadratic
+ *   has no maximum within one cell); offsets are clamped to half a fine cell
+ *   about the best fine cell.  Needs M'/M <= 16, N'/N <= 16 and M <= 1024.
  * Y, A:     input frames, frame f at Y + f*frame_stride (elements).
  * P:        output, frame f at P + f*p_frame_stride (floats); must not be NULL;
  *           p_frame_stride >= M'*N' and a multiple of 4; P 16-byte aligned.
@@ -135,7 +144,8 @@ int radar_frame_process(const radar_frame_desc *d, int32_t n_frames,
  *
  * H is an LS estimate (Eq. 16) laid out like Y.  If d->n_cp < N the DFT-CE of
  * Eq. 20-22 is applied first; d->zc_mode must be RADAR_ZC_NONE (H is already
- * de-precoded).  P as for radar_frame_process.  The workspace size is
+ * de-precoded) and d->flags must be 0 (no peaks, so nothing to refine:
+ * RADAR_E_ARG otherwise).  P as for radar_frame_process.  The workspace size is
  * radar_frame_workspace_size(d, n_frames, 1).
  * ------------------------------------------------------------------------ */
 int radar_periodogram(const radar_frame_desc *d, int32_t n_frames,

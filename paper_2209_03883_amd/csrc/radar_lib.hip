@@ -14,6 +14,7 @@ __device__ float2 g_radar_tw[RADAR_TW_ENTRIES];
 
 #include "k_frame.hpp"
 #include "k_peaks.hpp"
+#include "k_refine.hpp"
 
 namespace {
 
@@ -37,12 +38,14 @@ int validate_desc(const radar_frame_desc* d) {
   if (d->n_cp < 1 || d->n_cp > N) return RADAR_E_ARG;
   if (d->window < RADAR_WIN_RECT || d->window > RADAR_WIN_HAMMING) return RADAR_E_ARG;
   if (d->zc_mode != RADAR_ZC_NONE && d->zc_mode != RADAR_ZC_DIAG) return RADAR_E_ARG;
-  if (d->reserved != 0) return RADAR_E_ARG;
+  if ((d->flags & ~RADAR_FLAG_REFINE) != 0) return RADAR_E_ARG;
   if (d->ld < N) return RADAR_E_ARG;
   if (!is_pow2(N) || !is_pow2(M) || N < 16 || N > 4096 || M < 16 || M > 4096) return RADAR_E_UNSUPPORTED;
   if (!is_pow2(d->n_pad) || !is_pow2(d->m_pad)) return RADAR_E_UNSUPPORTED;
   if (d->n_pad / N > 8 || d->n_pad > RADAR_TW_LMAX || d->m_pad > RADAR_TW_LMAX) return RADAR_E_UNSUPPORTED;
   if (d->zc_mode == RADAR_ZC_DIAG && (d->zc_root % 2) == 0) return RADAR_E_NOT_COPRIME;  // N is a power of two
+  if ((d->flags & RADAR_FLAG_REFINE) && (d->m_pad / M > 16 || d->n_pad / N > 16 || M > 1024))
+    return RADAR_E_UNSUPPORTED;
   return RADAR_OK;
 }
 
@@ -394,14 +397,29 @@ int radar_frame_process(const radar_frame_desc* d, int32_t n_frames, const radar
   rc = enqueue_transforms(d, n_frames, reinterpret_cast<const float2*>(Y), reinterpret_cast<const float2*>(A),
                           frame_stride, 0, P, p_frame_stride, status, w, wsb, s);
   if (rc != RADAR_OK) return rc;
-  return enqueue_peaks(P, p_frame_stride, d->m_pad, d->n_pad, n_frames, k, w.pk, wsb, peaks, n_peaks, s);
+  rc = enqueue_peaks(P, p_frame_stride, d->m_pad, d->n_pad, n_frames, k, w.pk, wsb, peaks, n_peaks, s);
+  if (rc != RADAR_OK || !(d->flags & RADAR_FLAG_REFINE)) return rc;
+  radar::K7Args a7{};
+  a7.taps = reinterpret_cast<const float2*>(wsb + w.taps);
+  a7.peaks = peaks;
+  a7.n_peaks = n_peaks;
+  a7.k = k;
+  a7.M = d->n_sym;
+  a7.N = d->n_sub;
+  a7.n_cp = d->n_cp;
+  a7.m_pad = d->m_pad;
+  a7.n_pad = d->n_pad;
+  a7.window = d->window;
+  hipLaunchKernelGGL(radar::k7_refine, dim3(k, n_frames), dim3(radar::kRefineThreads), 0, s, a7);
+  RADAR_HIP_CHECK(hipGetLastError());
+  return RADAR_OK;
 }
 
 int radar_periodogram(const radar_frame_desc* d, int32_t n_frames, const radar_cf32* H, int64_t frame_stride,
                       float* P, int64_t p_frame_stride, void* ws, size_t ws_bytes, void* hip_stream) {
   int rc = check_frame_common(d, n_frames, frame_stride, p_frame_stride, P);
   if (rc != RADAR_OK) return rc;
-  if (!H || !ws) return RADAR_E_ARG;
+  if (!H || !ws || d->flags != 0) return RADAR_E_ARG;
   if (d->zc_mode != RADAR_ZC_NONE) return RADAR_E_ARG;
   const FrameWs w = frame_ws_layout(d, n_frames, 1);
   if (ws_bytes < w.total) return RADAR_E_WORKSPACE;

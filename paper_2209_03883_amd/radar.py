@@ -26,6 +26,7 @@ RADAR_E_NOT_COPRIME = -5
 WIN_RECT, WIN_HANN, WIN_HAMMING = 0, 1, 2
 ZC_NONE, ZC_DIAG = 0, 1
 ST_ZERO_SYMBOL, ST_NONFINITE = 1, 2
+FLAG_REFINE = 1
 
 EXPORTED = (
     "radar_version", "radar_status_string", "radar_init",
@@ -47,7 +48,7 @@ class FrameDesc(ctypes.Structure):
         ("n_pad", ctypes.c_int32), ("m_pad", ctypes.c_int32),
         ("n_cp", ctypes.c_int32), ("zc_mode", ctypes.c_int32),
         ("zc_root", ctypes.c_int32), ("zc_shift", ctypes.c_int32),
-        ("window", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("window", ctypes.c_int32), ("flags", ctypes.c_int32),
         ("ld", ctypes.c_int64),
     ]
 
@@ -115,12 +116,14 @@ class Config:
     zc_root: int | None = None
     zc_shift: int = 0
     window: int = WIN_HANN
+    refine: bool = False
 
     def desc(self, ld: int | None = None) -> FrameDesc:
         return FrameDesc(self.n_sub, self.n_sym, self.n_pad, self.m_pad, self.n_cp,
                          ZC_NONE if self.zc_root is None else ZC_DIAG,
                          0 if self.zc_root is None else int(self.zc_root), int(self.zc_shift),
-                         int(self.window), 0, int(self.n_sub if ld is None else ld))
+                         int(self.window), FLAG_REFINE if self.refine else 0,
+                         int(self.n_sub if ld is None else ld))
 
 
 def _stream_ptr(stream) -> int:

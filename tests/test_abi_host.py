@@ -71,6 +71,8 @@ def test_workspace_size_arithmetic():
     (dict(n_cp=1025), radar.RADAR_E_ARG),
     (dict(window=7), radar.RADAR_E_ARG),
     (dict(zc_root=8), radar.RADAR_E_NOT_COPRIME),      # gcd(8, 1024) != 1
+    (dict(n_sym=2048, m_pad=4096, refine=True), radar.RADAR_E_UNSUPPORTED),  # refinement needs M <= 1024
+    (dict(n_sym=16, m_pad=512, refine=True), radar.RADAR_E_UNSUPPORTED),     # and M'/M <= 16
 ])
 def test_validation_rejects(bad, code):
     base = dict(n_sub=1024, n_sym=1024, n_pad=4096, m_pad=4096, n_cp=256, zc_root=7)
@@ -110,3 +112,15 @@ def test_detect_rejects():
     assert L.radar_detect_topk(p, 64, 64, 1, 0, 0, p, p, p, 1 << 20, None) == radar.RADAR_E_ARG
     assert L.radar_detect_topk(p, 64, 64, 1, 0, 3, p, p, p, 10, None) == radar.RADAR_E_WORKSPACE
     assert L.radar_detect_topk(None, 64, 64, 1, 0, 3, p, p, p, 1 << 20, None) == radar.RADAR_E_ARG
+
+
+def test_flags_validation():
+    L = radar.lib()
+    d = radar.Config(256, 64, 1024, 256, 32, zc_root=1).desc()
+    d.flags = 2  # unknown bit
+    assert L.radar_frame_workspace_size(ctypes.byref(d), 1, 3) == 0
+    ok = radar.Config(256, 64, 1024, 256, 32, refine=True)
+    need = L.radar_frame_workspace_size(ctypes.byref(ok.desc()), 1, 3)
+    assert need > 0
+    # the periodogram entry finds no peaks: the refine flag is an argument error
+    assert L.radar_periodogram(ctypes.byref(ok.desc()), 1, 256, 0, 256, 0, 256, need, None) == radar.RADAR_E_ARG
