@@ -318,3 +318,146 @@ def refine_peak(Hw: np.ndarray, s: int, r: int, n_pad: int, m_pad: int):
     fine_s = (bi - 3) + ox
     fine_r = (bj - 3) + oy
     return fine_s / fs, fine_r / fr
+
+
+# --------------------------------------------------------------------------
+# FPS-SFT, the sparse alternative to the periodogram (Sec. III-C)
+#
+# The paper names the algorithm (Fourier projection-slice sparse FFT), its
+# per-iteration cost (three Q-length slices, Q = lcm(N, M), one Q-point DFT
+# each) and its iterative nature (components found earlier are passed on),
+# and defers the rest to the algorithm's own publication.  The reading used
+# here rests on the discrete projection-slice identity: for the slice
+#     s_tau[t] = h[(alpha t + tau_1) mod N, (beta t + tau_2) mod M],  t < Q,
+#     DFT_Q(s_tau)[m] = Q/(N M) * sum over (k1, k2) with
+#                       (alpha k1 Q/N + beta k2 Q/M) = m (mod Q)
+#                       of X[k1, k2] exp(+2 pi i (k1 tau_1/N + k2 tau_2/M)),
+# X = DFT_N x DFT_M of h.  A bin holding one component therefore reveals k1
+# and k2 through the phase ratios of the slices at offsets (1, 0) and (0, 1)
+# to the slice at (0, 0).
+#
+# h is the LS estimate of Eq. 16 (after ZC de-precoding) indexed
+# h[k, l] (subcarrier k, symbol l), without DFT-CE and without a window.
+# --------------------------------------------------------------------------
+# Oblique directions come first: along (1, 0) or (0, 1) every frequency of a
+# range (Doppler) column lands in one bin whatever its other coordinate, so the
+# bin check cannot reject a collision of two targets that share a range
+# (Doppler) bin, and such collisions then decode as ghosts.
+SFT_DIRECTIONS = ((1, 1), (1, -1), (1, 2), (2, 1), (1, -2), (2, -1), (1, 0), (0, 1))
+SFT_OFFSETS = ((0, 0), (1, 0), (0, 1))
+SFT_PFA = 1e-2     # false-alarm probability (Table I)
+SFT_TOL = 0.25     # 1-sparsity tolerance on the magnitude of the slice ratios
+# Bins whose power is below this fraction of the direction's largest raw bin
+# power are numerically empty (rounding residue of noiseless or peeled bins).
+SFT_FLOOR = 1e-10
+
+
+def sft_length(n: int, m: int) -> int:
+    """Q = lcm(N, M), the slice length (Sec. III-C)."""
+    return n * m // math.gcd(n, m)
+
+
+def sft_slices(H: np.ndarray, dirs=SFT_DIRECTIONS) -> np.ndarray:
+    """The Q-point DFTs of the three slices of every direction.
+
+    H: LS estimate [M][N] (symbol-major).  Returns S[i, j, :] = DFT_Q of the
+    slice of direction dirs[i] at offset SFT_OFFSETS[j].
+    """
+    H = np.asarray(H, dtype=np.complex128)
+    m, n = H.shape
+    q = sft_length(n, m)
+    t = np.arange(q, dtype=np.int64)
+    S = np.empty((len(dirs), len(SFT_OFFSETS), q), dtype=np.complex128)
+    for i, (a, b) in enumerate(dirs):
+        for j, (t1, t2) in enumerate(SFT_OFFSETS):
+            k = (a * t + t1) % n
+            l = (b * t + t2) % m
+            S[i, j] = np.fft.fft(H[l, k])
+    return S
+
+
+def sft_bin(k1: int, k2: int, a: int, b: int, n: int, m: int) -> int:
+    """The bin of direction (a, b) onto which frequency (k1, k2) projects."""
+    q = sft_length(n, m)
+    return (a * k1 * (q // n) + b * k2 * (q // m)) % q
+
+
+def sft_decode(S: np.ndarray, n: int, m: int, dirs=SFT_DIRECTIONS, k: int = 8, pfa: float = SFT_PFA,
+               tol: float = SFT_TOL):
+    """The iterative recovery of FPS-SFT from the slice spectra S (sft_slices).
+
+    Directions are taken in order.  In each: the components found so far are
+    peeled off the three slices; bins are visited by decreasing |S_0|
+    (lower bin first on ties) down to the threshold theta, where
+    theta^2 = -ln(pfa) * median(|S_0|^2) / ln 2 (the median of an exponential
+    noise power is its mean times ln 2), skipping numerically empty bins
+    (power below SFT_FLOOR times the largest bin power of the direction's raw
+    slice, a guard that only matters without noise); a bin is taken as 1-sparse when both
+    slice ratios S_1/S_0 and S_2/S_0 have magnitude within tol of 1, their
+    phases decode (k1, k2), and (k1, k2) projects back onto the same bin.
+    Its coefficient c = (N M / Q) S_0 is added to an already found (k1, k2) or
+    starts a new component.  The search ends when k components are known or
+    the directions run out.  Returns a list of [k1, k2, c].
+    """
+    S = np.asarray(S, dtype=np.complex128)
+    q = S.shape[2]
+    scale = q / (n * m)
+    found: list[list] = []
+    for i, (a, b) in enumerate(dirs):
+        if len(found) >= k:
+            break
+        Si = S[i].copy()
+        floor = SFT_FLOOR * float(np.max(Si[0].real ** 2 + Si[0].imag ** 2))
+        for k1, k2, c in found:
+            mb = sft_bin(k1, k2, a, b, n, m)
+            for j, (t1, t2) in enumerate(SFT_OFFSETS):
+                Si[j, mb] -= scale * c * np.exp(2j * np.pi * (k1 * t1 / n + k2 * t2 / m))
+        p = Si[0].real ** 2 + Si[0].imag ** 2
+        theta2 = -math.log(pfa) * float(np.median(p)) / math.log(2.0)
+        for mb in np.lexsort((np.arange(q), -p)):
+            if p[mb] < theta2 or p[mb] <= floor:
+                break
+            r1 = Si[1, mb] / Si[0, mb]
+            r2 = Si[2, mb] / Si[0, mb]
+            if abs(abs(r1) - 1.0) > tol or abs(abs(r2) - 1.0) > tol:
+                continue
+            k1 = int(np.rint(n * np.angle(r1) / (2.0 * np.pi))) % n
+            k2 = int(np.rint(m * np.angle(r2) / (2.0 * np.pi))) % m
+            if sft_bin(k1, k2, a, b, n, m) != mb:
+                continue
+            c = Si[0, mb] / scale
+            for comp in found:
+                if comp[0] == k1 and comp[1] == k2:
+                    comp[2] += c
+                    break
+            else:
+                found.append([k1, k2, c])
+            if len(found) >= k:
+                break
+    return found
+
+
+def sft_to_peaks(found, n: int, m: int):
+    """Components as periodogram-axis detections (s, r, p), ranked like find_peaks.
+
+    The slices use forward DFTs along both axes while Eq. 17 takes the inverse
+    DFT over the subcarriers, so the range bin is r = -k1 mod N; the Doppler
+    bin is k2 wrapped to [-M/2, M/2).  p = |c|^2 / (N M) is the value the
+    native-resolution, rectangular-window periodogram takes at that cell.
+    """
+    out = []
+    for k1, k2, c in found:
+        s = int(k2) if k2 < m // 2 else int(k2) - m
+        r = (-int(k1)) % n
+        out.append((s, r, float(abs(c) ** 2 / (n * m))))
+    out.sort(key=lambda e: (-e[2], (e[0] + m // 2) * n + e[1]))
+    return out
+
+
+def fps_sft(Y, A, *, zc_root=None, zc_shift=0, dirs=SFT_DIRECTIONS, k=8, pfa=SFT_PFA, tol=SFT_TOL):
+    """FPS-SFT on one received frame: LS estimate (Eq. 16, de-precoded), slices,
+    recovery; returns the detections of sft_to_peaks."""
+    m, n = np.asarray(Y).shape
+    z = None if zc_root is None else zc_sequence(n, zc_root, zc_shift)
+    S = sft_slices(ls_estimate(Y, A, z), dirs)
+    return sft_to_peaks(sft_decode(S, n, m, dirs, k, pfa, tol), n, m)

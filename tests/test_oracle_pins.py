@@ -374,3 +374,102 @@ def test_refine_peak_on_exact_fine_cell_gives_zero_offset():
     s, r = int(f.nu[0] * 4), int(f.rho[0] * 4)
     s_off, r_off = O.refine_peak(Hw, s, r, 256, 128)
     assert abs(s_off) < 1e-9 and abs(r_off) < 1e-9
+
+
+# ------------------------------------------------------- FPS-SFT (Sec. III-C)
+def _dft2_brute(h):
+    n, m = h.shape
+    X = np.zeros((n, m), dtype=np.complex128)
+    for k1 in range(n):
+        for k2 in range(m):
+            acc = 0j
+            for a in range(n):
+                for b in range(m):
+                    acc += h[a, b] * np.exp(-2j * np.pi * (k1 * a / n + k2 * b / m))
+            X[k1, k2] = acc
+    return X
+
+
+@pytest.mark.parametrize("n,m", [(8, 4), (4, 8), (8, 8), (6, 4)])
+def test_sft_slices_are_projections_of_the_2d_spectrum(n, m):
+    # discrete projection-slice identity, checked term by term against a
+    # brute-force 2-D DFT (also for a non-power-of-two N, Q = lcm = 12)
+    rng = np.random.default_rng(30 + n + m)
+    H = rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))
+    X = _dft2_brute(H.T)           # X[k1, k2], h[k, l] = H[l, k]
+    dirs = O.SFT_DIRECTIONS
+    S = O.sft_slices(H, dirs)
+    q = O.sft_length(n, m)
+    assert S.shape == (len(dirs), 3, q)
+    for i, (a, b) in enumerate(dirs):
+        for j, (t1, t2) in enumerate(O.SFT_OFFSETS):
+            want = np.zeros(q, dtype=np.complex128)
+            for k1 in range(n):
+                for k2 in range(m):
+                    mb = (a * k1 * (q // n) + b * k2 * (q // m)) % q
+                    want[mb] += X[k1, k2] * np.exp(2j * np.pi * (k1 * t1 / n + k2 * t2 / m)) * q / (n * m)
+            np.testing.assert_allclose(S[i, j], want, atol=1e-9)
+
+
+@pytest.mark.parametrize("n,m,nt,seed", [(256, 64, 3, 0), (1024, 1024, 8, 0), (64, 256, 5, 1), (16, 16, 2, 0),
+                                         (4096, 32, 6, 2), (32, 4096, 6, 0), (128, 128, 12, 0)])
+def test_sft_recovers_noiseless_sparse_frames(n, m, nt, seed):
+    spec = S.FrameSpec(n_sub=n, n_sym=m, qam=16, zc_root=3, n_targets=nt, noise=False, on_grid=True, rho_min=0,
+                       rho_max=max(1, n // 4), nu_abs_max=m // 2 - 1, min_sep=1.0)
+    f = S.make_frame(spec, 95, n * 10 + seed)
+    det = O.fps_sft(f.Y, f.A, zc_root=3, k=nt)
+    assert sorted((s, r) for s, r, _ in det) == sorted((int(v), int(r)) for r, v in zip(f.rho, f.nu))
+    # the coefficient is X[k1, k2] = N M b: p = N M |b|^2
+    want_p = sorted(n * m * np.abs(f.b) ** 2)
+    np.testing.assert_allclose(sorted(p for _, _, p in det), want_p, rtol=1e-9)
+
+
+def test_sft_peeling_resolves_collisions():
+    # T1 and T2 share k1 (collide along (1, 0)); T1 and T3 share k2 (collide
+    # along (0, 1) until T3, found along (1, 0), is peeled off).  Equal
+    # coefficients and k2 (or k1) four apart make each collided bin fail the
+    # 1-sparse test (ratio magnitude cos(pi/4)), so T1 is only found after the peel.
+    n = m = 16
+    comps = [(5, 3, 1.0), (5, 7, 1.0), (9, 3, 1.0)]
+    k = np.arange(n)[:, None]
+    l = np.arange(m)[None, :]
+    h = sum(c / (n * m) * np.exp(2j * np.pi * (k1 * k / n + k2 * l / m)) for k1, k2, c in comps)
+    S_ = O.sft_slices(h.T, ((1, 0), (0, 1)))
+    found = O.sft_decode(S_, n, m, ((1, 0), (0, 1)), k=3)
+    assert sorted((a, b) for a, b, _ in found) == [(5, 3), (5, 7), (9, 3)]
+    for k1, k2, c in found:
+        assert abs(c - dict(((a, b), cc) for a, b, cc in comps)[(k1, k2)]) < 1e-12
+
+
+def test_sft_k_cap_takes_strongest_bin_first():
+    n = m = 16
+    comps = [(2, 1, 1.0), (6, 9, 3.0)]
+    k = np.arange(n)[:, None]
+    l = np.arange(m)[None, :]
+    h = sum(c / (n * m) * np.exp(2j * np.pi * (k1 * k / n + k2 * l / m)) for k1, k2, c in comps)
+    found = O.sft_decode(O.sft_slices(h.T), n, m, k=1)
+    assert [(a, b) for a, b, _ in found] == [(6, 9)]
+
+
+def test_sft_detection_maps_onto_the_periodogram_cell():
+    # axis mapping and scale: a lone on-grid target's detection (s, r, p) is the
+    # native-resolution rectangular-window periodogram's peak cell and value
+    spec = S.FrameSpec(n_sub=128, n_sym=32, qam=4, zc_root=5, n_targets=1, noise=False, on_grid=True,
+                       rho_min=3, rho_max=40, nu_abs_max=15)
+    f = S.make_frame(spec, 99, 0)
+    (s, r, p), = O.fps_sft(f.Y, f.A, zc_root=5, k=1)
+    P = O.frame_periodogram(f.Y, f.A, n_pad=128, m_pad=32, n_cp=128, window_kind=O.WINDOW_RECT, zc_root=5)
+    assert (s, r) == (int(f.nu[0]), int(f.rho[0]))
+    assert p == pytest.approx(P[s + 16, r], rel=1e-12)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 5])
+def test_sft_agrees_with_periodogram_at_high_snr(seed):
+    # five on-grid targets at 20 dB: FPS-SFT's cells are the periodogram's
+    # top-5 local maxima (Sec. III-C compares the two on such a scene)
+    spec = S.FrameSpec(n_sub=256, n_sym=64, qam=16, zc_root=1, n_targets=5, snr_db=20.0, on_grid=True,
+                       rho_min=1, rho_max=60, nu_abs_max=31, min_sep=2.0)
+    f = S.make_frame(spec, 96, seed)
+    det = O.fps_sft(f.Y, f.A, zc_root=1, k=5)
+    P = O.frame_periodogram(f.Y, f.A, n_pad=256, m_pad=64, n_cp=256, window_kind=O.WINDOW_RECT, zc_root=1)
+    assert sorted((s, r) for s, r, _ in det) == sorted((row - 32, c) for row, c, _ in O.find_peaks(P, 5))
