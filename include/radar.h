@@ -168,6 +168,65 @@ int radar_detect_topk(const float *P, int32_t m_pad, int32_t n_pad, int32_t n_fr
                       void *ws, size_t ws_bytes, void *hip_stream);
 
 /* ------------------------------------------------------------------------
+ * radar_fps_sft -- FPS-SFT, the sparse alternative to the periodogram
+ * (Sec. III-C).
+ *
+ * Works on the LS estimate h[k, l] = y conj(z_k) / a of Eq. 16 at native
+ * resolution (no DFT-CE, no window, no padding).  Of the descriptor only
+ * n_sub (N), n_sym (M), zc_mode, zc_root, zc_shift and ld are used (N, M
+ * powers of two in [16, 4096]); flags must be 0.  Q = lcm(N, M) = max(N, M).
+ *
+ * For each direction (alpha, beta) of s->dirs, in order, three slices
+ * t -> h[(alpha t + tau1) mod N, (beta t + tau2) mod M], t < Q, at offsets
+ * (tau1, tau2) = (0,0), (1,0), (0,1) are gathered and Q-point DFTed; their
+ * bin m is the projection of the 2-D spectrum X = DFT_N x DFT_M of h onto
+ * m = (alpha k1 Q/N + beta k2 Q/M) mod Q.  Recovery, per direction: subtract
+ * the components found so far; visit bins by decreasing |S0|^2 (lower bin
+ * first on ties) while |S0|^2 >= theta^2 = -ln(pfa) median(|S0|^2) / ln 2
+ * and |S0|^2 > 1e-10 times the direction's largest raw |S0|^2; accept a bin
+ * whose ratios S1/S0 and S2/S0 have magnitude within tol of 1 and whose
+ * phases decode k1 = round(N arg(S1/S0) / 2 pi) mod N,
+ * k2 = round(M arg(S2/S0) / 2 pi) mod M projecting back onto that bin; its
+ * coefficient c = (N M / Q) S0 is added to a known (k1, k2) or starts a new
+ * component.  Stops when k components are known or the directions run out.
+ *
+ * Output per frame: the n_peaks[f] <= k components as radar_peak entries in
+ * periodogram coordinates, s = k2 wrapped to [-M/2, M/2), r = -k1 mod N,
+ * p = |c|^2 / (N M) (the value of the native-resolution rectangular-window
+ * periodogram of Eq. 17 at that cell for an isolated on-grid target), ranked
+ * by (p descending, (s + M/2) N + r ascending); s_off = r_off = 0.
+ * peaks: [n_frames][s->k]; status as for radar_frame_process, set from the
+ * gathered samples only.
+ * slices: optional output (NULL for none): the raw slice spectra
+ *         [n_frames][n_dirs][3][Q] complex64 before any subtraction.
+ * ws: device workspace of radar_fps_sft_workspace_size bytes (0 when slices
+ *     is given: the spectra then live there).
+ * Errors: RADAR_E_ARG for bad pointers, n_frames outside [1, 65535], n_dirs
+ * outside [1, 16], k outside [1, 64], pfa outside (0, 1), tol outside
+ * (0, 1], a direction with alpha = 0 mod N and beta = 0 mod M, or flags != 0;
+ * RADAR_E_UNSUPPORTED for N or M outside the sizes above;
+ * RADAR_E_NOT_COPRIME as for radar_frame_process; RADAR_E_WORKSPACE.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t n_dirs;               /* I, number of slice directions, 1..16 */
+  int32_t dirs[16][2];          /* (alpha, beta) per direction, any integers */
+  int32_t k;                    /* components sought, 1..64 */
+  float pfa;                    /* per-bin false-alarm probability (Table I: 1e-2) */
+  float tol;                    /* 1-sparsity tolerance on |S1/S0|, |S2/S0| */
+  int32_t flags;                /* must be 0 */
+} radar_sft_desc;
+
+/* Fills s with the default recovery settings: eight directions (1,1),
+ * (1,-1), (1,2), (2,1), (1,-2), (2,-1), (1,0), (0,1), pfa = 1e-2, tol = 0.25,
+ * and the given k. */
+void radar_sft_default(radar_sft_desc *s, int32_t k);
+size_t radar_fps_sft_workspace_size(const radar_frame_desc *d, const radar_sft_desc *s, int32_t n_frames);
+int radar_fps_sft(const radar_frame_desc *d, const radar_sft_desc *s, int32_t n_frames,
+                  const radar_cf32 *Y, const radar_cf32 *A, int64_t frame_stride,
+                  radar_peak *peaks, int32_t *n_peaks, uint32_t *status,
+                  radar_cf32 *slices, void *ws, size_t ws_bytes, void *hip_stream);
+
+/* ------------------------------------------------------------------------
  * Stage timing -- a profiling aid, off by default.
  *
  * radar_timing_start(max_launches) creates HIP events for up to max_launches
@@ -184,7 +243,10 @@ enum {
   RADAR_STAGE_DOPPLER = 1,      /* M'-point Doppler DFT of the taps       (Eq. 17) */
   RADAR_STAGE_RANGE = 2,        /* DFT_N back, window, N'-point range DFT, |.|^2 (Eq. 22, 17) */
   RADAR_STAGE_PEAKS = 3,        /* local maxima and top-k */
-  RADAR_NUM_STAGES = 4
+  RADAR_STAGE_REFINE = 4,       /* sub-cell refinement (RADAR_FLAG_REFINE) */
+  RADAR_STAGE_SFT_SLICES = 5,   /* FPS-SFT slice gather and Q-point DFTs */
+  RADAR_STAGE_SFT_DECODE = 6,   /* FPS-SFT recovery */
+  RADAR_NUM_STAGES = 7
 };
 int radar_timing_start(int32_t max_launches);
 int radar_timing_stop(double *ms_total, int64_t *launches);

@@ -15,6 +15,7 @@ __device__ float2 g_radar_tw[RADAR_TW_ENTRIES];
 #include "k_frame.hpp"
 #include "k_peaks.hpp"
 #include "k_refine.hpp"
+#include "k_sft.hpp"
 
 namespace {
 
@@ -287,6 +288,55 @@ int enqueue_peaks(const float* P, int64_t p_stride, int m_pad, int n_pad, int F,
   return RADAR_OK;
 }
 
+// ------------------------------------------------------------------ FPS-SFT
+struct SftPlan {
+  int N, M, Q, n_dirs;
+  int dir_a[radar::kSftMaxDirs], dir_b[radar::kSftMaxDirs];
+};
+
+int validate_sft(const radar_frame_desc* d, const radar_sft_desc* sd, SftPlan* plan) {
+  if (!d || !sd) return RADAR_E_ARG;
+  const int N = d->n_sub, M = d->n_sym;
+  if (N <= 0 || M <= 0 || d->ld < N || d->flags != 0 || sd->flags != 0) return RADAR_E_ARG;
+  if (d->zc_mode != RADAR_ZC_NONE && d->zc_mode != RADAR_ZC_DIAG) return RADAR_E_ARG;
+  if (sd->n_dirs < 1 || sd->n_dirs > radar::kSftMaxDirs) return RADAR_E_ARG;
+  if (sd->k < 1 || sd->k > radar::kSftMaxK) return RADAR_E_ARG;
+  if (!(sd->pfa > 0.0f && sd->pfa < 1.0f) || !(sd->tol > 0.0f && sd->tol <= 1.0f)) return RADAR_E_ARG;
+  if (!is_pow2(N) || !is_pow2(M) || N < 16 || N > 4096 || M < 16 || M > 4096) return RADAR_E_UNSUPPORTED;
+  if (d->zc_mode == RADAR_ZC_DIAG && (d->zc_root % 2) == 0) return RADAR_E_NOT_COPRIME;
+  plan->N = N;
+  plan->M = M;
+  plan->Q = N > M ? N : M;  // lcm of two powers of two
+  plan->n_dirs = sd->n_dirs;
+  for (int i = 0; i < sd->n_dirs; ++i) {
+    // alpha enters only through alpha t mod N and alpha k1 Q/N mod Q: reduce mod N (beta mod M)
+    const int a = (int)(((int64_t)sd->dirs[i][0] % N + N) % N);
+    const int b = (int)(((int64_t)sd->dirs[i][1] % M + M) % M);
+    if (a == 0 && b == 0) return RADAR_E_ARG;
+    plan->dir_a[i] = a;
+    plan->dir_b[i] = b;
+  }
+  return RADAR_OK;
+}
+
+size_t sft_spectra_bytes(const SftPlan& p, int n_frames) {
+  return align256((size_t)n_frames * p.n_dirs * 3 * p.Q * sizeof(float2));
+}
+
+template <int Q>
+int launch_sft_q(const radar::K5Args& a5, const radar::K6Args& a6, int F, hipStream_t s) {
+  using C = radar::K5Shape<Q>;
+  int slot = timer_open(RADAR_STAGE_SFT_SLICES, s);
+  hipLaunchKernelGGL(radar::k5_sft_slices<Q>, dim3((a5.total + C::TEAMS - 1) / C::TEAMS), dim3(C::BLOCK), 0, s, a5);
+  timer_close(RADAR_STAGE_SFT_SLICES, slot, s);
+  RADAR_HIP_CHECK(hipGetLastError());
+  slot = timer_open(RADAR_STAGE_SFT_DECODE, s);
+  hipLaunchKernelGGL(radar::k6_sft_decode<Q>, dim3(F), dim3(radar::kSftDecodeThreads), 0, s, a6);
+  timer_close(RADAR_STAGE_SFT_DECODE, slot, s);
+  RADAR_HIP_CHECK(hipGetLastError());
+  return RADAR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -410,7 +460,9 @@ int radar_frame_process(const radar_frame_desc* d, int32_t n_frames, const radar
   a7.m_pad = d->m_pad;
   a7.n_pad = d->n_pad;
   a7.window = d->window;
+  const int slot = timer_open(RADAR_STAGE_REFINE, s);
   hipLaunchKernelGGL(radar::k7_refine, dim3(k, n_frames), dim3(radar::kRefineThreads), 0, s, a7);
+  timer_close(RADAR_STAGE_REFINE, slot, s);
   RADAR_HIP_CHECK(hipGetLastError());
   return RADAR_OK;
 }
@@ -454,6 +506,89 @@ int radar_detect_topk(const float* P, int32_t m_pad, int32_t n_pad, int32_t n_fr
                      reinterpret_cast<float*>(wsb + w.rowmax));
   RADAR_HIP_CHECK(hipGetLastError());
   return enqueue_peaks(P, p_frame_stride, m_pad, n_pad, n_frames, k, w, wsb, peaks, n_peaks, s);
+}
+
+void radar_sft_default(radar_sft_desc* s, int32_t k) {
+  if (!s) return;
+  std::memset(s, 0, sizeof(*s));
+  static const int dirs[8][2] = {{1, 1}, {1, -1}, {1, 2}, {2, 1}, {1, -2}, {2, -1}, {1, 0}, {0, 1}};
+  s->n_dirs = 8;
+  for (int i = 0; i < 8; ++i) {
+    s->dirs[i][0] = dirs[i][0];
+    s->dirs[i][1] = dirs[i][1];
+  }
+  s->k = k;
+  s->pfa = 1e-2f;
+  s->tol = 0.25f;
+}
+
+size_t radar_fps_sft_workspace_size(const radar_frame_desc* d, const radar_sft_desc* sd, int32_t n_frames) {
+  SftPlan p;
+  if (validate_sft(d, sd, &p) != RADAR_OK || n_frames < 1) return 0;
+  return sft_spectra_bytes(p, n_frames);
+}
+
+int radar_fps_sft(const radar_frame_desc* d, const radar_sft_desc* sd, int32_t n_frames, const radar_cf32* Y,
+                  const radar_cf32* A, int64_t frame_stride, radar_peak* peaks, int32_t* n_peaks,
+                  uint32_t* status, radar_cf32* slices, void* ws, size_t ws_bytes, void* hip_stream) {
+  SftPlan p;
+  int rc = validate_sft(d, sd, &p);
+  if (rc != RADAR_OK) return rc;
+  if (n_frames < 1 || n_frames > 65535) return RADAR_E_ARG;
+  if (!Y || !A || !peaks || !n_peaks || !status) return RADAR_E_ARG;
+  const int64_t frame_elems = (int64_t)(p.M - 1) * d->ld + p.N;
+  if (n_frames > 1 && frame_stride < frame_elems) return RADAR_E_ARG;
+  float2* spectra = reinterpret_cast<float2*>(slices);
+  if (!spectra) {
+    if (!ws) return RADAR_E_ARG;
+    if (ws_bytes < sft_spectra_bytes(p, n_frames)) return RADAR_E_WORKSPACE;
+    spectra = static_cast<float2*>(ws);
+  }
+  if ((rc = ensure_init()) != RADAR_OK) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  hipLaunchKernelGGL(radar::k0_clear, dim3((n_frames + 255) / 256), dim3(256), 0, s, status, n_peaks, n_frames);
+  RADAR_HIP_CHECK(hipGetLastError());
+
+  radar::K5Args a5{};
+  a5.Y = reinterpret_cast<const float2*>(Y);
+  a5.A = reinterpret_cast<const float2*>(A);
+  a5.ld = d->ld;
+  a5.frame_stride = frame_stride;
+  a5.S = spectra;
+  a5.status = status;
+  a5.N = p.N;
+  a5.M = p.M;
+  a5.n_dirs = p.n_dirs;
+  a5.total = n_frames * p.n_dirs * 3;
+  a5.zc_root = d->zc_mode == RADAR_ZC_DIAG ? (uint32_t)d->zc_root : 0u;
+  a5.zc_shift = d->zc_mode == RADAR_ZC_DIAG ? (uint32_t)d->zc_shift : 0u;
+  radar::K6Args a6{};
+  a6.S = spectra;
+  a6.peaks = peaks;
+  a6.n_peaks = n_peaks;
+  a6.N = p.N;
+  a6.M = p.M;
+  a6.n_dirs = p.n_dirs;
+  a6.k = sd->k;
+  a6.thr_factor = (float)(-std::log((double)sd->pfa) / std::log(2.0));
+  a6.tol = sd->tol;
+  a6.floor_rel = 1e-10f;
+  for (int i = 0; i < p.n_dirs; ++i) {
+    a5.dir_a[i] = a6.dir_a[i] = p.dir_a[i];
+    a5.dir_b[i] = a6.dir_b[i] = p.dir_b[i];
+  }
+  switch (p.Q) {
+    case 16: return launch_sft_q<16>(a5, a6, n_frames, s);
+    case 32: return launch_sft_q<32>(a5, a6, n_frames, s);
+    case 64: return launch_sft_q<64>(a5, a6, n_frames, s);
+    case 128: return launch_sft_q<128>(a5, a6, n_frames, s);
+    case 256: return launch_sft_q<256>(a5, a6, n_frames, s);
+    case 512: return launch_sft_q<512>(a5, a6, n_frames, s);
+    case 1024: return launch_sft_q<1024>(a5, a6, n_frames, s);
+    case 2048: return launch_sft_q<2048>(a5, a6, n_frames, s);
+    case 4096: return launch_sft_q<4096>(a5, a6, n_frames, s);
+    default: return RADAR_E_UNSUPPORTED;
+  }
 }
 
 int radar_timing_start(int32_t max_launches) {

@@ -32,8 +32,9 @@ EXPORTED = (
     "radar_version", "radar_status_string", "radar_init",
     "radar_frame_workspace_size", "radar_frame_process", "radar_periodogram",
     "radar_detect_workspace_size", "radar_detect_topk", "radar_timing_start", "radar_timing_stop",
+    "radar_sft_default", "radar_fps_sft_workspace_size", "radar_fps_sft",
 )
-STAGES = ("taps", "doppler", "range", "peaks")
+STAGES = ("taps", "doppler", "range", "peaks", "refine", "sft_slices", "sft_decode")
 
 
 class RadarError(RuntimeError):
@@ -59,6 +60,11 @@ class Peak(ctypes.Structure):
 
 
 PEAK_WORDS = ctypes.sizeof(Peak) // 4  # 5 x 32-bit words
+
+
+class SftDesc(ctypes.Structure):
+    _fields_ = [("n_dirs", ctypes.c_int32), ("dirs", (ctypes.c_int32 * 2) * 16), ("k", ctypes.c_int32),
+                ("pfa", ctypes.c_float), ("tol", ctypes.c_float), ("flags", ctypes.c_int32)]
 
 _lib = None
 
@@ -87,6 +93,13 @@ def lib() -> ctypes.CDLL:
     L.radar_detect_workspace_size.argtypes = [i32, i32, i32, i32]
     L.radar_detect_topk.restype = ctypes.c_int
     L.radar_detect_topk.argtypes = [vp, i32, i32, i32, i64, i32, vp, vp, vp, sz, vp]
+    sp = ctypes.POINTER(SftDesc)
+    L.radar_sft_default.restype = None
+    L.radar_sft_default.argtypes = [sp, i32]
+    L.radar_fps_sft_workspace_size.restype = sz
+    L.radar_fps_sft_workspace_size.argtypes = [dp, sp, i32]
+    L.radar_fps_sft.restype = ctypes.c_int
+    L.radar_fps_sft.argtypes = [dp, sp, i32, vp, vp, i64, vp, vp, vp, vp, vp, sz, vp]
     L.radar_timing_start.restype = ctypes.c_int
     L.radar_timing_start.argtypes = [i32]
     L.radar_timing_stop.restype = ctypes.c_int
@@ -247,6 +260,60 @@ def detect_topk(P: torch.Tensor, k: int, *, workspace: torch.Tensor | None = Non
                              n_peaks.data_ptr(), workspace.data_ptr(), workspace.numel(), _stream_ptr(stream))
     _check(rc, "radar_detect_topk")
     return peaks, n_peaks
+
+
+def sft_desc(k: int, dirs=None, pfa: float | None = None, tol: float | None = None) -> SftDesc:
+    """radar_sft_desc with the library defaults, optionally overridden."""
+    d = SftDesc()
+    lib().radar_sft_default(ctypes.byref(d), int(k))
+    if dirs is not None:
+        if not 1 <= len(dirs) <= 16:
+            raise ValueError("1 to 16 directions")
+        d.n_dirs = len(dirs)
+        for i, (a, b) in enumerate(dirs):
+            d.dirs[i][0] = int(a)
+            d.dirs[i][1] = int(b)
+    if pfa is not None:
+        d.pfa = float(pfa)
+    if tol is not None:
+        d.tol = float(tol)
+    return d
+
+
+def fps_sft(Y: torch.Tensor, A: torch.Tensor, cfg: Config, sft: SftDesc, *, slices: bool = False,
+            workspace: torch.Tensor | None = None, stream=None):
+    """radar_fps_sft on F frames: returns (peaks, n_peaks, status[, slice spectra (F, I, 3, Q)])."""
+    L = lib()
+    Y = _as_frames(Y, cfg, "Y")
+    A = _as_frames(A, cfg, "A")
+    if Y.stride() != A.stride() or Y.shape != A.shape:
+        raise ValueError("Y and A must share shape and strides")
+    F = Y.shape[0]
+    dev = Y.device
+    desc = cfg.desc(ld=Y.stride(1))
+    desc.flags = 0
+    peaks = alloc_peaks(F, sft.k, dev)
+    n_peaks = torch.zeros(F, dtype=torch.int32, device=dev)
+    status = torch.zeros(F, dtype=torch.int32, device=dev)
+    S = None
+    ws_ptr, ws_bytes = None, 0
+    if slices:
+        q = max(cfg.n_sub, cfg.n_sym)
+        S = torch.empty((F, sft.n_dirs, 3, q), dtype=torch.complex64, device=dev)
+    else:
+        need = L.radar_fps_sft_workspace_size(ctypes.byref(desc), ctypes.byref(sft), F)
+        if need == 0:
+            raise RadarError(RADAR_E_ARG, "radar_fps_sft_workspace_size")
+        if workspace is None or workspace.numel() < need:
+            workspace = new_workspace(need, dev)
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel()
+    rc = L.radar_fps_sft(ctypes.byref(desc), ctypes.byref(sft), F, Y.data_ptr(), A.data_ptr(), _frame_stride(Y),
+                         peaks.data_ptr(), n_peaks.data_ptr(), status.data_ptr(),
+                         None if S is None else S.data_ptr(), ws_ptr, ws_bytes, _stream_ptr(stream))
+    _check(rc, "radar_fps_sft")
+    if slices:
+        return peaks, n_peaks, status, S
+    return peaks, n_peaks, status
 
 
 def timing_start(max_launches: int):

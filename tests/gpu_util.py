@@ -57,3 +57,29 @@ def compare_peak_indices(gpu, ref, P_ref):
             continue
         return None
     return excluded
+
+
+def check_topk_property(P, peaks, k):
+    """The reported peaks are exactly the top-k 3x3 cyclic local maxima of P.
+
+    Written from the definition (a cell >= its 8 cyclic neighbours; rank by
+    value descending, flat index ascending), independently of the oracle's
+    peak finder.  P: float32 [M'][N'] (row s + M'/2 holds Doppler s);
+    peaks: [(s, r, p, ...)].  Returns an error string, or None.
+    """
+    P = np.asarray(P, dtype=np.float32)
+    m_pad, n_pad = P.shape
+    is_max = np.ones(P.shape, dtype=bool)
+    for di in (-1, 0, 1):
+        for dj in (-1, 0, 1):
+            if di or dj:
+                is_max &= P >= np.roll(np.roll(P, di, axis=0), dj, axis=1)
+    rows, cols = np.nonzero(is_max)
+    vals = P[rows, cols]
+    flat = rows.astype(np.int64) * n_pad + cols
+    order = np.lexsort((flat, -vals.astype(np.float64)))[:k]
+    want = [(int(rows[i]) - m_pad // 2, int(cols[i]), float(vals[i])) for i in order]
+    got = [(int(s), int(r), float(np.float32(p))) for s, r, p, *_ in peaks]
+    if got != want:
+        return f"top-{k} mismatch: got {got[:4]}..., want {want[:4]}..."
+    return None

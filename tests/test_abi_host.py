@@ -124,3 +124,63 @@ def test_flags_validation():
     assert need > 0
     # the periodogram entry finds no peaks: the refine flag is an argument error
     assert L.radar_periodogram(ctypes.byref(ok.desc()), 1, 256, 0, 256, 0, 256, need, None) == radar.RADAR_E_ARG
+
+
+def test_sft_default_settings():
+    d = radar.sft_desc(8)
+    assert (d.n_dirs, d.k, d.flags) == (8, 8, 0)
+    assert [tuple(d.dirs[i]) for i in range(8)] == [(1, 1), (1, -1), (1, 2), (2, 1), (1, -2), (2, -1), (1, 0), (0, 1)]
+    assert d.pfa == pytest.approx(1e-2) and d.tol == pytest.approx(0.25)
+
+
+def test_sft_workspace_size():
+    L = radar.lib()
+    cfg = radar.Config(1024, 256, 1024, 256, 1024, zc_root=7)
+    s = radar.sft_desc(8)
+    assert L.radar_fps_sft_workspace_size(ctypes.byref(cfg.desc()), ctypes.byref(s), 3) == _al(3 * 8 * 3 * 1024 * 8)
+    s2 = radar.sft_desc(4, dirs=[(1, 1), (3, -5)])
+    assert L.radar_fps_sft_workspace_size(ctypes.byref(cfg.desc()), ctypes.byref(s2), 1) == _al(2 * 3 * 1024 * 8)
+
+
+@pytest.mark.parametrize("change,code", [
+    (dict(k=0), radar.RADAR_E_ARG), (dict(k=65), radar.RADAR_E_ARG),
+    (dict(n_dirs=0), radar.RADAR_E_ARG), (dict(n_dirs=17), radar.RADAR_E_ARG),
+    (dict(pfa=0.0), radar.RADAR_E_ARG), (dict(pfa=1.0), radar.RADAR_E_ARG),
+    (dict(tol=0.0), radar.RADAR_E_ARG), (dict(flags=1), radar.RADAR_E_ARG),
+    (dict(dir0=(0, 0)), radar.RADAR_E_ARG), (dict(dir0=(256, -64)), radar.RADAR_E_ARG),  # both vanish mod (N, M)
+    (dict(n_sub=8), radar.RADAR_E_UNSUPPORTED), (dict(n_sym=8192), radar.RADAR_E_UNSUPPORTED),
+    (dict(n_sub=96), radar.RADAR_E_UNSUPPORTED), (dict(zc_root=4), radar.RADAR_E_NOT_COPRIME),
+    (dict(refine=True), radar.RADAR_E_ARG),
+])
+def test_sft_validation_rejects(change, code):
+    base = dict(n_sub=256, n_sym=64, n_pad=256, m_pad=64, n_cp=256, zc_root=1)
+    for key in ("n_sub", "n_sym", "zc_root", "refine"):
+        if key in change:
+            base[key] = change[key]
+    cfg = radar.Config(**base)
+    s = radar.sft_desc(4)
+    for key in ("k", "n_dirs", "pfa", "tol", "flags"):
+        if key in change:
+            setattr(s, key, change[key])
+    if "dir0" in change:
+        s.dirs[0][0], s.dirs[0][1] = change["dir0"]
+    L = radar.lib()
+    assert L.radar_fps_sft_workspace_size(ctypes.byref(cfg.desc()), ctypes.byref(s), 1) == 0
+    # validation happens before any HIP call: dummy non-null pointers are never touched
+    p = 256
+    assert L.radar_fps_sft(ctypes.byref(cfg.desc()), ctypes.byref(s), 1, p, p, 0, p, p, p, None, p, 1 << 40,
+                           None) == code
+
+
+def test_sft_rejects_pointers_and_workspace():
+    L = radar.lib()
+    cfg = radar.Config(256, 64, 256, 64, 256, zc_root=1)
+    s = radar.sft_desc(4)
+    d, sp = ctypes.byref(cfg.desc()), ctypes.byref(s)
+    need = L.radar_fps_sft_workspace_size(d, sp, 2)
+    p = 256
+    assert L.radar_fps_sft(d, sp, 2, p, p, 256 * 64, p, p, p, None, p, need - 1, None) == radar.RADAR_E_WORKSPACE
+    assert L.radar_fps_sft(d, sp, 2, p, p, 256 * 64, p, p, p, None, None, need, None) == radar.RADAR_E_ARG
+    assert L.radar_fps_sft(d, sp, 2, None, p, 256 * 64, p, p, p, None, p, need, None) == radar.RADAR_E_ARG
+    assert L.radar_fps_sft(d, sp, 2, p, p, 100, p, p, p, None, p, need, None) == radar.RADAR_E_ARG  # overlap
+    assert L.radar_fps_sft(d, sp, 0, p, p, 0, p, p, p, None, p, need, None) == radar.RADAR_E_ARG

@@ -1,0 +1,175 @@
+"""GPU parity of FPS-SFT (radar_fps_sft) against the FP64 oracle, through the C ABI.
+
+The slice spectra are compared by tolerance.  The recovered components are
+integer decisions taken from those spectra (threshold, ratio tests, rounding
+of phases, bin order), so they are compared exactly wherever the oracle's own
+decisions are stable: the oracle's recovery is re-run on its spectra
+perturbed by a multiple of the FP32 error, and a frame whose decisions move
+under that perturbation is reported as near-boundary instead of compared.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import radar_oracle as O
+from synth import frames as S
+from tests.gpu_util import rounded, say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+radar = pytest.importorskip("paper_2209_03883_amd.radar")
+
+# Slice spectra: max |S_gpu - S_ref| / max |S_ref| per frame.  Q-point FP32
+# FFTs of FP32 quotients: about 1e-7 * log2(Q) normwise.
+SLICE_TOL = 1e-5
+# Perturbation used to probe the stability of the oracle's decisions: the
+# slice tolerance (100x the observed FP32 error), relative to each slice's
+# largest magnitude.
+PERTURB = 1e-5
+# Component power p = |c|^2/(NM) of matching detections.
+P_RTOL = 1e-3
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    radar.lib()
+
+
+def _cfg(n, m, zc_root):
+    return radar.Config(n, m, n, m, n, zc_root=zc_root)
+
+
+def _run(Ys, As, cfg, sft, ld=None):
+    Y = np.stack(Ys).astype(np.complex64)
+    A = np.stack(As).astype(np.complex64)
+    if ld is not None:
+        Yp = np.zeros(Y.shape[:2] + (ld,), np.complex64)
+        Ap = np.ones(Y.shape[:2] + (ld,), np.complex64)
+        Yp[:, :, :Y.shape[2]] = Y
+        Ap[:, :, :A.shape[2]] = A
+        Yd = torch.from_numpy(Yp).cuda()[:, :, :Y.shape[2]]
+        Ad = torch.from_numpy(Ap).cuda()[:, :, :A.shape[2]]
+    else:
+        Yd = torch.from_numpy(Y).cuda()
+        Ad = torch.from_numpy(A).cuda()
+    peaks, n_peaks, status, Sg = radar.fps_sft(Yd, Ad, cfg, sft, slices=True)
+    torch.cuda.synchronize()
+    return radar.unpack_peaks(peaks, n_peaks.cpu()), status.cpu().numpy(), Sg.cpu().numpy()
+
+
+def _oracle_slices(Y, A, zc_root, dirs):
+    n = Y.shape[1]
+    z = None if zc_root is None else O.zc_sequence(n, zc_root)
+    return O.sft_slices(O.ls_estimate(rounded(Y), rounded(A), z), dirs)
+
+
+def _decode(Sx, n, m, dirs, k, pfa, tol):
+    return O.sft_to_peaks(O.sft_decode(Sx, n, m, dirs, k, pfa, tol), n, m)
+
+
+def _stable(Sx, n, m, dirs, k, pfa, tol, ref, seed):
+    rng = np.random.default_rng(seed)
+    amp = PERTURB * np.max(np.abs(Sx), axis=2, keepdims=True)
+    cells = sorted((s, r) for s, r, _ in ref)
+    for _ in range(3):
+        noise = (rng.standard_normal(Sx.shape) + 1j * rng.standard_normal(Sx.shape)) * amp / np.sqrt(2.0)
+        if sorted((s, r) for s, r, _ in _decode(Sx + noise, n, m, dirs, k, pfa, tol)) != cells:
+            return False
+    return True
+
+
+def _compare(frames_Y, frames_A, n, m, zc_root, sft, label, ld=None, require_stable=True):
+    dirs = [tuple(sft.dirs[i]) for i in range(sft.n_dirs)]
+    pk, st, Sg = _run(frames_Y, frames_A, _cfg(n, m, zc_root), sft, ld=ld)
+    assert np.all(st == 0), st
+    unstable = 0
+    for f, (Y, A) in enumerate(zip(frames_Y, frames_A)):
+        Sx = _oracle_slices(Y, A, zc_root, dirs)
+        err = float(np.max(np.abs(Sg[f] - Sx)) / np.max(np.abs(Sx)))
+        assert err <= SLICE_TOL, (label, f, err)
+        ref = _decode(Sx, n, m, dirs, sft.k, sft.pfa, sft.tol)
+        got = pk[f]
+        # the GPU's own ranking is by its p, descending
+        assert all(a[2] >= b[2] for a, b in zip(got, got[1:])), (label, got)
+        if not _stable(Sx, n, m, dirs, sft.k, sft.pfa, sft.tol, ref, seed=f):
+            unstable += 1
+            say(f"{label}/{f}: slice error {err:.2e}, oracle decisions near a boundary: not compared")
+            continue
+        assert sorted((s, r) for s, r, *_ in got) == sorted((s, r) for s, r, _ in ref), (label, f, got, ref)
+        want = {(s, r): p for s, r, p in ref}
+        for s, r, p, so, ro in got:
+            assert p == pytest.approx(want[(s, r)], rel=P_RTOL), (label, f, s, r)
+            assert so == 0.0 and ro == 0.0
+        say(f"{label}/{f}: slice error {err:.2e}, {len(got)} components identical")
+    if require_stable:
+        assert unstable == 0, label
+    return pk, unstable
+
+
+@pytest.mark.parametrize("n,m,nt,seed", [(256, 64, 3, 0), (1024, 1024, 8, 0), (64, 256, 5, 1), (16, 16, 2, 0),
+                                         (4096, 32, 6, 2), (32, 4096, 6, 0), (128, 128, 12, 0)])
+def test_sft_noiseless_sparse_frames_exact(n, m, nt, seed):
+    spec = S.FrameSpec(n_sub=n, n_sym=m, qam=16, zc_root=3, n_targets=nt, noise=False, on_grid=True, rho_min=0,
+                       rho_max=max(1, n // 4), nu_abs_max=m // 2 - 1, min_sep=1.0)
+    f = S.make_frame(spec, 95, n * 10 + seed)
+    say(f"sft noiseless {n}x{m} K={nt}")
+    pk, _ = _compare([f.Y], [f.A], n, m, 3, radar.sft_desc(nt), f"noiseless-{n}x{m}")
+    assert sorted((s, r) for s, r, *_ in pk[0]) == sorted((int(v), int(r)) for r, v in zip(f.rho, f.nu))
+    np.testing.assert_allclose(sorted(p for _, _, p, _, _ in pk[0]), sorted(n * m * np.abs(f.b) ** 2), rtol=1e-4)
+
+
+def test_sft_small_workload_batch():
+    frames = [S.make_frame(S.spec_small(snr_db=0.0), 1, i) for i in range(6)]
+    say("sft small workload, 6 frames")
+    pk, _ = _compare([f.Y for f in frames], [f.A for f in frames], 256, 64, 1, radar.sft_desc(3), "small")
+    # batching does not change a frame's result
+    pk1, _, _ = _run([frames[4].Y], [frames[4].A], _cfg(256, 64, 1), radar.sft_desc(3))
+    assert pk1[0] == pk[4]
+
+
+@pytest.mark.parametrize("snr_db", [0.0, 10.0])
+def test_sft_full_frames(snr_db):
+    frames = [S.make_frame(S.spec_full(snr_db=snr_db), 2, 60 + i) for i in range(4)]
+    say(f"sft full frames snr {snr_db}")
+    _, unstable = _compare([f.Y for f in frames], [f.A for f in frames], 1024, 1024, 7, radar.sft_desc(8),
+                           f"full-{snr_db}", require_stable=False)
+    assert unstable <= 1
+
+
+def test_sft_high_snr_matches_periodogram_cells():
+    spec = S.FrameSpec(n_sub=256, n_sym=64, qam=16, zc_root=1, n_targets=5, snr_db=20.0, on_grid=True,
+                       rho_min=1, rho_max=60, nu_abs_max=31, min_sep=2.0)
+    frames = [S.make_frame(spec, 96, i) for i in (0, 1, 2, 5)]
+    say("sft 20 dB vs periodogram")
+    pk, _ = _compare([f.Y for f in frames], [f.A for f in frames], 256, 64, 1, radar.sft_desc(5), "20dB")
+    for f, got in zip(frames, pk):
+        assert sorted((s, r) for s, r, *_ in got) == sorted(zip(f.nu.astype(int), f.rho.astype(int)))
+
+
+@pytest.mark.parametrize("dirs,k", [([(3, -5)], 1), ([(-1, 7), (5, 2), (1, 0)], 2), ([(1, 1)] * 16, 4)])
+def test_sft_custom_directions(dirs, k):
+    spec = S.FrameSpec(n_sub=128, n_sym=64, qam=4, zc_root=None, n_targets=2, snr_db=15.0, on_grid=True,
+                       rho_min=1, rho_max=40, nu_abs_max=30, min_sep=3.0)
+    f = S.make_frame(spec, 97, len(dirs))
+    say(f"sft directions {dirs[:3]} k={k}")
+    _compare([f.Y], [f.A], 128, 64, None, radar.sft_desc(k, dirs=dirs), f"dirs-{len(dirs)}")
+
+
+def test_sft_strided_input():
+    spec = S.FrameSpec(n_sub=256, n_sym=128, qam=16, zc_root=5, n_targets=3, snr_db=10.0, on_grid=True,
+                       rho_min=1, rho_max=60, nu_abs_max=60)
+    frames = [S.make_frame(spec, 98, i) for i in range(2)]
+    say("sft strided ld")
+    _compare([f.Y for f in frames], [f.A for f in frames], 256, 128, 5, radar.sft_desc(3), "strided", ld=300)
+
+
+def test_sft_status_bit_for_zero_symbol():
+    f = S.make_frame(S.spec_small(snr_db=0.0), 1, 0)
+    A = f.A.copy()
+    A[0, 0] = 0.0  # on the (1, 1) slice at offset (0, 0), t = 0
+    say("sft status bits")
+    _, st, _ = _run([f.Y], [A], _cfg(256, 64, 1), radar.sft_desc(3))
+    assert st[0] & radar.ST_ZERO_SYMBOL
