@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--frames", type=int, default=32, help="frames per step")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="CPU work budget for the oracle baseline (0 disables it)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the refinement and FPS-SFT timings reported beside the headline figure")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 3 plain device copies of MIB MiB (calibrates HBM byte counters) and exit")
     return ap.parse_args()
@@ -56,10 +58,15 @@ def copy_calibration(mib):
     print(json.dumps({"copy_calibration_mib": mib, "bytes_per_copy_each_way": n * 4}))
 
 
+# sources the range kernel is compiled from: a committed counter summary is
+# valid while these are unchanged
+K3_SOURCES = ("device_common.hpp", "fft.hpp", "k_frame.hpp")
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2209_03883_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in K3_SOURCES:
         with open(os.path.join(csrc, name), "rb") as fh:
             h.update(name.encode())
             h.update(fh.read())
@@ -100,6 +107,48 @@ def cpu_baseline(frames, budget_s):
     del np
     return {"value": done / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
             "sample": f"{done} whole {N}x{M} frames (FP64 numpy, single thread), {dt:.1f} s"}
+
+
+def time_extras(radar, torch, Yd, Ad, cfg, ws, peaks, n_peaks, status, stream, B, steps, warmup):
+    """Two figures beside the headline: the same step with sub-cell refinement
+    of the k peaks, and FPS-SFT (eight directions, K = 8) on the same frames."""
+    import dataclasses
+
+    out = {}
+    cfg_r = dataclasses.replace(cfg, refine=True)
+    P = torch.empty((B, cfg.m_pad, cfg.n_pad), dtype=torch.float32, device=Yd.device)
+    for _ in range(warmup):
+        radar.frame_process(Yd, Ad, cfg_r, K, P=P, workspace=ws, peaks=peaks, n_peaks=n_peaks, status=status,
+                            stream=stream)
+    radar.timing_start(steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        radar.frame_process(Yd, Ad, cfg_r, K, P=P, workspace=ws, peaks=peaks, n_peaks=n_peaks, status=status,
+                            stream=stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = radar.timing_stop()
+    out["with_refinement_frames_per_s"] = B * steps / dt
+    out["refine_us_per_frame"] = st["refine"][0] / max(st["refine"][1], 1) * 1e3 / B
+    del P
+
+    sft = radar.sft_desc(K)
+    ws_sft = radar.new_workspace(radar.sft_workspace_bytes(cfg, sft, B), Yd.device)
+    for _ in range(warmup):
+        radar.fps_sft(Yd, Ad, cfg, sft, workspace=ws_sft, stream=stream)
+    radar.timing_start(steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        radar.fps_sft(Yd, Ad, cfg, sft, workspace=ws_sft, stream=stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = radar.timing_stop()
+    out["fps_sft_frames_per_s"] = B * steps / dt
+    out["fps_sft_us_per_frame"] = {k: st[k][0] / max(st[k][1], 1) * 1e3 / B for k in ("sft_slices", "sft_decode")}
+    print(f"[bench] extras {out}", file=sys.stderr, flush=True)
+    return out
 
 
 def main():
@@ -156,6 +205,9 @@ def main():
     stages = radar.timing_stop()
     print(f"[bench] timed {args.steps} steps in {dt:.3f} s; stages {stages}", file=sys.stderr, flush=True)
 
+    extras = {} if args.no_extras else time_extras(radar, torch, Yd, Ad, cfg, ws, peaks, n_peaks, status, stream,
+                                                   B, args.steps, args.warmup)
+
     frames_done = B * args.steps
     fps = frames_done / dt
     rng_ms, rng_n = stages["range"]
@@ -186,7 +238,8 @@ def main():
             "frames_per_step": B,
             "periodogram_materialised": True,
             "hbm_roofline_frames_per_s": HBM_PEAK_GBS * 1e9 / (16 * N * M + 4 * PAD * N * PAD * M),
-            "stage_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
+            "stage_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in stages.items() if v[1]},
+            **extras,
         },
         "roofline": {
             "kernel": "k3_range_power",

@@ -280,6 +280,15 @@ def sft_desc(k: int, dirs=None, pfa: float | None = None, tol: float | None = No
     return d
 
 
+def sft_workspace_bytes(cfg: Config, sft: SftDesc, n_frames: int) -> int:
+    desc = cfg.desc()
+    desc.flags = 0
+    n = lib().radar_fps_sft_workspace_size(ctypes.byref(desc), ctypes.byref(sft), int(n_frames))
+    if n == 0:
+        raise RadarError(RADAR_E_ARG, "radar_fps_sft_workspace_size")
+    return int(n)
+
+
 def fps_sft(Y: torch.Tensor, A: torch.Tensor, cfg: Config, sft: SftDesc, *, slices: bool = False,
             workspace: torch.Tensor | None = None, stream=None):
     """radar_fps_sft on F frames: returns (peaks, n_peaks, status[, slice spectra (F, I, 3, Q)])."""
@@ -301,9 +310,7 @@ def fps_sft(Y: torch.Tensor, A: torch.Tensor, cfg: Config, sft: SftDesc, *, slic
         q = max(cfg.n_sub, cfg.n_sym)
         S = torch.empty((F, sft.n_dirs, 3, q), dtype=torch.complex64, device=dev)
     else:
-        need = L.radar_fps_sft_workspace_size(ctypes.byref(desc), ctypes.byref(sft), F)
-        if need == 0:
-            raise RadarError(RADAR_E_ARG, "radar_fps_sft_workspace_size")
+        need = sft_workspace_bytes(cfg, sft, F)
         if workspace is None or workspace.numel() < need:
             workspace = new_workspace(need, dev)
         ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel()
