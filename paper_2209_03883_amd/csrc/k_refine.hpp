@@ -43,6 +43,7 @@ __device__ __forceinline__ double2 dirichlet(double x, int N) {
 __global__ void __launch_bounds__(kRefineThreads) k7_refine(K7Args a) {
   __shared__ float2 s_part[kRefineLSplit][7][kRefineNChunk];  // partial Doppler sums
   __shared__ double2 s_v[7][kRefineNChunk];
+  __shared__ double2 s_D[7][kRefineNChunk + 2];  // D(rho_y - n) for n = n0 - 1 .. n0 + chunk
   __shared__ double2 s_g[7][7];  // holds P[7][7] (as doubles) for the fit
   __shared__ double2 s_red[16][7 * 7];
   const int f = blockIdx.y;
@@ -91,6 +92,11 @@ __global__ void __launch_bounds__(kRefineThreads) k7_refine(K7Args a) {
         s_v[x][tid] = make_double2((double)v.x, (double)v.y);
       }
     }
+    // the Dirichlet kernel at every (fine range position, tap) pair of the chunk
+    for (int i = tid; i < 7 * (kRefineNChunk + 2); i += kRefineThreads) {
+      const int y = i / (kRefineNChunk + 2), j = i - y * (kRefineNChunk + 2);
+      s_D[y][j] = dirichlet((double)(cr + y - 3 - 16 * (n0 - 1 + j)) / 16.0, a.N);
+    }
     __syncthreads();
     // range sums: thread (x, y, n-slice) accumulates sum_n V_x[n] K(rho_y - n)
     if (tid < 7 * 7 * 16) {
@@ -98,10 +104,9 @@ __global__ void __launch_bounds__(kRefineThreads) k7_refine(K7Args a) {
       const int x = xy / 7, y = xy % 7;
       double2 g = make_double2(0.0, 0.0);
       for (int nn = slice; nn < kRefineNChunk && n0 + nn < a.n_cp; nn += 16) {
-        const double xr = (double)(cr + y - 3 - 16 * (n0 + nn)) / 16.0;
-        const double2 d0 = dirichlet(xr, a.N);
-        const double2 dp = dirichlet(xr + 1.0, a.N);
-        const double2 dm = dirichlet(xr - 1.0, a.N);
+        const double2 d0 = s_D[y][nn + 1];  // D(rho_y - n)
+        const double2 dp = s_D[y][nn];      // D(rho_y - n + 1)
+        const double2 dm = s_D[y][nn + 2];  // D(rho_y - n - 1)
         const double kr = (double)wc.x * d0.x - 0.5 * (double)wc.y * (dp.x + dm.x);
         const double ki = (double)wc.x * d0.y - 0.5 * (double)wc.y * (dp.y + dm.y);
         const double2 v = s_v[x][nn];
