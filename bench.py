@@ -110,8 +110,9 @@ def cpu_baseline(frames, budget_s):
 
 
 def time_extras(radar, torch, Yd, Ad, cfg, ws, peaks, n_peaks, status, stream, B, steps, warmup):
-    """Two figures beside the headline: the same step with sub-cell refinement
-    of the k peaks, and FPS-SFT (eight directions, K = 8) on the same frames."""
+    """Figures beside the headline: the same step with sub-cell refinement of
+    the k peaks, the same step in the BF16x3 and FP16x3 matrix-core forms, and
+    FPS-SFT (eight directions, K = 8) on the same frames."""
     import dataclasses
 
     out = {}
@@ -132,6 +133,27 @@ def time_extras(radar, torch, Yd, Ad, cfg, ws, peaks, n_peaks, status, stream, B
     out["with_refinement_frames_per_s"] = B * steps / dt
     out["refine_us_per_frame"] = st["refine"][0] / max(st["refine"][1], 1) * 1e3 / B
     del P
+
+    # the matrix-core precision forms of the Doppler and range FFTs, same step
+    for name, flag in (("bf16x3", radar.FLAG_BF16X3), ("fp16x3", radar.FLAG_FP16X3)):
+        cfg_p = dataclasses.replace(cfg, precision=flag)
+        P = torch.empty((B, cfg.m_pad, cfg.n_pad), dtype=torch.float32, device=Yd.device)
+        for _ in range(warmup):
+            radar.frame_process(Yd, Ad, cfg_p, K, P=P, workspace=ws, peaks=peaks, n_peaks=n_peaks, status=status,
+                                stream=stream)
+        radar.timing_start(steps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            radar.frame_process(Yd, Ad, cfg_p, K, P=P, workspace=ws, peaks=peaks, n_peaks=n_peaks, status=status,
+                                stream=stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = radar.timing_stop()
+        out[f"{name}_frames_per_s"] = B * steps / dt
+        out[f"{name}_stage_us_per_frame"] = {k: st[k][0] / max(st[k][1], 1) * 1e3 / B
+                                             for k in ("taps", "doppler", "range", "peaks")}
+        del P
 
     sft = radar.sft_desc(K)
     ws_sft = radar.new_workspace(radar.sft_workspace_bytes(cfg, sft, B), Yd.device)

@@ -66,7 +66,12 @@ enum {
 enum { RADAR_WIN_RECT = 0, RADAR_WIN_HANN = 1, RADAR_WIN_HAMMING = 2 };  /* periodic windows */
 enum { RADAR_ZC_NONE = 0, RADAR_ZC_DIAG = 1 };  /* ZC precoding along the subcarriers */
 enum { RADAR_ST_ZERO_SYMBOL = 1u, RADAR_ST_NONFINITE = 2u };
-enum { RADAR_FLAG_REFINE = 1 };  /* radar_frame_desc.flags */
+/* radar_frame_desc.flags */
+enum {
+  RADAR_FLAG_REFINE = 1,   /* sub-cell refinement of the peaks (radar_frame_process) */
+  RADAR_FLAG_BF16X3 = 2,   /* Doppler and range FFTs' radix-16 stages on BF16 matrix cores, split operands */
+  RADAR_FLAG_FP16X3 = 4    /* the same with FP16 operands and per-column power-of-two scaling */
+};
 
 /* One frame shape.  Names follow the paper: N subcarriers, M OFDM symbols,
  * N' >= N and M' >= M the zero-padded periodogram sizes of Eq. 17, N_cp the
@@ -124,6 +129,13 @@ int radar_init(void);
  *   neighbourhood is solved in FP64 (separable parabolas when that quadratic
  *   has no maximum within one cell); offsets are clamped to half a fine cell
  *   about the best fine cell.  Needs M'/M <= 16, N'/N <= 16 and M <= 1024.
+ *   With RADAR_FLAG_BF16X3 or RADAR_FLAG_FP16X3 (at most one) the radix-16
+ *   stages of the Doppler FFT and of the range IFFTs run as 16-point DFTs by
+ *   matrix product on the matrix cores: data and DFT matrix are each split
+ *   into two half-precision parts (v = hi + lo, hi = rn(v), lo = rn(v - hi)),
+ *   the products hi*hi, hi*lo and lo*hi accumulate in FP32; twiddles, windows,
+ *   the taps stage and |.|^2 stay FP32.  These forms exist for N' = 4N,
+ *   4 N_cp <= N, N >= 256 (RADAR_E_UNSUPPORTED otherwise).
  * Y, A:     input frames, frame f at Y + f*frame_stride (elements).
  * P:        output, frame f at P + f*p_frame_stride (floats); must not be NULL;
  *           p_frame_stride >= M'*N' and a multiple of 4; P 16-byte aligned.
@@ -144,8 +156,8 @@ int radar_frame_process(const radar_frame_desc *d, int32_t n_frames,
  *
  * H is an LS estimate (Eq. 16) laid out like Y.  If d->n_cp < N the DFT-CE of
  * Eq. 20-22 is applied first; d->zc_mode must be RADAR_ZC_NONE (H is already
- * de-precoded) and d->flags must be 0 (no peaks, so nothing to refine:
- * RADAR_E_ARG otherwise).  P as for radar_frame_process.  The workspace size is
+ * de-precoded) and d->flags must not hold RADAR_FLAG_REFINE (no peaks, so
+ * nothing to refine: RADAR_E_ARG otherwise); the precision flags apply.  P as for radar_frame_process.  The workspace size is
  * radar_frame_workspace_size(d, n_frames, 1).
  * ------------------------------------------------------------------------ */
 int radar_periodogram(const radar_frame_desc *d, int32_t n_frames,

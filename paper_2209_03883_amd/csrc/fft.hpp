@@ -99,6 +99,18 @@ struct Dft {
   }
 };
 
+// The FP32 in-register DFT of a Stockham stage (the plain form); other
+// policies (the matrix-core form) provide the same run<R, INV>().  A policy
+// with kWave = true must be called by every lane of the wavefront.
+struct DftFp32 {
+  static constexpr bool kWave = false;
+  __device__ __forceinline__ void init() {}
+  template <int R, bool INV>
+  __device__ __forceinline__ void run(float2* x) const {
+    Dft<R, INV>::run(x);
+  }
+};
+
 // LDS index with one pad slot every 16 entries (limits bank conflicts of the
 // strided Stockham writes).
 __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
@@ -179,13 +191,15 @@ __device__ __forceinline__ void load_stage_tw(StageTw<L, E, NS>& tw, int t, bool
 // remainder as the last stage.  `tw` holds this stage's twiddles; the next
 // stage's are fetched before the LDS exchange so their latency overlaps it.
 // `active` = false skips arithmetic and LDS traffic but keeps the barriers.
-template <int L, int E, int NS, bool INV, class TS>
+template <int L, int E, int NS, bool INV, class TS, class DF>
 __device__ __forceinline__ void fft_stages_tw(float2 (&v)[E], float2* lds, int t, bool active,
-                                              const StageTw<L, E, NS>& tw, const TS& ts) {
+                                              const StageTw<L, E, NS>& tw, const TS& ts, const DF& df) {
   using P = StagePlan<L, E, NS>;
   constexpr int T = P::T, R = P::R, NB = P::NB;
+  // a wave-wide DFT runs on every lane (inactive lanes transform garbage and store nothing)
+  constexpr bool kAll = DF::kWave && R == 16;
   if constexpr (L / NS > 1) {
-    if (active) {
+    if (active || kAll) {
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         float2 x[R];
@@ -200,11 +214,11 @@ __device__ __forceinline__ void fft_stages_tw(float2 (&v)[E], float2* lds, int t
             x[m] = INV ? cmulc(x[m], w) : cmul(x[m], w);
           }
         }
-        Dft<R, INV>::run(x);
+        df.template run<R, INV>(x);
         if constexpr (P::LAST) {
 #pragma unroll
           for (int m = 0; m < R; ++m) v[b + m * NB] = x[m];
-        } else {
+        } else if (active) {
           const int base = (j - k) * R + k;
 #pragma unroll
           for (int m = 0; m < R; ++m) lds[lds_pad(base + m * NS)] = x[m];
@@ -226,26 +240,28 @@ __device__ __forceinline__ void fft_stages_tw(float2 (&v)[E], float2* lds, int t
         // serves them in order)
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       }
-      fft_stages_tw<L, E, NS * R, INV>(v, lds, t, active, next, ts);
+      fft_stages_tw<L, E, NS * R, INV>(v, lds, t, active, next, ts, df);
     }
   }
 }
 
-template <int L, int E, int NS, bool INV, class TS = TwGlobal>
-__device__ __forceinline__ void fft_stages(float2 (&v)[E], float2* lds, int t, bool active, const TS& ts = TS{}) {
+template <int L, int E, int NS, bool INV, class TS = TwGlobal, class DF = DftFp32>
+__device__ __forceinline__ void fft_stages(float2 (&v)[E], float2* lds, int t, bool active, const TS& ts = TS{},
+                                           const DF& df = DF{}) {
   StageTw<L, E, NS> tw;
   load_stage_tw<L, E, NS>(tw, t, active, ts);
-  fft_stages_tw<L, E, NS, INV>(v, lds, t, active, tw, ts);
+  fft_stages_tw<L, E, NS, INV>(v, lds, t, active, tw, ts, df);
 }
 
 // Full L-point transform of the team's data (cyclic layout in and out).
 // Every thread of the work-group must call it when teams span several waves
 // (it then contains work-group barriers).
-template <int L, int E, bool INV>
-__device__ __forceinline__ void team_fft(float2 (&v)[E], float2* lds, int t, bool active = true) {
+template <int L, int E, bool INV, class DF = DftFp32>
+__device__ __forceinline__ void team_fft(float2 (&v)[E], float2* lds, int t, bool active = true,
+                                         const DF& df = DF{}) {
   static_assert(L >= E && (L & (L - 1)) == 0, "FFT length");
   static_assert(E == 4 || E == 8 || E == 16, "elements per thread");
-  fft_stages<L, E, 1, INV>(v, lds, t, active);
+  fft_stages<L, E, 1, INV>(v, lds, t, active, TwGlobal{}, df);
 }
 
 // Twiddle blocks of one FFT plan (the stages of team_fft from span NS0 on,

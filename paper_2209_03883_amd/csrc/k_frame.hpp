@@ -12,6 +12,7 @@
 #pragma once
 
 #include "fft.hpp"
+#include "mfma_dft.hpp"
 
 namespace radar {
 
@@ -224,9 +225,11 @@ struct K2Tile {
   static constexpr int SH = TW * EXCH > M * LD ? TW * EXCH : M * LD;
 };
 
-template <int M, int TW>
+template <int M, int TW, Prec PR = Prec::FP32>
 __global__ void __launch_bounds__((K2Tile<M, TW>::BLOCK)) k2_doppler_tiled(K2Args a) {
   using C = K2Tile<M, TW>;
+  typename DftFor<PR>::type df;
+  df.init();
   constexpr int T = C::T, BLOCK = C::BLOCK, LD = C::LD;
   __shared__ float2 sh[C::SH];
   const int team = threadIdx.x / T;
@@ -255,7 +258,7 @@ __global__ void __launch_bounds__((K2Tile<M, TW>::BLOCK)) k2_doppler_tiled(K2Arg
     }
   }
   __syncthreads();  // the tile is reused as exchange space
-  team_fft<M, 16, false>(v, sh + team * C::EXCH, t);
+  team_fft<M, 16, false>(v, sh + team * C::EXCH, t, true, df);
   __syncthreads();  // every team is done with its exchange region
 #pragma unroll
   for (int e = 0; e < 16; ++e) sh[(t + T * e) * LD + team] = v[e];
@@ -365,9 +368,11 @@ struct K3x4 {
   static constexpr int UBUF = N / 4 + 3;              // u[-1 .. N/4+1]
 };
 
-template <int N>
+template <int N, Prec PR = Prec::FP32>
 __global__ void __launch_bounds__(K3x4<N>::BLOCK) k3_range_power_x4(K3Args a) {
   using C = K3x4<N>;
+  typename DftFor<PR>::type df;
+  df.init();
   constexpr int T = C::T;
   constexpr int Q = N / 4;
   __shared__ float2 s_main[C::ROWS][C::MAIN];
@@ -418,7 +423,7 @@ __global__ void __launch_bounds__(K3x4<N>::BLOCK) k3_range_power_x4(K3Args a) {
     }
   }
   __syncthreads();  // X consumed before the exchange regions overwrite it
-  team_fft<N, 16, true>(gv, main + team * C::EXCH, t, fft_team);
+  team_fft<N, 16, true>(gv, main + team * C::EXCH, t, fft_team, df);
   float p[16];
   if (fft_team) {
 #pragma unroll
@@ -502,9 +507,11 @@ struct K3p {
   using Inv = PlanLayout<N, INV, 1>;
 };
 
-template <int N>
+template <int N, Prec PR = Prec::FP32>
 __global__ void __launch_bounds__(K3p<N>::BLOCK) k3_range_power_x4p(K3Args a, int total_groups) {
   using C = K3p<N>;
+  typename DftFor<PR>::type df;
+  df.init();
   constexpr int T = C::T;
   constexpr int Q = N / 4;
   __shared__ float2 tab[C::TAB];
@@ -558,7 +565,7 @@ __global__ void __launch_bounds__(K3p<N>::BLOCK) k3_range_power_x4p(K3Args a, in
     float2 X[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) X[e] = ub[(t + T * e) >> 2];
-    fft_stages<N, 16, 4, false>(X, lds, t, true, tw_fwd);
+    fft_stages<N, 16, 4, false>(X, lds, t, true, tw_fwd, df);
 #pragma unroll
     for (int e = 0; e < 16; ++e) X[e] = cscale(X[e], wc.x - wc.y * cwin[t + T * e]);
 
@@ -571,7 +578,7 @@ __global__ void __launch_bounds__(K3p<N>::BLOCK) k3_range_power_x4p(K3Args a, in
       float2 gv[16];
 #pragma unroll
       for (int e = 0; e < 16; ++e) gv[e] = cmulc(X[e], tab[C::PH + (phase - 1) * N + t + T * e]);
-      fft_stages<N, 16, 1, true>(gv, lds, t, true, tw_inv);
+      fft_stages<N, 16, 1, true>(gv, lds, t, true, tw_inv, df);
       if (phase == 2) {
 #pragma unroll
         for (int e = 0; e < 16; ++e) p_first[e] = cabs2(gv[e]) * a.scale;

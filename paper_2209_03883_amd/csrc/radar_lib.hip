@@ -39,13 +39,17 @@ int validate_desc(const radar_frame_desc* d) {
   if (d->n_cp < 1 || d->n_cp > N) return RADAR_E_ARG;
   if (d->window < RADAR_WIN_RECT || d->window > RADAR_WIN_HAMMING) return RADAR_E_ARG;
   if (d->zc_mode != RADAR_ZC_NONE && d->zc_mode != RADAR_ZC_DIAG) return RADAR_E_ARG;
-  if ((d->flags & ~RADAR_FLAG_REFINE) != 0) return RADAR_E_ARG;
+  if ((d->flags & ~(RADAR_FLAG_REFINE | RADAR_FLAG_BF16X3 | RADAR_FLAG_FP16X3)) != 0) return RADAR_E_ARG;
+  if ((d->flags & RADAR_FLAG_BF16X3) && (d->flags & RADAR_FLAG_FP16X3)) return RADAR_E_ARG;
   if (d->ld < N) return RADAR_E_ARG;
   if (!is_pow2(N) || !is_pow2(M) || N < 16 || N > 4096 || M < 16 || M > 4096) return RADAR_E_UNSUPPORTED;
   if (!is_pow2(d->n_pad) || !is_pow2(d->m_pad)) return RADAR_E_UNSUPPORTED;
   if (d->n_pad / N > 8 || d->n_pad > RADAR_TW_LMAX || d->m_pad > RADAR_TW_LMAX) return RADAR_E_UNSUPPORTED;
   if (d->zc_mode == RADAR_ZC_DIAG && (d->zc_root % 2) == 0) return RADAR_E_NOT_COPRIME;  // N is a power of two
   if ((d->flags & RADAR_FLAG_REFINE) && (d->m_pad / M > 16 || d->n_pad / N > 16 || M > 1024))
+    return RADAR_E_UNSUPPORTED;
+  // the matrix-core forms exist for the 4x range-padding kernels
+  if ((d->flags & (RADAR_FLAG_BF16X3 | RADAR_FLAG_FP16X3)) && !(d->n_pad == 4 * N && 4 * d->n_cp <= N && N >= 256))
     return RADAR_E_UNSUPPORTED;
   return RADAR_OK;
 }
@@ -122,14 +126,14 @@ void launch_k1_n(const radar::K1Args& a, int M, int F, hipStream_t s) {
   dim3 grid((M + TEAMS - 1) / TEAMS, F);
   hipLaunchKernelGGL(radar::k1_taps<N>, grid, dim3(radar::kBlock), 0, s, a);
 }
-template <int M>
+template <int M, radar::Prec PR>
 void launch_k2_m(const radar::K2Args& a, int n_cp, int F, hipStream_t s) {
   // tiles of TW taps: at most 64, at most 1024 threads, padded tile M*(TW+1) <= 17408 entries
   constexpr int T = M / 16;
   constexpr int TW0 = 1024 / T < 64 ? 1024 / T : 64;
   constexpr int TW = M * (TW0 + 1) <= 17408 ? TW0 : 17408 / M - 1;
   dim3 grid((n_cp + TW - 1) / TW, a.fm, F);
-  hipLaunchKernelGGL((radar::k2_doppler_tiled<M, TW>), grid, dim3(radar::K2Tile<M, TW>::BLOCK), 0, s, a);
+  hipLaunchKernelGGL((radar::k2_doppler_tiled<M, TW, PR>), grid, dim3(radar::K2Tile<M, TW>::BLOCK), 0, s, a);
 }
 template <int N, int F2>
 void launch_k3_nf(const radar::K3Args& a, int m_pad, int F, hipStream_t s) {
@@ -137,11 +141,11 @@ void launch_k3_nf(const radar::K3Args& a, int m_pad, int F, hipStream_t s) {
   dim3 grid((m_pad + TEAMS - 1) / TEAMS, F);
   hipLaunchKernelGGL((radar::k3_range_power<N, F2>), grid, dim3(radar::kBlock), 0, s, a);
 }
-template <int N>
+template <int N, radar::Prec PR>
 void launch_k3x4_n(const radar::K3Args& a, int m_pad, int F, hipStream_t s) {
   using C = radar::K3x4<N>;
   dim3 grid(m_pad / C::ROWS, F);
-  hipLaunchKernelGGL(radar::k3_range_power_x4<N>, grid, dim3(C::BLOCK), 0, s, a);
+  hipLaunchKernelGGL((radar::k3_range_power_x4<N, PR>), grid, dim3(C::BLOCK), 0, s, a);
 }
 int g_num_cus = 0;
 template <int N>
@@ -152,14 +156,14 @@ void launch_k1p_n(const radar::K1Args& a, int M, int F, hipStream_t s) {
   if (grid * C::WAVES > total) grid = (total + C::WAVES - 1) / C::WAVES;
   hipLaunchKernelGGL(radar::k1_taps_p<N>, dim3(grid), dim3(C::BLOCK), 0, s, a, total);
 }
-template <int N>
+template <int N, radar::Prec PR>
 void launch_k3x4p_n(const radar::K3Args& a, int m_pad, int F, hipStream_t s) {
   using C = radar::K3p<N>;
   const int total = (int)((int64_t)F * m_pad / C::ROWS);
   const int per_wg = C::WAVES;
   int grid = g_num_cus > 0 ? g_num_cus : 256;
   if (grid * per_wg > total) grid = (total + per_wg - 1) / per_wg;
-  hipLaunchKernelGGL(radar::k3_range_power_x4p<N>, dim3(grid), dim3(C::BLOCK), 0, s, a, total);
+  hipLaunchKernelGGL((radar::k3_range_power_x4p<N, PR>), dim3(grid), dim3(C::BLOCK), 0, s, a, total);
 }
 template <int N>
 void launch_k3_n(const radar::K3Args& a, int f2, int m_pad, int F, hipStream_t s) {
@@ -183,6 +187,23 @@ void launch_k3_n(const radar::K3Args& a, int f2, int m_pad, int F, hipStream_t s
     case 2048: CALL(2048); break;  \
     default: CALL(4096); break;    \
   }
+
+template <radar::Prec PR>
+void launch_k3x4_any(const radar::K3Args& a, int N, int m_pad, int F, hipStream_t s) {
+  switch (N) {
+    case 256: launch_k3x4p_n<256, PR>(a, m_pad, F, s); break;
+    case 512: launch_k3x4p_n<512, PR>(a, m_pad, F, s); break;
+    case 1024: launch_k3x4p_n<1024, PR>(a, m_pad, F, s); break;
+    case 2048: launch_k3x4_n<2048, PR>(a, m_pad, F, s); break;
+    default: launch_k3x4_n<4096, PR>(a, m_pad, F, s); break;
+  }
+}
+
+radar::Prec prec_of(const radar_frame_desc* d) {
+  if (d->flags & RADAR_FLAG_BF16X3) return radar::Prec::BF16X3;
+  if (d->flags & RADAR_FLAG_FP16X3) return radar::Prec::FP16X3;
+  return radar::Prec::FP32;
+}
 
 // K1 -> K2 -> K3 for one batch of frames with a common descriptor.
 int enqueue_transforms(const radar_frame_desc* d, int F, const float2* in, const float2* A,
@@ -224,9 +245,20 @@ int enqueue_transforms(const radar_frame_desc* d, int F, const float2* in, const
   a2.fm = d->m_pad / M;
   a2.ph_off = (a2.fm == 2 || a2.fm == 4 || a2.fm == 8) ? radar::phase_offset(ilog2(M), ilog2(a2.fm)) : -1;
   slot = timer_open(RADAR_STAGE_DOPPLER, s);
-#define K2_CALL(m) launch_k2_m<m>(a2, d->n_cp, F, s)
-  RADAR_SIZE_SWITCH(M, K2_CALL)
+  const radar::Prec prec = prec_of(d);
+  if (prec == radar::Prec::BF16X3) {
+#define K2_CALL(m) launch_k2_m<m, radar::Prec::BF16X3>(a2, d->n_cp, F, s)
+    RADAR_SIZE_SWITCH(M, K2_CALL)
 #undef K2_CALL
+  } else if (prec == radar::Prec::FP16X3) {
+#define K2_CALL(m) launch_k2_m<m, radar::Prec::FP16X3>(a2, d->n_cp, F, s)
+    RADAR_SIZE_SWITCH(M, K2_CALL)
+#undef K2_CALL
+  } else {
+#define K2_CALL(m) launch_k2_m<m, radar::Prec::FP32>(a2, d->n_cp, F, s)
+    RADAR_SIZE_SWITCH(M, K2_CALL)
+#undef K2_CALL
+  }
   timer_close(RADAR_STAGE_DOPPLER, slot, s);
   RADAR_HIP_CHECK(hipGetLastError());
 
@@ -244,13 +276,12 @@ int enqueue_transforms(const radar_frame_desc* d, int F, const float2* in, const
   const bool x4 = f2 == 4 && d->n_cp * 4 <= N && N >= 256;
   slot = timer_open(RADAR_STAGE_RANGE, s);
   if (x4) {
-    switch (N) {
-      case 256: launch_k3x4p_n<256>(a3, d->m_pad, F, s); break;
-      case 512: launch_k3x4p_n<512>(a3, d->m_pad, F, s); break;
-      case 1024: launch_k3x4p_n<1024>(a3, d->m_pad, F, s); break;
-      case 2048: launch_k3x4_n<2048>(a3, d->m_pad, F, s); break;
-      default: launch_k3x4_n<4096>(a3, d->m_pad, F, s); break;
-    }
+    if (prec == radar::Prec::BF16X3)
+      launch_k3x4_any<radar::Prec::BF16X3>(a3, N, d->m_pad, F, s);
+    else if (prec == radar::Prec::FP16X3)
+      launch_k3x4_any<radar::Prec::FP16X3>(a3, N, d->m_pad, F, s);
+    else
+      launch_k3x4_any<radar::Prec::FP32>(a3, N, d->m_pad, F, s);
   } else {
 #define K3_CALL(n) launch_k3_n<n>(a3, f2, d->m_pad, F, s)
     RADAR_SIZE_SWITCH(N, K3_CALL)
@@ -471,7 +502,7 @@ int radar_periodogram(const radar_frame_desc* d, int32_t n_frames, const radar_c
                       float* P, int64_t p_frame_stride, void* ws, size_t ws_bytes, void* hip_stream) {
   int rc = check_frame_common(d, n_frames, frame_stride, p_frame_stride, P);
   if (rc != RADAR_OK) return rc;
-  if (!H || !ws || d->flags != 0) return RADAR_E_ARG;
+  if (!H || !ws || (d->flags & RADAR_FLAG_REFINE)) return RADAR_E_ARG;
   if (d->zc_mode != RADAR_ZC_NONE) return RADAR_E_ARG;
   const FrameWs w = frame_ws_layout(d, n_frames, 1);
   if (ws_bytes < w.total) return RADAR_E_WORKSPACE;

@@ -26,7 +26,7 @@ RADAR_E_NOT_COPRIME = -5
 WIN_RECT, WIN_HANN, WIN_HAMMING = 0, 1, 2
 ZC_NONE, ZC_DIAG = 0, 1
 ST_ZERO_SYMBOL, ST_NONFINITE = 1, 2
-FLAG_REFINE = 1
+FLAG_REFINE, FLAG_BF16X3, FLAG_FP16X3 = 1, 2, 4
 
 EXPORTED = (
     "radar_version", "radar_status_string", "radar_init",
@@ -130,12 +130,13 @@ class Config:
     zc_shift: int = 0
     window: int = WIN_HANN
     refine: bool = False
+    precision: int = 0          # 0 (FP32), FLAG_BF16X3 or FLAG_FP16X3
 
     def desc(self, ld: int | None = None) -> FrameDesc:
         return FrameDesc(self.n_sub, self.n_sym, self.n_pad, self.m_pad, self.n_cp,
                          ZC_NONE if self.zc_root is None else ZC_DIAG,
                          0 if self.zc_root is None else int(self.zc_root), int(self.zc_shift),
-                         int(self.window), FLAG_REFINE if self.refine else 0,
+                         int(self.window), (FLAG_REFINE if self.refine else 0) | int(self.precision),
                          int(self.n_sub if ld is None else ld))
 
 

@@ -117,7 +117,7 @@ def test_detect_rejects():
 def test_flags_validation():
     L = radar.lib()
     d = radar.Config(256, 64, 1024, 256, 32, zc_root=1).desc()
-    d.flags = 2  # unknown bit
+    d.flags = 8  # unknown bit
     assert L.radar_frame_workspace_size(ctypes.byref(d), 1, 3) == 0
     ok = radar.Config(256, 64, 1024, 256, 32, refine=True)
     need = L.radar_frame_workspace_size(ctypes.byref(ok.desc()), 1, 3)
@@ -184,3 +184,27 @@ def test_sft_rejects_pointers_and_workspace():
     assert L.radar_fps_sft(d, sp, 2, None, p, 256 * 64, p, p, p, None, p, need, None) == radar.RADAR_E_ARG
     assert L.radar_fps_sft(d, sp, 2, p, p, 100, p, p, p, None, p, need, None) == radar.RADAR_E_ARG  # overlap
     assert L.radar_fps_sft(d, sp, 0, p, p, 0, p, p, p, None, p, need, None) == radar.RADAR_E_ARG
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(precision=radar.FLAG_BF16X3 | radar.FLAG_FP16X3), radar.RADAR_E_ARG),   # at most one form
+    (dict(precision=8), radar.RADAR_E_ARG),                                        # unknown bit
+    (dict(precision=radar.FLAG_BF16X3, n_pad=2048), radar.RADAR_E_UNSUPPORTED),   # needs N' = 4N
+    (dict(precision=radar.FLAG_FP16X3, n_cp=300), radar.RADAR_E_UNSUPPORTED),     # needs 4 N_cp <= N
+])
+def test_precision_flag_validation(kw, code):
+    base = dict(n_sub=1024, n_sym=1024, n_pad=4096, m_pad=4096, n_cp=256, zc_root=7)
+    base.update(kw)
+    cfg = radar.Config(**base)
+    L = radar.lib()
+    assert L.radar_frame_workspace_size(ctypes.byref(cfg.desc()), 1, 8) == 0
+    p = 256
+    assert L.radar_frame_process(ctypes.byref(cfg.desc()), 1, p, p, 0, p, 0, 8, p, p, p, p, 1 << 40, None) == code
+
+
+def test_precision_flags_accepted():
+    L = radar.lib()
+    for fl in (radar.FLAG_BF16X3, radar.FLAG_FP16X3, radar.FLAG_BF16X3 | radar.FLAG_REFINE):
+        cfg = radar.Config(1024, 1024, 4096, 4096, 256, zc_root=7, precision=fl & ~radar.FLAG_REFINE,
+                           refine=bool(fl & radar.FLAG_REFINE))
+        assert L.radar_frame_workspace_size(ctypes.byref(cfg.desc()), 1, 8) > 0

@@ -1,0 +1,113 @@
+"""The matrix-core precision forms (RADAR_FLAG_BF16X3, RADAR_FLAG_FP16X3)
+against the FP64 oracle and against the plain FP32 path, through the C ABI.
+
+Each case prints its error line: normwise max|P - P_ref| / max|P_ref|, and
+the largest relative error over the cells holding at least 1e-3 of the
+maximum, for FP32, BF16x3 and FP16x3.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import radar_oracle as O
+from synth import frames as S
+from tests.gpu_util import compare_peak_indices, normwise_error, oracle_ranked, rounded, say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+radar = pytest.importorskip("paper_2209_03883_amd.radar")
+
+# Normwise periodogram tolerance of the split half-precision forms.
+P_TOL_SPLIT = 2e-3
+# A peak cell may differ from the FP32 path's only where the oracle's values of
+# the two cells lie this close (relative): below the split forms' error.
+NEAR_TIE_SPLIT = 1e-3
+
+FORMS = {"fp32": 0, "bf16x3": radar.FLAG_BF16X3, "fp16x3": radar.FLAG_FP16X3}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    radar.lib()
+
+
+def _run(frames, cfg, k, flags):
+    Y, A = S.frames_to_complex64(frames)
+    desc_cfg = radar.Config(cfg.n_sub, cfg.n_sym, cfg.n_pad, cfg.m_pad, cfg.n_cp, zc_root=cfg.zc_root,
+                            window=cfg.window, precision=flags)
+    P, peaks, n_peaks, status = radar.frame_process(torch.from_numpy(Y).cuda(), torch.from_numpy(A).cuda(),
+                                                    desc_cfg, k)
+    torch.cuda.synchronize()
+    return P.cpu().numpy(), radar.unpack_peaks(peaks, n_peaks.cpu()), status.cpu().numpy()
+
+
+def _rel_big(P, P_ref):
+    big = P_ref >= 1e-3 * P_ref.max()
+    return float(np.max(np.abs(P[big] - P_ref[big]) / P_ref[big]))
+
+
+def _check(frames, cfg, k, label):
+    out = {name: _run(frames, cfg, k, fl) for name, fl in FORMS.items()}
+    for i, f in enumerate(frames):
+        P_ref = O.frame_periodogram(rounded(f.Y), rounded(f.A), n_pad=cfg.n_pad, m_pad=cfg.m_pad, n_cp=cfg.n_cp,
+                                    window_kind=cfg.window, zc_root=cfg.zc_root)
+        ref = oracle_ranked(O, P_ref, k)
+        line = []
+        for name, (P, pk, st) in out.items():
+            assert st[i] == 0
+            err = normwise_error(P[i], P_ref)
+            line.append(f"{name} {err:.2e} (cells >= 1e-3 max: {_rel_big(P[i], P_ref):.2e})")
+            assert err <= (1e-5 if name == "fp32" else P_TOL_SPLIT), (label, name, err)
+            # peak cells: the oracle's, up to near-ties at this form's error level
+            excl = compare_peak_indices([(s, r) for s, r, *_ in pk[i]], ref, P_ref,
+                                        near_tie=1e-5 if name == "fp32" else NEAR_TIE_SPLIT)
+            assert excl is not None, (label, name, pk[i][:4], ref[:4])
+        say(f"{label}/{i}: " + "; ".join(line))
+        # and the FP32 path's cells
+        fp32 = [(s, r) for s, r, *_ in out["fp32"][1][i]]
+        for name in ("bf16x3", "fp16x3"):
+            got = [(s, r) for s, r, *_ in out[name][1][i]]
+            for (gs, gr), (fs, fr) in zip(got, fp32):
+                if (gs, gr) != (fs, fr):
+                    va, vb = P_ref[gs + cfg.m_pad // 2, gr], P_ref[fs + cfg.m_pad // 2, fr]
+                    assert abs(va - vb) <= NEAR_TIE_SPLIT * max(va, vb), (label, name, got, fp32)
+    return out
+
+
+def test_precision_small_workload():
+    cfg = radar.Config(256, 64, 1024, 256, 32, zc_root=1, window=radar.WIN_HANN)
+    frames = [S.make_frame(S.spec_small(snr_db=0.0), 1, i) for i in range(3)]
+    say("precision forms, small workload")
+    _check(frames, cfg, 3, "small")
+
+
+@pytest.mark.parametrize("snr_db", [0.0, 10.0])
+def test_precision_full_frame(snr_db):
+    cfg = radar.Config(1024, 1024, 4096, 4096, 256, zc_root=7, window=radar.WIN_HANN)
+    frames = [S.make_frame(S.spec_full(snr_db=snr_db), 2, 80 + int(snr_db))]
+    say(f"precision forms, full frame, SNR {snr_db}")
+    _check(frames, cfg, 8, f"full-{snr_db}")
+
+
+def test_precision_form_workload_2048x1024():
+    # N = 2048 x M = 1024 with 4x padding: the 8192 x 4096 periodogram
+    cfg = radar.Config(2048, 1024, 8192, 4096, 512, zc_root=7, window=radar.WIN_HANN)
+    frames = [S.make_frame(S.spec_full(snr_db=0.0, n_sub=2048, n_sym=1024), 4, 0)]
+    say("precision forms, 2048 x 1024 -> 8192 x 4096")
+    _check(frames, cfg, 8, "2048x1024")
+
+
+@pytest.mark.parametrize("shape", [(512, 256, 2048, 1024, 128, radar.WIN_HAMMING, 3),
+                                   (4096, 16, 16384, 64, 1024, radar.WIN_RECT, 5),
+                                   (256, 4096, 1024, 4096, 64, radar.WIN_HANN, 1)])
+def test_precision_shapes(shape):
+    n, m, nq, mp, ncp, win, root = shape
+    cfg = radar.Config(n, m, nq, mp, ncp, zc_root=root, window=win)
+    spec = S.FrameSpec(n_sub=n, n_sym=m, qam=16, zc_root=root, n_targets=3, snr_db=10.0, on_grid=False,
+                       rho_min=1.0, rho_max=ncp - 1.0, nu_abs_max=m / 2 - 1, rayleigh=True, min_sep=2.0)
+    frames = [S.make_frame(spec, 70, n + m)]
+    say(f"precision forms, shape {shape}")
+    _check(frames, cfg, 3, f"shape-{n}x{m}")
