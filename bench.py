@@ -38,7 +38,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="CPU work budget for the oracle baseline (0 disables it)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the refinement and FPS-SFT timings reported beside the headline figure")
+                    help="skip the figures reported beside the headline (refinement, precision forms, FPS-SFT, "
+                         "uneven batch)")
+    ap.add_argument("--batch-frames", type=int, default=512,
+                    help="frames of the uneven Monte-Carlo batch reported beside the headline (0 skips it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 3 plain device copies of MIB MiB (calibrates HBM byte counters) and exit")
     return ap.parse_args()
@@ -173,6 +176,92 @@ def time_extras(radar, torch, Yd, Ad, cfg, ws, peaks, n_peaks, status, stream, B
     return out
 
 
+def _match_errors(truth_rho, truth_nu, det, n, m):
+    """Range and Doppler errors (native bins) of the truth-to-detection
+    assignment minimising the summed wrapped distance."""
+    import numpy as np
+    from scipy.optimize import linear_sum_assignment
+
+    if not det:
+        return []
+    dr = np.array([[r - tr for r, _ in det] for tr in truth_rho])
+    dv = np.array([[v - tv for _, v in det] for tv in truth_nu])
+    dv = (dv + m / 2) % m - m / 2
+    rows, cols = linear_sum_assignment(np.hypot(dr, dv))
+    return [(dr[i, j], dv[i, j]) for i, j in zip(rows, cols)]
+
+
+def time_batch(radar, torch, n_frames, steps):
+    """The uneven Monte-Carlo batch: n_frames frames of random N x M shapes in
+    one autotuned, graph-captured plan (4x padding both axes, N_cp = N/4, Hann,
+    k = 16); throughput over replays, and range / Doppler RMSE against SNR
+    from the grid peaks and from the refined peaks."""
+    import numpy as np
+    from synth import frames_torch as G
+
+    specs = G.monte_carlo_specs(n_frames)
+    jobs, truth = [], []
+    for i, sp in enumerate(specs):
+        Y, A, tgt = G.make_frame(sp, 3, i)
+        cfg = radar.Config(sp.n_sub, sp.n_sym, 4 * sp.n_sub, 4 * sp.n_sym, sp.n_sub // 4, zc_root=7,
+                           window=radar.WIN_HANN)
+        jobs.append((Y, A, cfg, 16))
+        truth.append(tgt)
+    torch.cuda.synchronize()
+    b = radar.Batch(jobs, graph=True, tune=True)
+    b.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.launch()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    alg = sum(80 * sp.n_sub * sp.n_sym for sp in specs)
+
+    def rmse_table(batch):
+        bins = {}
+        for i, sp in enumerate(specs):
+            _, pk, st = batch.results(i)
+            n, m = sp.n_sub, sp.n_sym
+            det = [((r + ro) * n / (4 * n), (s + so) * m / (4 * m)) for s, r, _, so, ro in pk[:sp.n_targets]]
+            errs = _match_errors(truth[i][0], truth[i][1], det, n, m)
+            key = int(np.floor((sp.snr_db + 20.0) / 5.0)) * 5 - 20
+            e = bins.setdefault(key, [[], [], 0, 0])
+            for er, ev in errs:
+                e[0].append(er)
+                e[1].append(ev)
+                e[2] += int(abs(er) <= 1.0 and abs(ev) <= 1.0)
+            e[3] += sp.n_targets
+        out = {}
+        for key in sorted(bins):
+            er, ev, hits, tot = bins[key]
+            out[f"{key}..{key + 5} dB"] = {"rmse_range_bins": float(np.sqrt(np.mean(np.square(er)))) if er else None,
+                                           "rmse_doppler_bins": float(np.sqrt(np.mean(np.square(ev)))) if ev else None,
+                                           "hit_rate": hits / max(tot, 1)}
+        return out
+
+    grid = rmse_table(b)
+    groups = b.groups()
+    b.close()
+    del b
+    rjobs = [(Y, A, dataclasses_replace(cfg, refine=True), k) for Y, A, cfg, k in jobs]
+    br = radar.Batch(rjobs, graph=True, tune=True)
+    br.launch()
+    torch.cuda.synchronize()
+    refined = rmse_table(br)
+    br.close()
+    return {"batch_frames": n_frames, "batch_shape_groups": len(groups),
+            "batch_frames_per_s": n_frames / dt, "batch_ms_per_launch": dt * 1e3,
+            "batch_algorithmic_gbytes": alg / 1e9, "batch_hbm_gbs": alg / dt / 1e9,
+            "batch_rmse_vs_snr_grid": grid, "batch_rmse_vs_snr_refined": refined}
+
+
+def dataclasses_replace(cfg, **kw):
+    import dataclasses
+
+    return dataclasses.replace(cfg, **kw)
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -229,6 +318,11 @@ def main():
 
     extras = {} if args.no_extras else time_extras(radar, torch, Yd, Ad, cfg, ws, peaks, n_peaks, status, stream,
                                                    B, args.steps, args.warmup)
+    if not args.no_extras and args.batch_frames > 0:
+        print(f"[bench] uneven batch of {args.batch_frames} frames", file=sys.stderr, flush=True)
+        extras.update(time_batch(radar, torch, args.batch_frames, 5))
+        print(f"[bench] batch {({k: v for k, v in extras.items() if k.startswith('batch_') and 'rmse' not in k})}",
+              file=sys.stderr, flush=True)
 
     frames_done = B * args.steps
     fps = frames_done / dt

@@ -239,6 +239,60 @@ int radar_fps_sft(const radar_frame_desc *d, const radar_sft_desc *s, int32_t n_
                   radar_cf32 *slices, void *ws, size_t ws_bytes, void *hip_stream);
 
 /* ------------------------------------------------------------------------
+ * Batches of frames with uneven shapes -- the receive path of
+ * radar_frame_process for many jobs at once, captured into one graph.
+ *
+ * A job is one frame with its own descriptor and its own buffers (device
+ * pointers, caller-owned, laid out as for radar_frame_process with
+ * n_frames = 1): Y, A [M][ld]; P [M'][N'] (16-byte aligned); peaks [k];
+ * n_peaks and status one word each.  Descriptors follow radar_frame_process
+ * (flags may hold RADAR_FLAG_REFINE and one precision flag).
+ *
+ * radar_batch_create groups the jobs by descriptor and k, uploads per-group
+ * tables of the jobs' buffers into the workspace (synchronously), and builds
+ * the launch sequence: per group the clear, taps, Doppler, range, peak (and
+ * refinement) kernels, which address each frame through its table entry.
+ * With RADAR_BATCH_TUNE it first times candidate launch plans per group on
+ * the jobs' own data (persistent grid sizes; the four-phase or the
+ * one-team-per-row range kernel) and keeps the fastest; choices are cached
+ * per shape for the life of the process.  With RADAR_BATCH_GRAPH the whole
+ * sequence is captured once into a HIP graph, and radar_batch_launch replays
+ * it on the given stream; otherwise radar_batch_launch enqueues the kernels.
+ * The plan keeps the job pointers and the workspace: both must stay valid
+ * and unmoved until radar_batch_destroy.  Launches of one plan run in
+ * stream order; a plan is not thread-safe.
+ *
+ * ws: device workspace of radar_batch_workspace_size bytes (the job tables
+ *     plus the scratch of the largest group).
+ * Errors: as radar_frame_process per job (validation before any HIP call),
+ * RADAR_E_ARG for n_jobs < 1, unknown batch flags or a NULL plan pointer,
+ * RADAR_E_HIP if a HIP call (upload, capture, instantiation) fails.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  radar_frame_desc d;
+  const radar_cf32 *Y, *A;
+  float *P;
+  radar_peak *peaks;
+  int32_t *n_peaks;
+  uint32_t *status;
+  int32_t k;                    /* peaks sought, 1..64 */
+} radar_frame_job;
+
+enum { RADAR_BATCH_GRAPH = 1, RADAR_BATCH_TUNE = 2 };
+
+typedef struct radar_batch radar_batch;
+size_t radar_batch_workspace_size(const radar_frame_job *jobs, int32_t n_jobs);
+int radar_batch_create(const radar_frame_job *jobs, int32_t n_jobs, int32_t flags, void *ws, size_t ws_bytes,
+                       void *hip_stream, radar_batch **out);
+int radar_batch_launch(radar_batch *b, void *hip_stream);
+/* Number of shape groups, and the tuned plan of group g (k1_mult: taps
+ * work-groups per CU, k3_mult: range work-groups per CU, k3_generic: 1 when
+ * the one-team-per-row range kernel was chosen). */
+int radar_batch_info(const radar_batch *b, int32_t g, int32_t *n_groups, int32_t *n_frames,
+                     int32_t *k1_mult, int32_t *k3_mult, int32_t *k3_generic);
+void radar_batch_destroy(radar_batch *b);
+
+/* ------------------------------------------------------------------------
  * Stage timing -- a profiling aid, off by default.
  *
  * radar_timing_start(max_launches) creates HIP events for up to max_launches

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/radar.h"
+
 // The twiddle table.  Every value is computed on the host in double precision
 // and rounded once to float.  Three sections, laid out so that the entries a
 // wavefront reads in one instruction are contiguous across its lanes:
@@ -50,6 +52,18 @@ constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x >> 1); }
 extern __device__ float2 g_radar_tw[RADAR_TW_ENTRIES];
 
 namespace radar {
+
+// Per-frame buffers of one job of a batch with uneven shapes (device memory).
+// Kernels given a table of these address frame f through refs[f] instead of
+// base + f * stride.
+struct FrameRef {
+  const float2* Y;
+  const float2* A;
+  float* P;
+  radar_peak* peaks;
+  int32_t* n_peaks;
+  uint32_t* status;
+};
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }

@@ -30,6 +30,7 @@ struct K1Args {
   int window;
   int from_h;             // input already is the LS estimate H
   float inv_n;            // 1/N
+  const FrameRef* refs;   // per-frame Y, A, status (batch jobs), or null: base + f * frame_stride
 };
 
 // K1: one team per OFDM symbol.
@@ -46,8 +47,8 @@ __global__ void __launch_bounds__(kBlock) k1_taps(K1Args a) {
   const int lc = active ? l : 0;
   float2* lds = lds_all + team * LdsSize<N>::value;
 
-  const float2* y = a.Y + f * a.frame_stride + lc * a.ld;
-  const float2* x = a.A + f * a.frame_stride + lc * a.ld;
+  const float2* y = (a.refs ? a.refs[f].Y : a.Y + f * a.frame_stride) + lc * a.ld;
+  const float2* x = (a.refs ? a.refs[f].A : a.A + f * a.frame_stride) + lc * a.ld;
   uint32_t st = 0;
   float2 v[16];
 #pragma unroll
@@ -83,7 +84,10 @@ __global__ void __launch_bounds__(kBlock) k1_taps(K1Args a) {
     const int n = t + T * e;
     if (n < a.n_cp) out[n] = cscale(v[e], scale);
   }
-  if (st && a.status) atomicOr(a.status + f, st);
+  if (st) {
+    uint32_t* sp = a.refs ? a.refs[f].status : (a.status ? a.status + f : nullptr);
+    if (sp) atomicOr(sp, st);
+  }
 }
 
 
@@ -123,8 +127,8 @@ __global__ void __launch_bounds__(K1p<N>::BLOCK) k1_taps_p(K1Args a, int total_g
     const int gsym = grp * C::ROWS + g;                     // symbol over all frames
     const int f = gsym / a.M;
     const int l = gsym - f * a.M;
-    const float2* y = a.Y + f * a.frame_stride + l * a.ld;
-    const float2* x = a.A + f * a.frame_stride + l * a.ld;
+    const float2* y = (a.refs ? a.refs[f].Y : a.Y + f * a.frame_stride) + l * a.ld;
+    const float2* x = (a.refs ? a.refs[f].A : a.A + f * a.frame_stride) + l * a.ld;
     uint32_t st = 0;
     float2 v[16];
 #pragma unroll
@@ -158,7 +162,10 @@ __global__ void __launch_bounds__(K1p<N>::BLOCK) k1_taps_p(K1Args a, int total_g
       const int n = t + T * e;
       if (n < a.n_cp) out[n] = cscale(v[e], scale);
     }
-    if (st && a.status) atomicOr(a.status + f, st);
+    if (st) {
+      uint32_t* sp = a.refs ? a.refs[f].status : (a.status ? a.status + f : nullptr);
+      if (sp) atomicOr(sp, st);
+    }
   }
 }
 
@@ -282,6 +289,7 @@ struct K3Args {
   int window;
   float scale;            // 1/(N M)
   float* rowmax;          // [F][M'] row maxima of P (written by the x4 kernel), or null
+  const FrameRef* refs;   // per-frame P (batch jobs), or null: P + f * p_stride
 };
 
 template <int F2>
@@ -336,7 +344,7 @@ __global__ void __launch_bounds__(kBlock) k3_range_power(K3Args a) {
     for (int e = 0; e < 16; ++e) pw[e][b2] = cabs2(g[e]) * a.scale;
   }
   if (!active) return;
-  float* dst = a.P + (int64_t)f * a.p_stride + (int64_t)row * a.n_pad;
+  float* dst = (a.refs ? a.refs[f].P : a.P + (int64_t)f * a.p_stride) + (int64_t)row * a.n_pad;
 #pragma unroll
   for (int e = 0; e < 16; ++e) store_row_chunk<F2>(dst + F2 * (t + T * e), pw[e]);
 }
@@ -449,7 +457,7 @@ __global__ void __launch_bounds__(K3x4<N>::BLOCK) k3_range_power_x4(K3Args a) {
   for (int e = 0; e < 16; ++e) prow[4 * (t + T * e) + team] = p[e];
   __syncthreads();
 
-  float* dst = a.P + (int64_t)f * a.p_stride + (int64_t)row * (4 * N);
+  float* dst = (a.refs ? a.refs[f].P : a.P + (int64_t)f * a.p_stride) + (int64_t)row * (4 * N);
   float mx = 0.0f;
 #pragma unroll
   for (int i = gi; i < N; i += C::GROUP) {
@@ -569,7 +577,7 @@ __global__ void __launch_bounds__(K3p<N>::BLOCK) k3_range_power_x4p(K3Args a, in
 #pragma unroll
     for (int e = 0; e < 16; ++e) X[e] = cscale(X[e], wc.x - wc.y * cwin[t + T * e]);
 
-    float* dst = a.P + (int64_t)f * a.p_stride + (int64_t)row * (4 * N);
+    float* dst = (a.refs ? a.refs[f].P : a.P + (int64_t)f * a.p_stride) + (int64_t)row * (4 * N);
     float mx = 0.0f;
     float p_first[16];
 #pragma unroll
@@ -617,11 +625,13 @@ __global__ void __launch_bounds__(K3p<N>::BLOCK) k3_range_power_x4p(K3Args a, in
 
 // Clears the per-frame status and peak-count words (a fill kernel rather than
 // a memset, so the sequence stays safe inside captured graphs).
-__global__ void k0_clear(uint32_t* status, int32_t* n_peaks, int n_frames) {
+__global__ void k0_clear(uint32_t* status, int32_t* n_peaks, int n_frames, const FrameRef* refs) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n_frames) {
-    if (status) status[i] = 0u;
-    if (n_peaks) n_peaks[i] = 0;
+    uint32_t* sp = refs ? refs[i].status : (status ? status + i : nullptr);
+    int32_t* np = refs ? refs[i].n_peaks : (n_peaks ? n_peaks + i : nullptr);
+    if (sp) *sp = 0u;
+    if (np) *np = 0;
   }
 }
 

@@ -78,10 +78,10 @@ __device__ __forceinline__ float block_max_f32(float v, float* red) {
 // Row maxima of arbitrary periodograms (used when the range kernel did not
 // produce them).  Grid (m_pad, F), 256 threads.
 __global__ void __launch_bounds__(256) k_row_max(const float* P, int64_t p_stride, int m_pad, int n_pad,
-                                                 float* rowmax) {
+                                                 float* rowmax, const FrameRef* refs) {
   __shared__ float red[4];
   const int f = blockIdx.y, row = blockIdx.x;
-  const float* r0 = P + (int64_t)f * p_stride + (int64_t)row * n_pad;
+  const float* r0 = (refs ? refs[f].P : P + (int64_t)f * p_stride) + (int64_t)row * n_pad;
   float mx = -__builtin_huge_valf();
   for (int r = threadIdx.x; r < n_pad; r += blockDim.x) mx = fmaxf(mx, r0[r]);
   mx = block_max_f32(mx, red);
@@ -156,14 +156,15 @@ __global__ void __launch_bounds__(256) k_peak_threshold(const float* rowmax, int
 // cand[f][j][0..k) for list entry j (key 0 pads).
 __global__ void __launch_bounds__(256) k_peak_rows_listed(const float* P, int64_t p_stride, int m_pad, int n_pad,
                                                           int k, const float* tau, const int32_t* list,
-                                                          const int32_t* cnt, uint64_t* cand) {
+                                                          const int32_t* cnt, uint64_t* cand,
+                                                          const FrameRef* refs) {
   extern __shared__ uint32_t s_ord[];  // n_pad entries, 0 = not a candidate
   __shared__ uint64_t red[4];
   __shared__ int s_cnt[4];
   const int f = blockIdx.y;
   const int count = cnt[f];
   const float th = tau[f];
-  const float* base = P + (int64_t)f * p_stride;
+  const float* base = refs ? refs[f].P : P + (int64_t)f * p_stride;
   for (int j = blockIdx.x; j < count; j += gridDim.x) {
     const int row = list[(int64_t)f * m_pad + j];
     const float* rm = base + (int64_t)((row - 1) & (m_pad - 1)) * n_pad;
@@ -233,7 +234,8 @@ __global__ void __launch_bounds__(256) k_peak_rows_listed(const float* P, int64_
 // Step 4: the k best keys over the scanned rows of a frame, one wavefront per
 // frame (grid F, 64 threads).
 __global__ void __launch_bounds__(64) k_peak_merge(const uint64_t* cand, const int32_t* cnt, int m_pad, int n_pad,
-                                                   int k, radar_peak* peaks, int32_t* n_peaks) {
+                                                   int k, radar_peak* peaks, int32_t* n_peaks,
+                                                   const FrameRef* refs) {
   const int f = blockIdx.x;
   const int count = cnt[f] * k;
   const uint64_t* c = cand + (int64_t)f * m_pad * k;
@@ -255,11 +257,11 @@ __global__ void __launch_bounds__(64) k_peak_merge(const uint64_t* cand, const i
       pk.p = ord_value((uint32_t)(best >> 32));
       pk.s_off = 0.0f;
       pk.r_off = 0.0f;
-      peaks[(int64_t)f * k + i] = pk;
+      (refs ? refs[f].peaks : peaks + (int64_t)f * k)[i] = pk;
     }
     last = best;
   }
-  if (threadIdx.x == 0) n_peaks[f] = i;
+  if (threadIdx.x == 0) *(refs ? refs[f].n_peaks : n_peaks + f) = i;
 }
 
 }  // namespace radar

@@ -24,6 +24,7 @@ struct K7Args {
   radar_peak* peaks;       // [F][k]
   const int32_t* n_peaks;  // [F]
   int k, M, N, n_cp, m_pad, n_pad, window;
+  const FrameRef* refs;    // per-frame peaks / n_peaks (batch jobs), or null
 };
 
 constexpr int kRefineThreads = 1024;
@@ -48,8 +49,8 @@ __global__ void __launch_bounds__(kRefineThreads) k7_refine(K7Args a) {
   __shared__ double2 s_red[16][7 * 7];
   const int f = blockIdx.y;
   const int i = blockIdx.x;
-  if (i >= a.n_peaks[f]) return;
-  radar_peak* pk = a.peaks + (int64_t)f * a.k + i;
+  if (i >= (a.refs ? *a.refs[f].n_peaks : a.n_peaks[f])) return;
+  radar_peak* pk = (a.refs ? a.refs[f].peaks : a.peaks + (int64_t)f * a.k) + i;
   const int fs = 16 * a.M / a.m_pad;   // fine cells per padded cell
   const int fr = 16 * a.N / a.n_pad;
   const int cs = pk->s * fs;           // signed fine Doppler index

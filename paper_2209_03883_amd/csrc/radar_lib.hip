@@ -2,9 +2,12 @@
 // table, and kernel launches behind the C ABI declared in include/radar.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "../../include/radar.h"
@@ -96,10 +99,20 @@ struct StageTimer {
   std::vector<hipEvent_t> ev[RADAR_NUM_STAGES];  // 2 per launch
 };
 StageTimer g_timer;
+thread_local bool g_capturing = false;  // launches are being captured into a graph: no event records
+
+// Launch parameters an autotuner may choose per shape (defaults: one
+// persistent work-group per CU, the four-phase range kernel where it applies).
+struct Tuning {
+  int k1_mult = 1;         // persistent taps kernel: work-groups per CU
+  int k3_mult = 1;         // persistent range kernel: work-groups per CU
+  bool k3_generic = false; // use the one-team-per-row range kernel instead of the four-phase one
+};
+thread_local Tuning g_tune;
 
 // Records the opening event of a timed stage launch; returns the slot or -1.
 int timer_open(int stage, hipStream_t s) {
-  if (!g_timer.on || g_timer.used[stage] >= g_timer.cap) return -1;
+  if (g_capturing || !g_timer.on || g_timer.used[stage] >= g_timer.cap) return -1;
   const int slot = g_timer.used[stage]++;
   hipEventRecord(g_timer.ev[stage][2 * slot], s);
   return slot;
@@ -152,7 +165,7 @@ template <int N>
 void launch_k1p_n(const radar::K1Args& a, int M, int F, hipStream_t s) {
   using C = radar::K1p<N>;
   const int total = (int)((int64_t)F * M / C::ROWS);
-  int grid = g_num_cus > 0 ? g_num_cus : 256;
+  int grid = (g_num_cus > 0 ? g_num_cus : 256) * g_tune.k1_mult;
   if (grid * C::WAVES > total) grid = (total + C::WAVES - 1) / C::WAVES;
   hipLaunchKernelGGL(radar::k1_taps_p<N>, dim3(grid), dim3(C::BLOCK), 0, s, a, total);
 }
@@ -161,7 +174,7 @@ void launch_k3x4p_n(const radar::K3Args& a, int m_pad, int F, hipStream_t s) {
   using C = radar::K3p<N>;
   const int total = (int)((int64_t)F * m_pad / C::ROWS);
   const int per_wg = C::WAVES;
-  int grid = g_num_cus > 0 ? g_num_cus : 256;
+  int grid = (g_num_cus > 0 ? g_num_cus : 256) * g_tune.k3_mult;
   if (grid * per_wg > total) grid = (total + per_wg - 1) / per_wg;
   hipLaunchKernelGGL((radar::k3_range_power_x4p<N, PR>), dim3(grid), dim3(C::BLOCK), 0, s, a, total);
 }
@@ -208,7 +221,7 @@ radar::Prec prec_of(const radar_frame_desc* d) {
 // K1 -> K2 -> K3 for one batch of frames with a common descriptor.
 int enqueue_transforms(const radar_frame_desc* d, int F, const float2* in, const float2* A,
                        int64_t frame_stride, int from_h, float* P, int64_t p_stride, uint32_t* status,
-                       const FrameWs& w, char* ws, hipStream_t s) {
+                       const FrameWs& w, char* ws, hipStream_t s, const radar::FrameRef* refs = nullptr) {
   const int N = d->n_sub, M = d->n_sym;
   float2* taps = reinterpret_cast<float2*>(ws + w.taps);
   float2* U = reinterpret_cast<float2*>(ws + w.U);
@@ -229,6 +242,7 @@ int enqueue_transforms(const radar_frame_desc* d, int F, const float2* in, const
   a1.window = d->window;
   a1.from_h = from_h;
   a1.inv_n = 1.0f / (float)N;
+  a1.refs = refs;
   int slot = timer_open(RADAR_STAGE_TAPS, s);
 #define K1_CALL(n) launch_k1_n<n>(a1, M, F, s)
   RADAR_SIZE_SWITCH(N, K1_CALL)
@@ -272,8 +286,9 @@ int enqueue_transforms(const radar_frame_desc* d, int F, const float2* in, const
   a3.window = d->window;
   a3.scale = (float)(1.0 / ((double)N * (double)M));
   a3.rowmax = reinterpret_cast<float*>(ws + w.pk.rowmax);
+  a3.refs = refs;
   const int f2 = d->n_pad / N;
-  const bool x4 = f2 == 4 && d->n_cp * 4 <= N && N >= 256;
+  const bool x4 = f2 == 4 && d->n_cp * 4 <= N && N >= 256 && !(g_tune.k3_generic && prec == radar::Prec::FP32);
   slot = timer_open(RADAR_STAGE_RANGE, s);
   if (x4) {
     if (prec == radar::Prec::BF16X3)
@@ -291,15 +306,37 @@ int enqueue_transforms(const radar_frame_desc* d, int F, const float2* in, const
   RADAR_HIP_CHECK(hipGetLastError());
   if (!x4) {
     hipLaunchKernelGGL(radar::k_row_max, dim3(d->m_pad, F), dim3(256), 0, s, P, p_stride, d->m_pad, d->n_pad,
-                       a3.rowmax);
+                       a3.rowmax, refs);
     RADAR_HIP_CHECK(hipGetLastError());
   }
   return RADAR_OK;
 }
 
+// Sub-cell refinement of the k peaks of every frame from the DFT-CE taps.
+int enqueue_refine(const radar_frame_desc* d, int F, int k, const float2* taps, radar_peak* peaks,
+                   int32_t* n_peaks, const radar::FrameRef* refs, hipStream_t s) {
+  radar::K7Args a7{};
+  a7.taps = taps;
+  a7.peaks = peaks;
+  a7.n_peaks = n_peaks;
+  a7.k = k;
+  a7.M = d->n_sym;
+  a7.N = d->n_sub;
+  a7.n_cp = d->n_cp;
+  a7.m_pad = d->m_pad;
+  a7.n_pad = d->n_pad;
+  a7.window = d->window;
+  a7.refs = refs;
+  const int slot = timer_open(RADAR_STAGE_REFINE, s);
+  hipLaunchKernelGGL(radar::k7_refine, dim3(k, F), dim3(radar::kRefineThreads), 0, s, a7);
+  timer_close(RADAR_STAGE_REFINE, slot, s);
+  RADAR_HIP_CHECK(hipGetLastError());
+  return RADAR_OK;
+}
+
 // Peak search from P and its row maxima (already in the workspace).
 int enqueue_peaks(const float* P, int64_t p_stride, int m_pad, int n_pad, int F, int k, const PeakWs& w, char* ws,
-                  radar_peak* peaks, int32_t* n_peaks, hipStream_t s) {
+                  radar_peak* peaks, int32_t* n_peaks, hipStream_t s, const radar::FrameRef* refs = nullptr) {
   float* rowmax = reinterpret_cast<float*>(ws + w.rowmax);
   float* tau = reinterpret_cast<float*>(ws + w.tau);
   int32_t* cnt = reinterpret_cast<int32_t*>(ws + w.cnt);
@@ -311,9 +348,10 @@ int enqueue_peaks(const float* P, int64_t p_stride, int m_pad, int n_pad, int F,
   RADAR_HIP_CHECK(hipGetLastError());
   const int groups = m_pad < 32 ? m_pad : 32;
   hipLaunchKernelGGL(radar::k_peak_rows_listed, dim3(groups, F), dim3(256), n_pad * sizeof(uint32_t), s, P,
-                     p_stride, m_pad, n_pad, k, tau, list, cnt, cand);
+                     p_stride, m_pad, n_pad, k, tau, list, cnt, cand, refs);
   RADAR_HIP_CHECK(hipGetLastError());
-  hipLaunchKernelGGL(radar::k_peak_merge, dim3(F), dim3(64), 0, s, cand, cnt, m_pad, n_pad, k, peaks, n_peaks);
+  hipLaunchKernelGGL(radar::k_peak_merge, dim3(F), dim3(64), 0, s, cand, cnt, m_pad, n_pad, k, peaks, n_peaks,
+                     refs);
   RADAR_HIP_CHECK(hipGetLastError());
   timer_close(RADAR_STAGE_PEAKS, slot, s);
   return RADAR_OK;
@@ -365,6 +403,148 @@ int launch_sft_q(const radar::K5Args& a5, const radar::K6Args& a6, int F, hipStr
   hipLaunchKernelGGL(radar::k6_sft_decode<Q>, dim3(F), dim3(radar::kSftDecodeThreads), 0, s, a6);
   timer_close(RADAR_STAGE_SFT_DECODE, slot, s);
   RADAR_HIP_CHECK(hipGetLastError());
+  return RADAR_OK;
+}
+
+// ------------------------------------------------------ uneven batches
+struct BatchGroup {
+  radar_frame_desc d;
+  int k = 0;
+  std::vector<int> jobs;
+  size_t refs_off = 0;  // FrameRef table in the workspace
+  Tuning tune;
+};
+
+bool same_group(const radar_frame_desc& a, int ka, const radar_frame_desc& b, int kb) {
+  return ka == kb && a.n_sub == b.n_sub && a.n_sym == b.n_sym && a.n_pad == b.n_pad && a.m_pad == b.m_pad &&
+         a.n_cp == b.n_cp && a.zc_mode == b.zc_mode && a.zc_root == b.zc_root && a.zc_shift == b.zc_shift &&
+         a.window == b.window && a.flags == b.flags && a.ld == b.ld;
+}
+
+int validate_job(const radar_frame_job& j) {
+  const int rc = validate_desc(&j.d);
+  if (rc != RADAR_OK) return rc;
+  if (!j.Y || !j.A || !j.P || !j.peaks || !j.n_peaks || !j.status) return RADAR_E_ARG;
+  if (reinterpret_cast<uintptr_t>(j.P) & 15) return RADAR_E_ARG;
+  if (j.k < 1 || j.k > 64) return RADAR_E_ARG;
+  return RADAR_OK;
+}
+
+// groups in order of first appearance; fills refs offsets and returns the workspace size
+size_t plan_groups(const radar_frame_job* jobs, int n, std::vector<BatchGroup>& groups, size_t* scratch_off) {
+  groups.clear();
+  for (int i = 0; i < n; ++i) {
+    auto it = std::find_if(groups.begin(), groups.end(),
+                           [&](const BatchGroup& g) { return same_group(g.d, g.k, jobs[i].d, jobs[i].k); });
+    if (it == groups.end()) {
+      BatchGroup g;
+      g.d = jobs[i].d;
+      g.k = jobs[i].k;
+      groups.push_back(g);
+      it = groups.end() - 1;
+    }
+    it->jobs.push_back(i);
+  }
+  size_t off = 0, scratch = 0;
+  for (auto& g : groups) {
+    g.refs_off = off;
+    off += align256(g.jobs.size() * sizeof(radar::FrameRef));
+    scratch = std::max(scratch, frame_ws_layout(&g.d, (int)g.jobs.size(), g.k).total);
+  }
+  *scratch_off = off;
+  return off + scratch;
+}
+
+}  // namespace
+
+struct radar_batch {
+  std::vector<BatchGroup> groups;
+  char* ws = nullptr;
+  size_t scratch_off = 0;
+  int flags = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+int enqueue_group(const radar_batch& b, const BatchGroup& g, hipStream_t s) {
+  const int F = (int)g.jobs.size();
+  const auto* refs = reinterpret_cast<const radar::FrameRef*>(b.ws + g.refs_off);
+  char* scratch = b.ws + b.scratch_off;
+  const FrameWs w = frame_ws_layout(&g.d, F, g.k);
+  const Tuning saved = g_tune;
+  g_tune = g.tune;
+  hipLaunchKernelGGL(radar::k0_clear, dim3((F + 255) / 256), dim3(256), 0, s, nullptr, nullptr, F, refs);
+  int rc = hipGetLastError() == hipSuccess ? RADAR_OK : RADAR_E_HIP;
+  if (rc == RADAR_OK)
+    rc = enqueue_transforms(&g.d, F, nullptr, nullptr, 0, 0, nullptr, 0, nullptr, w, scratch, s, refs);
+  if (rc == RADAR_OK) rc = enqueue_peaks(nullptr, 0, g.d.m_pad, g.d.n_pad, F, g.k, w.pk, scratch, nullptr, nullptr, s, refs);
+  if (rc == RADAR_OK && (g.d.flags & RADAR_FLAG_REFINE))
+    rc = enqueue_refine(&g.d, F, g.k, reinterpret_cast<const float2*>(scratch + w.taps), nullptr, nullptr, refs, s);
+  g_tune = saved;
+  return rc;
+}
+
+// Autotuner: candidate launch plans of one group, timed on the jobs' data.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int, int, int, int, int>, Tuning> g_tune_cache;
+
+int tune_group(radar_batch& b, BatchGroup& g, hipStream_t s) {
+  const radar_frame_desc& d = g.d;
+  const int F = (int)g.jobs.size();
+  const auto key = std::make_tuple(d.n_sub, d.n_sym, d.n_pad, d.m_pad, d.n_cp, d.flags, g.k, F);
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      g.tune = it->second;
+      return RADAR_OK;
+    }
+  }
+  const int N = d.n_sub;
+  const bool persistent_k1 = N >= 256 && N <= 1024;
+  const bool x4 = d.n_pad == 4 * N && 4 * d.n_cp <= N && N >= 256;
+  const bool x4p = x4 && N <= 1024;
+  const bool fp32 = !(d.flags & (RADAR_FLAG_BF16X3 | RADAR_FLAG_FP16X3));
+  std::vector<Tuning> cands(1);
+  if (persistent_k1 || x4p) {
+    Tuning t;
+    t.k1_mult = persistent_k1 ? 2 : 1;
+    t.k3_mult = x4p ? 2 : 1;
+    cands.push_back(t);
+  }
+  if (x4 && fp32) {
+    Tuning t;
+    t.k3_generic = true;
+    cands.push_back(t);
+  }
+  if (cands.size() > 1) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return RADAR_E_HIP;
+    float best = 1e30f;
+    Tuning pick = cands[0];
+    for (const Tuning& t : cands) {
+      g.tune = t;
+      int rc = enqueue_group(b, g, s);  // warm-up
+      if (rc != RADAR_OK) return rc;
+      hipEventRecord(e0, s);
+      for (int r = 0; r < 3 && rc == RADAR_OK; ++r) rc = enqueue_group(b, g, s);
+      hipEventRecord(e1, s);
+      if (rc != RADAR_OK || hipEventSynchronize(e1) != hipSuccess) return RADAR_E_HIP;
+      float ms = 0.0f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) {
+        best = ms;
+        pick = t;
+      }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    g.tune = pick;
+  }
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune_cache[key] = g.tune;
   return RADAR_OK;
 }
 
@@ -472,7 +652,8 @@ int radar_frame_process(const radar_frame_desc* d, int32_t n_frames, const radar
   if (ws_bytes < w.total) return RADAR_E_WORKSPACE;
   if ((rc = ensure_init()) != RADAR_OK) return rc;
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
-  hipLaunchKernelGGL(radar::k0_clear, dim3((n_frames + 255) / 256), dim3(256), 0, s, status, n_peaks, n_frames);
+  hipLaunchKernelGGL(radar::k0_clear, dim3((n_frames + 255) / 256), dim3(256), 0, s, status, n_peaks, n_frames,
+                     nullptr);
   RADAR_HIP_CHECK(hipGetLastError());
   char* wsb = static_cast<char*>(ws);
   rc = enqueue_transforms(d, n_frames, reinterpret_cast<const float2*>(Y), reinterpret_cast<const float2*>(A),
@@ -480,22 +661,7 @@ int radar_frame_process(const radar_frame_desc* d, int32_t n_frames, const radar
   if (rc != RADAR_OK) return rc;
   rc = enqueue_peaks(P, p_frame_stride, d->m_pad, d->n_pad, n_frames, k, w.pk, wsb, peaks, n_peaks, s);
   if (rc != RADAR_OK || !(d->flags & RADAR_FLAG_REFINE)) return rc;
-  radar::K7Args a7{};
-  a7.taps = reinterpret_cast<const float2*>(wsb + w.taps);
-  a7.peaks = peaks;
-  a7.n_peaks = n_peaks;
-  a7.k = k;
-  a7.M = d->n_sym;
-  a7.N = d->n_sub;
-  a7.n_cp = d->n_cp;
-  a7.m_pad = d->m_pad;
-  a7.n_pad = d->n_pad;
-  a7.window = d->window;
-  const int slot = timer_open(RADAR_STAGE_REFINE, s);
-  hipLaunchKernelGGL(radar::k7_refine, dim3(k, n_frames), dim3(radar::kRefineThreads), 0, s, a7);
-  timer_close(RADAR_STAGE_REFINE, slot, s);
-  RADAR_HIP_CHECK(hipGetLastError());
-  return RADAR_OK;
+  return enqueue_refine(d, n_frames, k, reinterpret_cast<const float2*>(wsb + w.taps), peaks, n_peaks, nullptr, s);
 }
 
 int radar_periodogram(const radar_frame_desc* d, int32_t n_frames, const radar_cf32* H, int64_t frame_stride,
@@ -529,12 +695,13 @@ int radar_detect_topk(const float* P, int32_t m_pad, int32_t n_pad, int32_t n_fr
   if (n_frames > 1 && p_frame_stride < (int64_t)m_pad * n_pad) return RADAR_E_ARG;
   if (ws_bytes < radar_detect_workspace_size(m_pad, n_pad, n_frames, k)) return RADAR_E_WORKSPACE;
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
-  hipLaunchKernelGGL(radar::k0_clear, dim3((n_frames + 255) / 256), dim3(256), 0, s, nullptr, n_peaks, n_frames);
+  hipLaunchKernelGGL(radar::k0_clear, dim3((n_frames + 255) / 256), dim3(256), 0, s, nullptr, n_peaks, n_frames,
+                     nullptr);
   RADAR_HIP_CHECK(hipGetLastError());
   const PeakWs w = peak_ws_layout(m_pad, n_frames, k, 0);
   char* wsb = static_cast<char*>(ws);
   hipLaunchKernelGGL(radar::k_row_max, dim3(m_pad, n_frames), dim3(256), 0, s, P, p_frame_stride, m_pad, n_pad,
-                     reinterpret_cast<float*>(wsb + w.rowmax));
+                     reinterpret_cast<float*>(wsb + w.rowmax), nullptr);
   RADAR_HIP_CHECK(hipGetLastError());
   return enqueue_peaks(P, p_frame_stride, m_pad, n_pad, n_frames, k, w, wsb, peaks, n_peaks, s);
 }
@@ -577,7 +744,8 @@ int radar_fps_sft(const radar_frame_desc* d, const radar_sft_desc* sd, int32_t n
   }
   if ((rc = ensure_init()) != RADAR_OK) return rc;
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
-  hipLaunchKernelGGL(radar::k0_clear, dim3((n_frames + 255) / 256), dim3(256), 0, s, status, n_peaks, n_frames);
+  hipLaunchKernelGGL(radar::k0_clear, dim3((n_frames + 255) / 256), dim3(256), 0, s, status, n_peaks, n_frames,
+                     nullptr);
   RADAR_HIP_CHECK(hipGetLastError());
 
   radar::K5Args a5{};
@@ -620,6 +788,109 @@ int radar_fps_sft(const radar_frame_desc* d, const radar_sft_desc* sd, int32_t n
     case 4096: return launch_sft_q<4096>(a5, a6, n_frames, s);
     default: return RADAR_E_UNSUPPORTED;
   }
+}
+
+size_t radar_batch_workspace_size(const radar_frame_job* jobs, int32_t n_jobs) {
+  if (!jobs || n_jobs < 1) return 0;
+  for (int i = 0; i < n_jobs; ++i)
+    if (validate_desc(&jobs[i].d) != RADAR_OK || jobs[i].k < 1 || jobs[i].k > 64) return 0;
+  std::vector<BatchGroup> groups;
+  size_t scratch_off = 0;
+  return plan_groups(jobs, n_jobs, groups, &scratch_off);
+}
+
+int radar_batch_create(const radar_frame_job* jobs, int32_t n_jobs, int32_t flags, void* ws, size_t ws_bytes,
+                       void* hip_stream, radar_batch** out) {
+  if (!out || !jobs || n_jobs < 1 || !ws) return RADAR_E_ARG;
+  *out = nullptr;
+  if (flags & ~(RADAR_BATCH_GRAPH | RADAR_BATCH_TUNE)) return RADAR_E_ARG;
+  for (int i = 0; i < n_jobs; ++i) {
+    const int rc = validate_job(jobs[i]);
+    if (rc != RADAR_OK) return rc;
+  }
+  auto* b = new radar_batch();
+  const size_t need = plan_groups(jobs, n_jobs, b->groups, &b->scratch_off);
+  if (ws_bytes < need) {
+    delete b;
+    return RADAR_E_WORKSPACE;
+  }
+  b->ws = static_cast<char*>(ws);
+  b->flags = flags;
+  int rc = ensure_init();
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  // job tables, uploaded once
+  for (const auto& g : b->groups) {
+    if (rc != RADAR_OK) break;
+    std::vector<radar::FrameRef> refs(g.jobs.size());
+    for (size_t j = 0; j < g.jobs.size(); ++j) {
+      const radar_frame_job& jb = jobs[g.jobs[j]];
+      refs[j] = {reinterpret_cast<const float2*>(jb.Y), reinterpret_cast<const float2*>(jb.A), jb.P, jb.peaks,
+                 jb.n_peaks, jb.status};
+    }
+    if (hipMemcpyAsync(b->ws + g.refs_off, refs.data(), refs.size() * sizeof(radar::FrameRef),
+                       hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      rc = RADAR_E_HIP;
+  }
+  if (rc == RADAR_OK && (flags & RADAR_BATCH_TUNE))
+    for (auto& g : b->groups)
+      if ((rc = tune_group(*b, g, s)) != RADAR_OK) break;
+  if (rc == RADAR_OK && (flags & RADAR_BATCH_GRAPH)) {
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+      rc = RADAR_E_HIP;
+    } else {
+      g_capturing = true;
+      if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = RADAR_E_HIP;
+      for (const auto& g : b->groups)
+        if (rc == RADAR_OK) rc = enqueue_group(*b, g, cs);
+      hipGraph_t graph = nullptr;
+      const hipError_t ec = hipStreamEndCapture(cs, &graph);
+      g_capturing = false;
+      if (rc == RADAR_OK && ec != hipSuccess) rc = RADAR_E_HIP;
+      b->graph = graph;
+      if (rc == RADAR_OK && hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0) != hipSuccess)
+        rc = RADAR_E_HIP;
+      hipStreamDestroy(cs);
+    }
+  }
+  if (rc != RADAR_OK) {
+    radar_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return RADAR_OK;
+}
+
+int radar_batch_launch(radar_batch* b, void* hip_stream) {
+  if (!b) return RADAR_E_ARG;
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  if (b->exec) return hipGraphLaunch(b->exec, s) == hipSuccess ? RADAR_OK : RADAR_E_HIP;
+  for (const auto& g : b->groups) {
+    const int rc = enqueue_group(*b, g, s);
+    if (rc != RADAR_OK) return rc;
+  }
+  return RADAR_OK;
+}
+
+int radar_batch_info(const radar_batch* b, int32_t g, int32_t* n_groups, int32_t* n_frames, int32_t* k1_mult,
+                     int32_t* k3_mult, int32_t* k3_generic) {
+  if (!b) return RADAR_E_ARG;
+  if (n_groups) *n_groups = (int32_t)b->groups.size();
+  if (g < 0 || g >= (int32_t)b->groups.size()) return (n_frames || k1_mult || k3_mult || k3_generic) ? RADAR_E_ARG : RADAR_OK;
+  const BatchGroup& gr = b->groups[g];
+  if (n_frames) *n_frames = (int32_t)gr.jobs.size();
+  if (k1_mult) *k1_mult = gr.tune.k1_mult;
+  if (k3_mult) *k3_mult = gr.tune.k3_mult;
+  if (k3_generic) *k3_generic = gr.tune.k3_generic ? 1 : 0;
+  return RADAR_OK;
+}
+
+void radar_batch_destroy(radar_batch* b) {
+  if (!b) return;
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  delete b;
 }
 
 int radar_timing_start(int32_t max_launches) {

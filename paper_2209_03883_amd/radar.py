@@ -33,7 +33,10 @@ EXPORTED = (
     "radar_frame_workspace_size", "radar_frame_process", "radar_periodogram",
     "radar_detect_workspace_size", "radar_detect_topk", "radar_timing_start", "radar_timing_stop",
     "radar_sft_default", "radar_fps_sft_workspace_size", "radar_fps_sft",
+    "radar_batch_workspace_size", "radar_batch_create", "radar_batch_launch", "radar_batch_info",
+    "radar_batch_destroy",
 )
+BATCH_GRAPH, BATCH_TUNE = 1, 2
 STAGES = ("taps", "doppler", "range", "peaks", "refine", "sft_slices", "sft_decode")
 
 
@@ -60,6 +63,12 @@ class Peak(ctypes.Structure):
 
 
 PEAK_WORDS = ctypes.sizeof(Peak) // 4  # 5 x 32-bit words
+
+
+class FrameJob(ctypes.Structure):
+    _fields_ = [("d", FrameDesc), ("Y", ctypes.c_void_p), ("A", ctypes.c_void_p), ("P", ctypes.c_void_p),
+                ("peaks", ctypes.c_void_p), ("n_peaks", ctypes.c_void_p), ("status", ctypes.c_void_p),
+                ("k", ctypes.c_int32)]
 
 
 class SftDesc(ctypes.Structure):
@@ -100,6 +109,18 @@ def lib() -> ctypes.CDLL:
     L.radar_fps_sft_workspace_size.argtypes = [dp, sp, i32]
     L.radar_fps_sft.restype = ctypes.c_int
     L.radar_fps_sft.argtypes = [dp, sp, i32, vp, vp, i64, vp, vp, vp, vp, vp, sz, vp]
+    jp = ctypes.POINTER(FrameJob)
+    L.radar_batch_workspace_size.restype = sz
+    L.radar_batch_workspace_size.argtypes = [jp, i32]
+    L.radar_batch_create.restype = ctypes.c_int
+    L.radar_batch_create.argtypes = [jp, i32, i32, vp, sz, vp, ctypes.POINTER(vp)]
+    L.radar_batch_launch.restype = ctypes.c_int
+    L.radar_batch_launch.argtypes = [vp, vp]
+    L.radar_batch_info.restype = ctypes.c_int
+    ip = ctypes.POINTER(i32)
+    L.radar_batch_info.argtypes = [vp, i32, ip, ip, ip, ip, ip]
+    L.radar_batch_destroy.restype = None
+    L.radar_batch_destroy.argtypes = [vp]
     L.radar_timing_start.restype = ctypes.c_int
     L.radar_timing_start.argtypes = [i32]
     L.radar_timing_stop.restype = ctypes.c_int
@@ -322,6 +343,83 @@ def fps_sft(Y: torch.Tensor, A: torch.Tensor, cfg: Config, sft: SftDesc, *, slic
     if slices:
         return peaks, n_peaks, status, S
     return peaks, n_peaks, status
+
+
+class Batch:
+    """A radar_batch plan over frames of uneven shapes.
+
+    jobs: list of (Y, A, cfg, k) with Y, A complex64 CUDA tensors (M, N) (rows may
+    be strided).  Allocates each job's P, peaks, n_peaks and status, and the
+    plan's workspace; keeps references to every tensor for the plan's life.
+    """
+
+    def __init__(self, jobs, *, graph: bool = True, tune: bool = False, stream=None):
+        L = lib()
+        self._keep = []
+        arr = (FrameJob * len(jobs))()
+        self.P, self.peaks, self.n_peaks, self.status, self.k = [], [], [], [], []
+        dev = None
+        for i, (Y, A, cfg, k) in enumerate(jobs):
+            Y = _as_frames(Y, cfg, "Y")[0]
+            A = _as_frames(A, cfg, "A")[0]
+            if Y.stride() != A.stride():
+                raise ValueError("Y and A must share strides")
+            dev = Y.device
+            P = torch.empty((cfg.m_pad, cfg.n_pad), dtype=torch.float32, device=dev)
+            pk = alloc_peaks(1, k, dev)[0]
+            npk = torch.zeros(1, dtype=torch.int32, device=dev)
+            st = torch.zeros(1, dtype=torch.int32, device=dev)
+            self._keep += [Y, A]
+            self.P.append(P)
+            self.peaks.append(pk)
+            self.n_peaks.append(npk)
+            self.status.append(st)
+            self.k.append(int(k))
+            arr[i].d = cfg.desc(ld=Y.stride(0))
+            arr[i].Y, arr[i].A, arr[i].P = Y.data_ptr(), A.data_ptr(), P.data_ptr()
+            arr[i].peaks, arr[i].n_peaks, arr[i].status = pk.data_ptr(), npk.data_ptr(), st.data_ptr()
+            arr[i].k = int(k)
+        need = L.radar_batch_workspace_size(arr, len(jobs))
+        if need == 0:
+            raise RadarError(RADAR_E_ARG, "radar_batch_workspace_size")
+        self.workspace = new_workspace(need, dev)
+        h = ctypes.c_void_p()
+        flags = (BATCH_GRAPH if graph else 0) | (BATCH_TUNE if tune else 0)
+        _check(L.radar_batch_create(arr, len(jobs), flags, self.workspace.data_ptr(), self.workspace.numel(),
+                                    _stream_ptr(stream), ctypes.byref(h)), "radar_batch_create")
+        self._h = h
+        self._jobs = arr
+
+    def launch(self, stream=None):
+        _check(lib().radar_batch_launch(self._h, _stream_ptr(stream)), "radar_batch_launch")
+
+    def groups(self):
+        """[(n_frames, k1_mult, k3_mult, k3_generic)] per shape group."""
+        L = lib()
+        n = ctypes.c_int32()
+        _check(L.radar_batch_info(self._h, -1, ctypes.byref(n), None, None, None, None), "radar_batch_info")
+        out = []
+        for g in range(n.value):
+            v = [ctypes.c_int32() for _ in range(4)]
+            _check(L.radar_batch_info(self._h, g, None, *[ctypes.byref(x) for x in v]), "radar_batch_info")
+            out.append(tuple(x.value for x in v))
+        return out
+
+    def results(self, i):
+        """(P, [(s, r, p, s_off, r_off)], status) of job i (host copies)."""
+        return (self.P[i].cpu().numpy(), unpack_peaks(self.peaks[i][None], self.n_peaks[i].cpu())[0],
+                int(self.status[i].cpu()[0]))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().radar_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def timing_start(max_launches: int):

@@ -208,3 +208,44 @@ def test_precision_flags_accepted():
         cfg = radar.Config(1024, 1024, 4096, 4096, 256, zc_root=7, precision=fl & ~radar.FLAG_REFINE,
                            refine=bool(fl & radar.FLAG_REFINE))
         assert L.radar_frame_workspace_size(ctypes.byref(cfg.desc()), 1, 8) > 0
+
+
+def _job(cfg, k, ld=None):
+    j = radar.FrameJob()
+    j.d = cfg.desc(ld=ld)
+    j.Y = j.A = j.P = j.peaks = j.n_peaks = j.status = 256
+    j.k = k
+    return j
+
+
+def test_batch_workspace_groups_by_shape():
+    L = radar.lib()
+    a = radar.Config(256, 64, 1024, 256, 32, zc_root=1)
+    b = radar.Config(1024, 256, 4096, 1024, 256, zc_root=7)
+    jobs = (radar.FrameJob * 6)(_job(a, 3), _job(b, 8), _job(a, 3), _job(a, 3), _job(b, 8), _job(a, 4))
+    ref = 48  # six device pointers per job table entry
+    want = _al(3 * ref) + _al(2 * ref) + _al(1 * ref) + max(_ws(a, 3, 3), _ws(b, 2, 8), _ws(a, 1, 4))
+    assert L.radar_batch_workspace_size(jobs, 6) == want
+    # a different ld is a different group
+    jobs2 = (radar.FrameJob * 2)(_job(a, 3), _job(a, 3, ld=300))
+    assert L.radar_batch_workspace_size(jobs2, 2) == 2 * _al(ref) + _ws(a, 1, 3)
+
+
+def test_batch_rejects_before_any_hip_call():
+    L = radar.lib()
+    a = radar.Config(256, 64, 1024, 256, 32, zc_root=1)
+    out = ctypes.c_void_p()
+    good = (radar.FrameJob * 1)(_job(a, 3))
+    assert L.radar_batch_workspace_size(good, 0) == 0
+    assert L.radar_batch_create(good, 0, 0, 256, 1 << 30, None, ctypes.byref(out)) == radar.RADAR_E_ARG
+    assert L.radar_batch_create(good, 1, 8, 256, 1 << 30, None, ctypes.byref(out)) == radar.RADAR_E_ARG  # flag
+    assert L.radar_batch_create(good, 1, 0, 256, 1 << 30, None, None) == radar.RADAR_E_ARG
+    bad = (radar.FrameJob * 2)(_job(a, 3), _job(radar.Config(1000, 64, 4000, 256, 32), 3))
+    assert L.radar_batch_workspace_size(bad, 2) == 0
+    assert L.radar_batch_create(bad, 2, 0, 256, 1 << 30, None, ctypes.byref(out)) == radar.RADAR_E_UNSUPPORTED
+    nok = (radar.FrameJob * 1)(_job(a, 65))
+    assert L.radar_batch_create(nok, 1, 0, 256, 1 << 30, None, ctypes.byref(out)) == radar.RADAR_E_ARG
+    nul = (radar.FrameJob * 1)(_job(a, 3))
+    nul[0].P = None
+    assert L.radar_batch_create(nul, 1, 0, 256, 1 << 30, None, ctypes.byref(out)) == radar.RADAR_E_ARG
+    assert L.radar_batch_launch(None, None) == radar.RADAR_E_ARG
