@@ -226,18 +226,19 @@ def time_batch(radar, torch, n_frames, steps):
             det = [((r + ro) * n / (4 * n), (s + so) * m / (4 * m)) for s, r, _, so, ro in pk[:sp.n_targets]]
             errs = _match_errors(truth[i][0], truth[i][1], det, n, m)
             key = int(np.floor((sp.snr_db + 20.0) / 5.0)) * 5 - 20
-            e = bins.setdefault(key, [[], [], 0, 0])
+            e = bins.setdefault(key, [[], [], 0])
             for er, ev in errs:
-                e[0].append(er)
-                e[1].append(ev)
-                e[2] += int(abs(er) <= 1.0 and abs(ev) <= 1.0)
-            e[3] += sp.n_targets
+                if abs(er) <= 1.0 and abs(ev) <= 1.0:  # a hit: both errors within one native bin
+                    e[0].append(er)
+                    e[1].append(ev)
+            e[2] += sp.n_targets
         out = {}
         for key in sorted(bins):
-            er, ev, hits, tot = bins[key]
-            out[f"{key}..{key + 5} dB"] = {"rmse_range_bins": float(np.sqrt(np.mean(np.square(er)))) if er else None,
-                                           "rmse_doppler_bins": float(np.sqrt(np.mean(np.square(ev)))) if ev else None,
-                                           "hit_rate": hits / max(tot, 1)}
+            er, ev, tot = bins[key]
+            out[f"{key}..{key + 5} dB"] = {
+                "targets": tot, "hit_rate": len(er) / max(tot, 1),
+                "rmse_range_bins_hits": float(np.sqrt(np.mean(np.square(er)))) if er else None,
+                "rmse_doppler_bins_hits": float(np.sqrt(np.mean(np.square(ev)))) if ev else None}
         return out
 
     grid = rmse_table(b)

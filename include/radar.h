@@ -263,7 +263,9 @@ int radar_fps_sft(const radar_frame_desc *d, const radar_sft_desc *s, int32_t n_
  * stream order; a plan is not thread-safe.
  *
  * ws: device workspace of radar_batch_workspace_size bytes (the job tables
- *     plus the scratch of the largest group).
+ *     plus every group's own scratch: the captured graph runs groups on up
+ *     to four concurrent branches, heaviest groups first onto the least
+ *     loaded branch).
  * Errors: as radar_frame_process per job (validation before any HIP call),
  * RADAR_E_ARG for n_jobs < 1, unknown batch flags or a NULL plan pointer,
  * RADAR_E_HIP if a HIP call (upload, capture, instantiation) fails.

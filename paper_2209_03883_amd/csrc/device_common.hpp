@@ -65,6 +65,27 @@ struct FrameRef {
   uint32_t* status;
 };
 
+// Pointers read from a FrameRef table are generic to the compiler.  The hot
+// loads and stores go through pointers typed in the global address space, so
+// they stay global (not flat) accesses, whose completion the LDS waits do not
+// track.
+#define RADAR_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ RADAR_GLOBAL T* gptr(T* p) {
+  return (RADAR_GLOBAL T*)p;
+}
+typedef float radar_v2 __attribute__((ext_vector_type(2)));
+typedef float radar_v4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float2 gload2(const RADAR_GLOBAL float2* p) {
+  const radar_v2 v = *(const RADAR_GLOBAL radar_v2*)p;
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void gstore2(RADAR_GLOBAL float* p, float a, float b) {
+  *(RADAR_GLOBAL radar_v2*)p = radar_v2{a, b};
+}
+__device__ __forceinline__ void gstore4(RADAR_GLOBAL float* p, float a, float b, float c, float d) {
+  *(RADAR_GLOBAL radar_v4*)p = radar_v4{a, b, c, d};
+}
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }

@@ -47,16 +47,16 @@ __global__ void __launch_bounds__(kBlock) k1_taps(K1Args a) {
   const int lc = active ? l : 0;
   float2* lds = lds_all + team * LdsSize<N>::value;
 
-  const float2* y = (a.refs ? a.refs[f].Y : a.Y + f * a.frame_stride) + lc * a.ld;
-  const float2* x = (a.refs ? a.refs[f].A : a.A + f * a.frame_stride) + lc * a.ld;
+  const RADAR_GLOBAL float2* y = gptr(a.refs ? a.refs[f].Y : a.Y + f * a.frame_stride) + lc * a.ld;
+  const RADAR_GLOBAL float2* x = gptr(a.refs ? a.refs[f].A : a.A + f * a.frame_stride) + lc * a.ld;
   uint32_t st = 0;
   float2 v[16];
 #pragma unroll
-  for (int e = 0; e < 16; ++e) v[e] = y[t + T * e];
+  for (int e = 0; e < 16; ++e) v[e] = gload2(y + t + T * e);
   if (!a.from_h) {
     float2 s[16];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) s[e] = x[t + T * e];
+    for (int e = 0; e < 16; ++e) s[e] = gload2(x + t + T * e);
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int k = t + T * e;
@@ -127,16 +127,16 @@ __global__ void __launch_bounds__(K1p<N>::BLOCK) k1_taps_p(K1Args a, int total_g
     const int gsym = grp * C::ROWS + g;                     // symbol over all frames
     const int f = gsym / a.M;
     const int l = gsym - f * a.M;
-    const float2* y = (a.refs ? a.refs[f].Y : a.Y + f * a.frame_stride) + l * a.ld;
-    const float2* x = (a.refs ? a.refs[f].A : a.A + f * a.frame_stride) + l * a.ld;
+    const RADAR_GLOBAL float2* y = gptr(a.refs ? a.refs[f].Y : a.Y + f * a.frame_stride) + l * a.ld;
+    const RADAR_GLOBAL float2* x = gptr(a.refs ? a.refs[f].A : a.A + f * a.frame_stride) + l * a.ld;
     uint32_t st = 0;
     float2 v[16];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) v[e] = y[t + T * e];
+    for (int e = 0; e < 16; ++e) v[e] = gload2(y + t + T * e);
     if (!a.from_h) {
       float2 sv[16];
 #pragma unroll
-      for (int e = 0; e < 16; ++e) sv[e] = x[t + T * e];
+      for (int e = 0; e < 16; ++e) sv[e] = gload2(x + t + T * e);
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const int k = t + T * e;
@@ -293,15 +293,15 @@ struct K3Args {
 };
 
 template <int F2>
-__device__ __forceinline__ void store_row_chunk(float* dst, const float (&p)[F2]) {
+__device__ __forceinline__ void store_row_chunk(RADAR_GLOBAL float* dst, const float (&p)[F2]) {
   if constexpr (F2 == 1) {
     dst[0] = p[0];
   } else if constexpr (F2 == 2) {
-    *reinterpret_cast<float2*>(dst) = make_float2(p[0], p[1]);
+    gstore2(dst, p[0], p[1]);
   } else {
 #pragma unroll
     for (int i = 0; i < F2; i += 4)
-      *reinterpret_cast<float4*>(dst + i) = make_float4(p[i], p[i + 1], p[i + 2], p[i + 3]);
+      gstore4(dst + i, p[i], p[i + 1], p[i + 2], p[i + 3]);
   }
 }
 
@@ -344,7 +344,7 @@ __global__ void __launch_bounds__(kBlock) k3_range_power(K3Args a) {
     for (int e = 0; e < 16; ++e) pw[e][b2] = cabs2(g[e]) * a.scale;
   }
   if (!active) return;
-  float* dst = (a.refs ? a.refs[f].P : a.P + (int64_t)f * a.p_stride) + (int64_t)row * a.n_pad;
+  RADAR_GLOBAL float* dst = gptr(a.refs ? a.refs[f].P : a.P + (int64_t)f * a.p_stride) + (int64_t)row * a.n_pad;
 #pragma unroll
   for (int e = 0; e < 16; ++e) store_row_chunk<F2>(dst + F2 * (t + T * e), pw[e]);
 }
@@ -457,12 +457,12 @@ __global__ void __launch_bounds__(K3x4<N>::BLOCK) k3_range_power_x4(K3Args a) {
   for (int e = 0; e < 16; ++e) prow[4 * (t + T * e) + team] = p[e];
   __syncthreads();
 
-  float* dst = (a.refs ? a.refs[f].P : a.P + (int64_t)f * a.p_stride) + (int64_t)row * (4 * N);
+  RADAR_GLOBAL float* dst = gptr(a.refs ? a.refs[f].P : a.P + (int64_t)f * a.p_stride) + (int64_t)row * (4 * N);
   float mx = 0.0f;
 #pragma unroll
   for (int i = gi; i < N; i += C::GROUP) {
     const float4 q = reinterpret_cast<const float4*>(prow)[i];
-    reinterpret_cast<float4*>(dst)[i] = q;
+    gstore4(dst + 4 * i, q.x, q.y, q.z, q.w);
     mx = fmaxf(mx, fmaxf(fmaxf(q.x, q.y), fmaxf(q.z, q.w)));
   }
   // row maximum over the GROUP threads of this row
@@ -577,7 +577,7 @@ __global__ void __launch_bounds__(K3p<N>::BLOCK) k3_range_power_x4p(K3Args a, in
 #pragma unroll
     for (int e = 0; e < 16; ++e) X[e] = cscale(X[e], wc.x - wc.y * cwin[t + T * e]);
 
-    float* dst = (a.refs ? a.refs[f].P : a.P + (int64_t)f * a.p_stride) + (int64_t)row * (4 * N);
+    RADAR_GLOBAL float* dst = gptr(a.refs ? a.refs[f].P : a.P + (int64_t)f * a.p_stride) + (int64_t)row * (4 * N);
     float mx = 0.0f;
     float p_first[16];
 #pragma unroll
@@ -594,7 +594,7 @@ __global__ void __launch_bounds__(K3p<N>::BLOCK) k3_range_power_x4p(K3Args a, in
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
           const float p3 = cabs2(gv[e]) * a.scale;
-          reinterpret_cast<float2*>(dst)[2 * (t + T * e) + 1] = make_float2(p_first[e], p3);
+          gstore2(dst + 2 * (2 * (t + T * e) + 1), p_first[e], p3);
           mx = fmaxf(mx, fmaxf(p_first[e], p3));
         }
       } else {
@@ -612,7 +612,7 @@ __global__ void __launch_bounds__(K3p<N>::BLOCK) k3_range_power_x4p(K3Args a, in
         gz = cscale(ub[0], c1);  // u[N] = u[0]
       }
       const float p0 = cabs2(gz) * a.scale;
-      reinterpret_cast<float2*>(dst)[2 * r1] = make_float2(p0, p_first[e]);
+      gstore2(dst + 4 * r1, p0, p_first[e]);
       mx = fmaxf(mx, fmaxf(p0, p_first[e]));
     }
 #pragma unroll

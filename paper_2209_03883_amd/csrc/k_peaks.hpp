@@ -81,7 +81,7 @@ __global__ void __launch_bounds__(256) k_row_max(const float* P, int64_t p_strid
                                                  float* rowmax, const FrameRef* refs) {
   __shared__ float red[4];
   const int f = blockIdx.y, row = blockIdx.x;
-  const float* r0 = (refs ? refs[f].P : P + (int64_t)f * p_stride) + (int64_t)row * n_pad;
+  const RADAR_GLOBAL float* r0 = gptr(refs ? refs[f].P : P + (int64_t)f * p_stride) + (int64_t)row * n_pad;
   float mx = -__builtin_huge_valf();
   for (int r = threadIdx.x; r < n_pad; r += blockDim.x) mx = fmaxf(mx, r0[r]);
   mx = block_max_f32(mx, red);
@@ -164,12 +164,12 @@ __global__ void __launch_bounds__(256) k_peak_rows_listed(const float* P, int64_
   const int f = blockIdx.y;
   const int count = cnt[f];
   const float th = tau[f];
-  const float* base = refs ? refs[f].P : P + (int64_t)f * p_stride;
+  const RADAR_GLOBAL float* base = gptr(refs ? refs[f].P : P + (int64_t)f * p_stride);
   for (int j = blockIdx.x; j < count; j += gridDim.x) {
     const int row = list[(int64_t)f * m_pad + j];
-    const float* rm = base + (int64_t)((row - 1) & (m_pad - 1)) * n_pad;
-    const float* r0 = base + (int64_t)row * n_pad;
-    const float* rp = base + (int64_t)((row + 1) & (m_pad - 1)) * n_pad;
+    const RADAR_GLOBAL float* rm = base + (int64_t)((row - 1) & (m_pad - 1)) * n_pad;
+    const RADAR_GLOBAL float* r0 = base + (int64_t)row * n_pad;
+    const RADAR_GLOBAL float* rp = base + (int64_t)((row + 1) & (m_pad - 1)) * n_pad;
     for (int r = threadIdx.x; r < n_pad; r += blockDim.x) {
       const float v = r0[r];
       bool pk = v >= th;

@@ -411,7 +411,9 @@ struct BatchGroup {
   radar_frame_desc d;
   int k = 0;
   std::vector<int> jobs;
-  size_t refs_off = 0;  // FrameRef table in the workspace
+  size_t refs_off = 0;     // FrameRef table in the workspace
+  size_t scratch_off = 0;  // this group's scratch (groups may run concurrently)
+  double work = 0.0;       // algorithmic bytes, for balancing concurrent branches
   Tuning tune;
 };
 
@@ -430,8 +432,9 @@ int validate_job(const radar_frame_job& j) {
   return RADAR_OK;
 }
 
-// groups in order of first appearance; fills refs offsets and returns the workspace size
-size_t plan_groups(const radar_frame_job* jobs, int n, std::vector<BatchGroup>& groups, size_t* scratch_off) {
+// groups in order of first appearance; fills the table and scratch offsets and
+// returns the workspace size
+size_t plan_groups(const radar_frame_job* jobs, int n, std::vector<BatchGroup>& groups) {
   groups.clear();
   for (int i = 0; i < n; ++i) {
     auto it = std::find_if(groups.begin(), groups.end(),
@@ -445,22 +448,26 @@ size_t plan_groups(const radar_frame_job* jobs, int n, std::vector<BatchGroup>& 
     }
     it->jobs.push_back(i);
   }
-  size_t off = 0, scratch = 0;
+  size_t off = 0;
   for (auto& g : groups) {
     g.refs_off = off;
     off += align256(g.jobs.size() * sizeof(radar::FrameRef));
-    scratch = std::max(scratch, frame_ws_layout(&g.d, (int)g.jobs.size(), g.k).total);
   }
-  *scratch_off = off;
-  return off + scratch;
+  for (auto& g : groups) {
+    g.scratch_off = off;
+    off += frame_ws_layout(&g.d, (int)g.jobs.size(), g.k).total;
+    g.work = (double)g.jobs.size() * (16.0 * g.d.n_sub * g.d.n_sym + 4.0 * g.d.n_pad * g.d.m_pad);
+  }
+  return off;
 }
+
+constexpr int kBatchBranches = 4;  // concurrent branches of a captured batch
 
 }  // namespace
 
 struct radar_batch {
   std::vector<BatchGroup> groups;
   char* ws = nullptr;
-  size_t scratch_off = 0;
   int flags = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -471,7 +478,7 @@ namespace {
 int enqueue_group(const radar_batch& b, const BatchGroup& g, hipStream_t s) {
   const int F = (int)g.jobs.size();
   const auto* refs = reinterpret_cast<const radar::FrameRef*>(b.ws + g.refs_off);
-  char* scratch = b.ws + b.scratch_off;
+  char* scratch = b.ws + g.scratch_off;
   const FrameWs w = frame_ws_layout(&g.d, F, g.k);
   const Tuning saved = g_tune;
   g_tune = g.tune;
@@ -795,8 +802,7 @@ size_t radar_batch_workspace_size(const radar_frame_job* jobs, int32_t n_jobs) {
   for (int i = 0; i < n_jobs; ++i)
     if (validate_desc(&jobs[i].d) != RADAR_OK || jobs[i].k < 1 || jobs[i].k > 64) return 0;
   std::vector<BatchGroup> groups;
-  size_t scratch_off = 0;
-  return plan_groups(jobs, n_jobs, groups, &scratch_off);
+  return plan_groups(jobs, n_jobs, groups);
 }
 
 int radar_batch_create(const radar_frame_job* jobs, int32_t n_jobs, int32_t flags, void* ws, size_t ws_bytes,
@@ -809,7 +815,7 @@ int radar_batch_create(const radar_frame_job* jobs, int32_t n_jobs, int32_t flag
     if (rc != RADAR_OK) return rc;
   }
   auto* b = new radar_batch();
-  const size_t need = plan_groups(jobs, n_jobs, b->groups, &b->scratch_off);
+  const size_t need = plan_groups(jobs, n_jobs, b->groups);
   if (ws_bytes < need) {
     delete b;
     return RADAR_E_WORKSPACE;
@@ -840,10 +846,36 @@ int radar_batch_create(const radar_frame_job* jobs, int32_t n_jobs, int32_t flag
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
       rc = RADAR_E_HIP;
     } else {
+      // groups run on up to kBatchBranches concurrent branches (each has its
+      // own scratch), heaviest first onto the least loaded branch
+      const int nb = std::min<int>(kBatchBranches, (int)b->groups.size());
+      std::vector<hipStream_t> br(nb, nullptr);
+      std::vector<hipEvent_t> ev(nb + 1, nullptr);
+      for (int i = 0; i < nb && rc == RADAR_OK; ++i)
+        if (hipStreamCreateWithFlags(&br[i], hipStreamNonBlocking) != hipSuccess) rc = RADAR_E_HIP;
+      for (int i = 0; i <= nb && rc == RADAR_OK; ++i)
+        if (hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess) rc = RADAR_E_HIP;
+      std::vector<int> order(b->groups.size());
+      for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+      std::stable_sort(order.begin(), order.end(),
+                       [&](int x, int y) { return b->groups[x].work > b->groups[y].work; });
       g_capturing = true;
-      if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = RADAR_E_HIP;
-      for (const auto& g : b->groups)
-        if (rc == RADAR_OK) rc = enqueue_group(*b, g, cs);
+      if (rc == RADAR_OK && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        rc = RADAR_E_HIP;
+      if (rc == RADAR_OK && hipEventRecord(ev[nb], cs) != hipSuccess) rc = RADAR_E_HIP;
+      for (int i = 0; i < nb && rc == RADAR_OK; ++i)
+        if (hipStreamWaitEvent(br[i], ev[nb], 0) != hipSuccess) rc = RADAR_E_HIP;
+      std::vector<double> load(nb, 0.0);
+      for (int gi : order) {
+        if (rc != RADAR_OK) break;
+        const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[j] += b->groups[gi].work;
+        rc = enqueue_group(*b, b->groups[gi], br[j]);
+      }
+      for (int i = 0; i < nb && rc == RADAR_OK; ++i) {
+        if (hipEventRecord(ev[i], br[i]) != hipSuccess || hipStreamWaitEvent(cs, ev[i], 0) != hipSuccess)
+          rc = RADAR_E_HIP;
+      }
       hipGraph_t graph = nullptr;
       const hipError_t ec = hipStreamEndCapture(cs, &graph);
       g_capturing = false;
@@ -851,6 +883,10 @@ int radar_batch_create(const radar_frame_job* jobs, int32_t n_jobs, int32_t flag
       b->graph = graph;
       if (rc == RADAR_OK && hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0) != hipSuccess)
         rc = RADAR_E_HIP;
+      for (auto e : ev)
+        if (e) hipEventDestroy(e);
+      for (auto st : br)
+        if (st) hipStreamDestroy(st);
       hipStreamDestroy(cs);
     }
   }

@@ -224,11 +224,12 @@ def test_batch_workspace_groups_by_shape():
     b = radar.Config(1024, 256, 4096, 1024, 256, zc_root=7)
     jobs = (radar.FrameJob * 6)(_job(a, 3), _job(b, 8), _job(a, 3), _job(a, 3), _job(b, 8), _job(a, 4))
     ref = 48  # six device pointers per job table entry
-    want = _al(3 * ref) + _al(2 * ref) + _al(1 * ref) + max(_ws(a, 3, 3), _ws(b, 2, 8), _ws(a, 1, 4))
+    # job tables, then every group's own scratch (groups may run concurrently)
+    want = _al(3 * ref) + _al(2 * ref) + _al(1 * ref) + _ws(a, 3, 3) + _ws(b, 2, 8) + _ws(a, 1, 4)
     assert L.radar_batch_workspace_size(jobs, 6) == want
     # a different ld is a different group
     jobs2 = (radar.FrameJob * 2)(_job(a, 3), _job(a, 3, ld=300))
-    assert L.radar_batch_workspace_size(jobs2, 2) == 2 * _al(ref) + _ws(a, 1, 3)
+    assert L.radar_batch_workspace_size(jobs2, 2) == 2 * _al(ref) + 2 * _ws(a, 1, 3)
 
 
 def test_batch_rejects_before_any_hip_call():
