@@ -295,6 +295,53 @@ int radar_batch_info(const radar_batch *b, int32_t g, int32_t *n_groups, int32_t
 void radar_batch_destroy(radar_batch *b);
 
 /* ------------------------------------------------------------------------
+ * The CNN sub-cell refiner (the learned alternative to RADAR_FLAG_REFINE;
+ * the paper names machine learning as future work in Sec. V).
+ *
+ * Network: a 32 x 32 log-periodogram patch (rows Doppler, columns range,
+ * centred on a detected cell) -> conv 3x3 1->32 -> conv 3x3 32->32 stride 2
+ * -> conv 3x3 32->32 -> conv 3x3 32->32 stride 2 (zero padding 1, ReLU after
+ * each) -> dense 2048->10 (ReLU) -> dense 10->2 = (range, Doppler) offset in
+ * cells of the N' x M' grid.  theta: the radar_cnn_param_count() = 48576
+ * FP32 parameters, in order conv1..conv4 (weights [co][ky][kx][ci], biases
+ * [co]), dense1 (weights [10][2048] over the flattening (y*8+x)*32+c, biases
+ * [10]), dense2 ([2][10], [2]).  The three 32->32 convolutions (forward and
+ * input gradient) run on BF16 matrix cores with FP32 accumulation (weights
+ * and activations rounded to BF16, gradients FP32); the rest is FP32.
+ *
+ * radar_cnn_patches: patch n = f*k + i of frame f's periodogram P
+ *   (p_frame_stride floats apart, [m_pad][n_pad], powers of two >= 32) around
+ *   peak i: ln(max(P, 1e-12 P_c)) - ln P_c over rows row-16..row+15 and
+ *   columns r-16..r+15 (cyclic), P_c the peak cell; valid[n] = 1 if
+ *   i < n_peaks[f] (else the patch is zero).  patches [n_frames*k][32][32].
+ * radar_cnn_forward: out[b] = network(patches[b]), b < batch.
+ * radar_cnn_gradient: grad = dL/dtheta and *loss = L (device pointers) for
+ *   L = mean over the batch and both outputs of (network - labels)^2;
+ *   labels [batch][2].
+ * radar_cnn_adam: one Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias
+ *   correction for step >= 1) on theta with FP32 moments m, v.
+ * radar_cnn_train_step: radar_cnn_gradient then radar_cnn_adam.
+ * All arrays are device memory; ws is radar_cnn_workspace_size(batch, train)
+ * bytes (train = 0 for forward only).  Errors: RADAR_E_ARG for NULL pointers
+ * or batch outside [1, 65536], RADAR_E_UNSUPPORTED for grid sizes the patch
+ * extraction does not support, RADAR_E_WORKSPACE.
+ * ------------------------------------------------------------------------ */
+int32_t radar_cnn_param_count(void);
+size_t radar_cnn_workspace_size(int32_t batch, int32_t train);
+int radar_cnn_patches(const float *P, int64_t p_frame_stride, int32_t m_pad, int32_t n_pad, int32_t n_frames,
+                      int32_t k, const radar_peak *peaks, const int32_t *n_peaks, float *patches,
+                      int32_t *valid, void *hip_stream);
+int radar_cnn_forward(const float *theta, const float *patches, int32_t batch, float *out,
+                      void *ws, size_t ws_bytes, void *hip_stream);
+int radar_cnn_gradient(const float *theta, const float *patches, const float *labels, int32_t batch,
+                       float *grad, float *loss, void *ws, size_t ws_bytes, void *hip_stream);
+int radar_cnn_adam(float *theta, const float *grad, float *m, float *v, int32_t step, float lr,
+                   void *hip_stream);
+int radar_cnn_train_step(float *theta, float *m, float *v, int32_t step, float lr, const float *patches,
+                         const float *labels, int32_t batch, float *loss, void *ws, size_t ws_bytes,
+                         void *hip_stream);
+
+/* ------------------------------------------------------------------------
  * Stage timing -- a profiling aid, off by default.
  *
  * radar_timing_start(max_launches) creates HIP events for up to max_launches

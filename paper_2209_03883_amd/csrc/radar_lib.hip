@@ -19,6 +19,7 @@ __device__ float2 g_radar_tw[RADAR_TW_ENTRIES];
 #include "k_peaks.hpp"
 #include "k_refine.hpp"
 #include "k_sft.hpp"
+#include "k_cnn.hpp"
 
 namespace {
 
@@ -402,6 +403,136 @@ int launch_sft_q(const radar::K5Args& a5, const radar::K6Args& a6, int F, hipStr
   slot = timer_open(RADAR_STAGE_SFT_DECODE, s);
   hipLaunchKernelGGL(radar::k6_sft_decode<Q>, dim3(F), dim3(radar::kSftDecodeThreads), 0, s, a6);
   timer_close(RADAR_STAGE_SFT_DECODE, slot, s);
+  RADAR_HIP_CHECK(hipGetLastError());
+  return RADAR_OK;
+}
+
+// ------------------------------------------------------------------- CNN
+struct CnnWs {
+  size_t wb, a1, a2, a3, a4, z5, out, dout, dz5, dz4, dz3, dz2, dz1, part, grad, total;
+};
+
+CnnWs cnn_ws_layout(int B, bool train) {
+  CnnWs w{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  const size_t b = (size_t)B;
+  w.wb = take(3 * 9216 * sizeof(__bf16));
+  w.a1 = take(b * 32768 * sizeof(__bf16));
+  w.a2 = take(b * 8192 * sizeof(__bf16));
+  w.a3 = take(b * 8192 * sizeof(__bf16));
+  w.a4 = take(b * 2048 * sizeof(__bf16));
+  w.z5 = take(b * 10 * sizeof(float));
+  w.out = take(b * 2 * sizeof(float));
+  if (train) {
+    w.dout = take(b * 2 * sizeof(float));
+    w.dz5 = take(b * 10 * sizeof(float));
+    w.dz4 = take(b * 2048 * sizeof(float));
+    w.dz3 = take(b * 8192 * sizeof(float));
+    w.dz2 = take(b * 8192 * sizeof(float));
+    w.dz1 = take(b * 32768 * sizeof(float));
+    w.part = take(b * 9248 * sizeof(float));
+    w.grad = take(radar::kCnnParams * sizeof(float));
+  }
+  w.total = off;
+  return w;
+}
+
+template <int S>
+size_t wgrad_lds(int H, int W) {
+  return (size_t)(H / S) * (W / S) * 32 * sizeof(float) + (size_t)(H + 2) * (W + 2) * 32 * sizeof(__bf16);
+}
+
+int cnn_attrs_done = 0;
+int cnn_setup() {
+  if (cnn_attrs_done) return RADAR_OK;
+  const int need = (int)wgrad_lds<2>(32, 32);  // the largest weight-gradient tile (conv2)
+  if (hipFuncSetAttribute(reinterpret_cast<const void*>(radar::k_conv_wgrad<2>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, need) != hipSuccess)
+    return RADAR_E_HIP;
+  cnn_attrs_done = 1;
+  return RADAR_OK;
+}
+
+int cnn_forward(const float* theta, const float* x, int B, const CnnWs& w, char* ws, float* out, hipStream_t s) {
+  __bf16* wb = reinterpret_cast<__bf16*>(ws + w.wb);
+  __bf16* a1 = reinterpret_cast<__bf16*>(ws + w.a1);
+  __bf16* a2 = reinterpret_cast<__bf16*>(ws + w.a2);
+  __bf16* a3 = reinterpret_cast<__bf16*>(ws + w.a3);
+  __bf16* a4 = reinterpret_cast<__bf16*>(ws + w.a4);
+  float* z5 = reinterpret_cast<float*>(ws + w.z5);
+  hipLaunchKernelGGL(radar::k_cnn_weights_bf16, dim3((3 * 9216 + 255) / 256), dim3(256), 0, s, theta, wb);
+  hipLaunchKernelGGL(radar::k_conv1_fwd, dim3(B * 4), dim3(256), 0, s, x, theta, a1, B);
+  hipLaunchKernelGGL((radar::k_conv_mfma<2, 0>), dim3((B * 8 + 3) / 4), dim3(256), 0, s, a1, wb,
+                     theta + radar::kOffConv2B, nullptr, a2, B, 32, 32);
+  hipLaunchKernelGGL((radar::k_conv_mfma<1, 0>), dim3((B * 8 + 3) / 4), dim3(256), 0, s, a2, wb + 9216,
+                     theta + radar::kOffConv3B, nullptr, a3, B, 16, 16);
+  hipLaunchKernelGGL((radar::k_conv_mfma<2, 0>), dim3((B * 2 + 3) / 4), dim3(256), 0, s, a3, wb + 2 * 9216,
+                     theta + radar::kOffConv4B, nullptr, a4, B, 16, 16);
+  hipLaunchKernelGGL(radar::k_fc_fwd, dim3(B), dim3(256), 0, s, a4, theta, z5, out);
+  RADAR_HIP_CHECK(hipGetLastError());
+  return RADAR_OK;
+}
+
+int cnn_gradient(const float* theta, const float* x, const float* labels, int B, const CnnWs& w, char* ws,
+                 float* grad, float* loss, hipStream_t s) {
+  float* out = reinterpret_cast<float*>(ws + w.out);
+  int rc = cnn_forward(theta, x, B, w, ws, out, s);
+  if (rc != RADAR_OK) return rc;
+  const __bf16* wb = reinterpret_cast<const __bf16*>(ws + w.wb);
+  const __bf16* a1 = reinterpret_cast<const __bf16*>(ws + w.a1);
+  const __bf16* a2 = reinterpret_cast<const __bf16*>(ws + w.a2);
+  const __bf16* a3 = reinterpret_cast<const __bf16*>(ws + w.a3);
+  const __bf16* a4 = reinterpret_cast<const __bf16*>(ws + w.a4);
+  const float* z5 = reinterpret_cast<const float*>(ws + w.z5);
+  float* dout = reinterpret_cast<float*>(ws + w.dout);
+  float* dz5 = reinterpret_cast<float*>(ws + w.dz5);
+  float* dz4 = reinterpret_cast<float*>(ws + w.dz4);
+  float* dz3 = reinterpret_cast<float*>(ws + w.dz3);
+  float* dz2 = reinterpret_cast<float*>(ws + w.dz2);
+  float* dz1 = reinterpret_cast<float*>(ws + w.dz1);
+  float* part = reinterpret_cast<float*>(ws + w.part);
+  hipLaunchKernelGGL(radar::k_mse, dim3(1), dim3(256), 0, s, out, labels, B, dout, loss);
+  hipLaunchKernelGGL(radar::k_fc2_bwd, dim3(1), dim3(256), 0, s, dout, z5, theta, B, dz5, grad);
+  hipLaunchKernelGGL(radar::k_fc1_wgrad, dim3((20490 + 255) / 256), dim3(256), 0, s, a4, dz5, B, grad);
+  hipLaunchKernelGGL(radar::k_fc1_dgrad, dim3(B * 8), dim3(256), 0, s, a4, dz5, theta, B, dz4);
+  // conv4 (16x16 -> 8x8)
+  hipLaunchKernelGGL((radar::k_conv_wgrad<2>), dim3(B), dim3(256), wgrad_lds<2>(16, 16), s, a3, dz4, part, 16, 16);
+  hipLaunchKernelGGL(radar::k_sum_partials, dim3((9248 + 255) / 256), dim3(256), 0, s, part, B, 9248, grad,
+                     radar::kOffConv4W);
+  hipLaunchKernelGGL((radar::k_conv_mfma<2, 1>), dim3((B * 8 + 3) / 4), dim3(256), 0, s, dz4, wb + 2 * 9216,
+                     nullptr, a3, dz3, B, 16, 16);
+  // conv3 (16x16 -> 16x16)
+  hipLaunchKernelGGL((radar::k_conv_wgrad<1>), dim3(B), dim3(256), wgrad_lds<1>(16, 16), s, a2, dz3, part, 16, 16);
+  hipLaunchKernelGGL(radar::k_sum_partials, dim3((9248 + 255) / 256), dim3(256), 0, s, part, B, 9248, grad,
+                     radar::kOffConv3W);
+  hipLaunchKernelGGL((radar::k_conv_mfma<1, 1>), dim3((B * 8 + 3) / 4), dim3(256), 0, s, dz3, wb + 9216, nullptr,
+                     a2, dz2, B, 16, 16);
+  // conv2 (32x32 -> 16x16)
+  hipLaunchKernelGGL((radar::k_conv_wgrad<2>), dim3(B), dim3(256), wgrad_lds<2>(32, 32), s, a1, dz2, part, 32, 32);
+  hipLaunchKernelGGL(radar::k_sum_partials, dim3((9248 + 255) / 256), dim3(256), 0, s, part, B, 9248, grad,
+                     radar::kOffConv2W);
+  hipLaunchKernelGGL((radar::k_conv_mfma<2, 1>), dim3((B * 32 + 3) / 4), dim3(256), 0, s, dz2, wb, nullptr, a1,
+                     dz1, B, 32, 32);
+  // conv1
+  hipLaunchKernelGGL(radar::k_conv1_wgrad, dim3(B), dim3(256), 0, s, x, dz1, part);
+  hipLaunchKernelGGL(radar::k_sum_partials, dim3((320 + 255) / 256), dim3(256), 0, s, part, B, 320, grad,
+                     radar::kOffConv1W);
+  RADAR_HIP_CHECK(hipGetLastError());
+  return RADAR_OK;
+}
+
+int cnn_adam(float* theta, const float* grad, float* m, float* v, int step, float lr, hipStream_t s) {
+  const double b1 = 0.9, b2 = 0.999;
+  const float c1 = (float)(1.0 / (1.0 - std::pow(b1, step)));
+  const float c2 = (float)(1.0 / (1.0 - std::pow(b2, step)));
+  hipLaunchKernelGGL(radar::k_adam, dim3((radar::kCnnParams + 255) / 256), dim3(256), 0, s, theta, grad, m, v,
+                     radar::kCnnParams, lr, (float)b1, (float)b2, (float)(1.0 - b1), (float)(1.0 - b2), 1e-8f, c1,
+                     c2);
   RADAR_HIP_CHECK(hipGetLastError());
   return RADAR_OK;
 }
@@ -927,6 +1058,69 @@ void radar_batch_destroy(radar_batch* b) {
   if (b->exec) hipGraphExecDestroy(b->exec);
   if (b->graph) hipGraphDestroy(b->graph);
   delete b;
+}
+
+int32_t radar_cnn_param_count(void) { return radar::kCnnParams; }
+
+size_t radar_cnn_workspace_size(int32_t batch, int32_t train) {
+  if (batch < 1 || batch > 65536) return 0;
+  return cnn_ws_layout(batch, train != 0).total;
+}
+
+int radar_cnn_patches(const float* P, int64_t p_frame_stride, int32_t m_pad, int32_t n_pad, int32_t n_frames,
+                      int32_t k, const radar_peak* peaks, const int32_t* n_peaks, float* patches, int32_t* valid,
+                      void* hip_stream) {
+  if (!P || !peaks || !n_peaks || !patches) return RADAR_E_ARG;
+  if (n_frames < 1 || k < 1 || k > 64 || (int64_t)n_frames * k > 65535 * 16) return RADAR_E_ARG;
+  if (!is_pow2(m_pad) || !is_pow2(n_pad) || m_pad < 32 || n_pad < 32 || m_pad > 16384 || n_pad > 16384)
+    return RADAR_E_UNSUPPORTED;
+  if (n_frames > 1 && p_frame_stride < (int64_t)m_pad * n_pad) return RADAR_E_ARG;
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  hipLaunchKernelGGL(radar::k_cnn_patches, dim3(n_frames * k), dim3(256), 0, s, P, p_frame_stride, m_pad, n_pad, k,
+                     peaks, n_peaks, patches, valid);
+  RADAR_HIP_CHECK(hipGetLastError());
+  return RADAR_OK;
+}
+
+int radar_cnn_forward(const float* theta, const float* patches, int32_t batch, float* out, void* ws, size_t ws_bytes,
+                      void* hip_stream) {
+  if (!theta || !patches || !out || !ws || batch < 1 || batch > 65536) return RADAR_E_ARG;
+  const CnnWs w = cnn_ws_layout(batch, false);
+  if (ws_bytes < w.total) return RADAR_E_WORKSPACE;
+  return cnn_forward(theta, patches, batch, w, static_cast<char*>(ws), out, reinterpret_cast<hipStream_t>(hip_stream));
+}
+
+int radar_cnn_gradient(const float* theta, const float* patches, const float* labels, int32_t batch, float* grad,
+                       float* loss, void* ws, size_t ws_bytes, void* hip_stream) {
+  if (!theta || !patches || !labels || !grad || !ws || batch < 1 || batch > 65536) return RADAR_E_ARG;
+  const CnnWs w = cnn_ws_layout(batch, true);
+  if (ws_bytes < w.total) return RADAR_E_WORKSPACE;
+  int rc = cnn_setup();
+  if (rc != RADAR_OK) return rc;
+  return cnn_gradient(theta, patches, labels, batch, w, static_cast<char*>(ws), grad, loss,
+                      reinterpret_cast<hipStream_t>(hip_stream));
+}
+
+int radar_cnn_adam(float* theta, const float* grad, float* m, float* v, int32_t step, float lr, void* hip_stream) {
+  if (!theta || !grad || !m || !v || step < 1 || !(lr > 0.0f)) return RADAR_E_ARG;
+  return cnn_adam(theta, grad, m, v, step, lr, reinterpret_cast<hipStream_t>(hip_stream));
+}
+
+int radar_cnn_train_step(float* theta, float* m, float* v, int32_t step, float lr, const float* patches,
+                         const float* labels, int32_t batch, float* loss, void* ws, size_t ws_bytes,
+                         void* hip_stream) {
+  if (!theta || !m || !v || !patches || !labels || !ws || batch < 1 || batch > 65536 || step < 1 || !(lr > 0.0f))
+    return RADAR_E_ARG;
+  const CnnWs w = cnn_ws_layout(batch, true);
+  if (ws_bytes < w.total) return RADAR_E_WORKSPACE;
+  int rc = cnn_setup();
+  if (rc != RADAR_OK) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  char* wsb = static_cast<char*>(ws);
+  float* grad = reinterpret_cast<float*>(wsb + w.grad);
+  rc = cnn_gradient(theta, patches, labels, batch, w, wsb, grad, loss, s);
+  if (rc != RADAR_OK) return rc;
+  return cnn_adam(theta, grad, m, v, step, lr, s);
 }
 
 int radar_timing_start(int32_t max_launches) {

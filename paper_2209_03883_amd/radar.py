@@ -35,6 +35,8 @@ EXPORTED = (
     "radar_sft_default", "radar_fps_sft_workspace_size", "radar_fps_sft",
     "radar_batch_workspace_size", "radar_batch_create", "radar_batch_launch", "radar_batch_info",
     "radar_batch_destroy",
+    "radar_cnn_param_count", "radar_cnn_workspace_size", "radar_cnn_patches", "radar_cnn_forward",
+    "radar_cnn_gradient", "radar_cnn_adam", "radar_cnn_train_step",
 )
 BATCH_GRAPH, BATCH_TUNE = 1, 2
 STAGES = ("taps", "doppler", "range", "peaks", "refine", "sft_slices", "sft_decode")
@@ -121,6 +123,20 @@ def lib() -> ctypes.CDLL:
     L.radar_batch_info.argtypes = [vp, i32, ip, ip, ip, ip, ip]
     L.radar_batch_destroy.restype = None
     L.radar_batch_destroy.argtypes = [vp]
+    fp = ctypes.c_void_p
+    L.radar_cnn_param_count.restype = i32
+    L.radar_cnn_workspace_size.restype = sz
+    L.radar_cnn_workspace_size.argtypes = [i32, i32]
+    L.radar_cnn_patches.restype = ctypes.c_int
+    L.radar_cnn_patches.argtypes = [fp, i64, i32, i32, i32, i32, vp, vp, fp, vp, vp]
+    L.radar_cnn_forward.restype = ctypes.c_int
+    L.radar_cnn_forward.argtypes = [fp, fp, i32, fp, vp, sz, vp]
+    L.radar_cnn_gradient.restype = ctypes.c_int
+    L.radar_cnn_gradient.argtypes = [fp, fp, fp, i32, fp, fp, vp, sz, vp]
+    L.radar_cnn_adam.restype = ctypes.c_int
+    L.radar_cnn_adam.argtypes = [fp, fp, fp, fp, i32, ctypes.c_float, vp]
+    L.radar_cnn_train_step.restype = ctypes.c_int
+    L.radar_cnn_train_step.argtypes = [fp, fp, fp, i32, ctypes.c_float, fp, fp, i32, fp, vp, sz, vp]
     L.radar_timing_start.restype = ctypes.c_int
     L.radar_timing_start.argtypes = [i32]
     L.radar_timing_stop.restype = ctypes.c_int
@@ -420,6 +436,84 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------ CNN
+def _f32(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float32 CUDA tensor")
+    return t
+
+
+class CnnWorkspace:
+    """Reusable device workspace of the CNN calls for batches up to `batch`."""
+
+    def __init__(self, batch: int, train: bool, device):
+        n = lib().radar_cnn_workspace_size(int(batch), int(bool(train)))
+        if n == 0:
+            raise RadarError(RADAR_E_ARG, "radar_cnn_workspace_size")
+        self.batch, self.train = int(batch), bool(train)
+        self.buf = new_workspace(n, device)
+
+
+def _cnn_ws(ws, batch, train, device):
+    if ws is None or ws.batch < batch or (train and not ws.train):
+        ws = CnnWorkspace(batch, train, device)
+    return ws
+
+
+def cnn_param_count() -> int:
+    return int(lib().radar_cnn_param_count())
+
+
+def cnn_patches(P: torch.Tensor, peaks: torch.Tensor, n_peaks: torch.Tensor, stream=None):
+    """radar_cnn_patches: P (F, M', N') float32, peaks (F, k, 5) -> (patches (F*k, 32, 32), valid (F*k,))."""
+    P = _f32(P if P.dim() == 3 else P.unsqueeze(0), "P")
+    F, mp, nq = P.shape
+    k = peaks.shape[1]
+    out = torch.empty((F * k, 32, 32), dtype=torch.float32, device=P.device)
+    valid = torch.empty(F * k, dtype=torch.int32, device=P.device)
+    _check(lib().radar_cnn_patches(P.data_ptr(), mp * nq, mp, nq, F, k, peaks.data_ptr(), n_peaks.data_ptr(),
+                                   out.data_ptr(), valid.data_ptr(), _stream_ptr(stream)), "radar_cnn_patches")
+    return out, valid
+
+
+def cnn_forward(theta: torch.Tensor, patches: torch.Tensor, *, workspace: CnnWorkspace | None = None, stream=None):
+    _f32(theta, "theta")
+    _f32(patches, "patches")
+    B = patches.shape[0]
+    ws = _cnn_ws(workspace, B, False, patches.device)
+    out = torch.empty((B, 2), dtype=torch.float32, device=patches.device)
+    _check(lib().radar_cnn_forward(theta.data_ptr(), patches.data_ptr(), B, out.data_ptr(), ws.buf.data_ptr(),
+                                   ws.buf.numel(), _stream_ptr(stream)), "radar_cnn_forward")
+    return out
+
+
+def cnn_gradient(theta, patches, labels, *, workspace: CnnWorkspace | None = None, stream=None):
+    for t, n in ((theta, "theta"), (patches, "patches"), (labels, "labels")):
+        _f32(t, n)
+    B = patches.shape[0]
+    ws = _cnn_ws(workspace, B, True, patches.device)
+    grad = torch.empty_like(theta)
+    loss = torch.empty(1, dtype=torch.float32, device=theta.device)
+    _check(lib().radar_cnn_gradient(theta.data_ptr(), patches.data_ptr(), labels.data_ptr(), B, grad.data_ptr(),
+                                    loss.data_ptr(), ws.buf.data_ptr(), ws.buf.numel(), _stream_ptr(stream)),
+           "radar_cnn_gradient")
+    return grad, loss
+
+
+def cnn_adam(theta, grad, m, v, step: int, lr: float, stream=None):
+    _check(lib().radar_cnn_adam(theta.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(), int(step),
+                                float(lr), _stream_ptr(stream)), "radar_cnn_adam")
+
+
+def cnn_train_step(theta, m, v, step: int, lr: float, patches, labels, loss, *, workspace: CnnWorkspace,
+                   stream=None):
+    B = patches.shape[0]
+    _check(lib().radar_cnn_train_step(theta.data_ptr(), m.data_ptr(), v.data_ptr(), int(step), float(lr),
+                                      patches.data_ptr(), labels.data_ptr(), B, loss.data_ptr(),
+                                      workspace.buf.data_ptr(), workspace.buf.numel(), _stream_ptr(stream)),
+           "radar_cnn_train_step")
 
 
 def timing_start(max_launches: int):

@@ -1,0 +1,169 @@
+"""GPU parity of the CNN refiner's kernels against the FP64 oracle, through
+the C ABI, and a training run showing what the network gains.
+
+Tolerances.  The GPU rounds the conv2..conv4 weights and every activation
+to BF16 (relative step 2^-8) and gathers the output gradients into BF16
+operands; the oracle is given the same BF16-rounded weights and computes
+everything else in FP64.  Four rounded layers give output and gradient
+errors of a few parts in a thousand of the largest component; the bounds
+below (normwise: max |gpu - ref| / max |ref|) leave a factor of about ten.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import cnn_oracle as C
+from oracle import radar_oracle as O
+from synth import cnn_init
+from synth import frames as S
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+radar = pytest.importorskip("paper_2209_03883_amd.radar")
+
+FWD_TOL = 3e-2
+GRAD_TOL = 5e-2
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    radar.lib()
+
+
+def _bf16(a):
+    return torch.from_numpy(np.asarray(a, np.float32)).to(torch.bfloat16).to(torch.float32).numpy().astype(np.float64)
+
+
+def _theta(seed):
+    th = cnn_init.init_params(seed).astype(np.float64)
+    rng = np.random.default_rng(seed)
+    p = C.unflatten(th)
+    for name, _ in C.param_shapes():  # non-zero biases so every bias path is exercised
+        if name.endswith(".b"):
+            p[name][:] = rng.uniform(-0.05, 0.05, p[name].shape)
+    return C.flatten(p).astype(np.float32)
+
+
+def _ref_params(theta):
+    p = C.unflatten(theta.astype(np.float64))
+    for name in ("conv2.w", "conv3.w", "conv4.w"):
+        p[name] = _bf16(p[name])
+    return p
+
+
+def _patches(B, seed):
+    # log-periodogram-like patches: a peaked lobe plus noise, centre at 0
+    rng = np.random.default_rng(seed)
+    y, x = np.meshgrid(np.arange(32) - 16, np.arange(32) - 16, indexing="ij")
+    out = np.empty((B, 32, 32))
+    for b in range(B):
+        dy, dx = rng.uniform(-0.5, 0.5, 2)
+        lobe = -0.4 * ((y - dy) ** 2 + (x - dx) ** 2) / 4.0
+        out[b] = np.maximum(lobe + 0.3 * rng.standard_normal((32, 32)), -27.6) - lobe[16, 16]
+    return out.astype(np.float32)
+
+
+def _norm_err(a, b):
+    return float(np.max(np.abs(np.asarray(a, np.float64) - b)) / max(np.max(np.abs(b)), 1e-30))
+
+
+def test_cnn_forward_matches_oracle():
+    theta = _theta(1)
+    x = _patches(64, 2)
+    say("cnn forward, 64 patches")
+    out = radar.cnn_forward(torch.from_numpy(theta).cuda(), torch.from_numpy(x).cuda()).cpu().numpy()
+    ref, _ = C.forward(_ref_params(theta), x.astype(np.float64))
+    err = _norm_err(out, ref)
+    say(f"forward normwise error {err:.2e}")
+    assert err <= FWD_TOL
+
+
+@pytest.mark.parametrize("B", [32, 256])
+def test_cnn_gradient_matches_oracle(B):
+    theta = _theta(3)
+    x = _patches(B, 4)
+    lab = np.random.default_rng(5).uniform(-2, 2, (B, 2)).astype(np.float32)
+    say(f"cnn gradient, batch {B}")
+    g, loss = radar.cnn_gradient(torch.from_numpy(theta).cuda(), torch.from_numpy(x).cuda(),
+                                 torch.from_numpy(lab).cuda())
+    g = g.cpu().numpy()
+    p = _ref_params(theta)
+    out, cache = C.forward(p, x.astype(np.float64))
+    L, dout = C.mse(out, lab)
+    gr = C.flatten(C.backward(p, cache, dout))
+    assert float(loss.cpu()[0]) == pytest.approx(L, rel=FWD_TOL)
+    off = 0
+    worst = 0.0
+    for name, shape in C.param_shapes():
+        n = int(np.prod(shape))
+        err = _norm_err(g[off:off + n], gr[off:off + n])
+        worst = max(worst, err)
+        assert err <= GRAD_TOL, (name, err)
+        off += n
+    say(f"gradient: worst normwise error per tensor {worst:.2e}")
+
+
+def test_cnn_adam_matches_oracle():
+    rng = np.random.default_rng(6)
+    n = radar.cnn_param_count()
+    th, g = rng.standard_normal(n).astype(np.float32), rng.standard_normal(n).astype(np.float32)
+    m, v = (0.1 * rng.standard_normal(n)).astype(np.float32), rng.uniform(0, 0.1, n).astype(np.float32)
+    t = [torch.from_numpy(a.copy()).cuda() for a in (th, g, m, v)]
+    radar.cnn_adam(t[0], t[1], t[2], t[3], 7, 1e-3)
+    r_th, r_m, r_v = C.adam_step(th.astype(np.float64), g.astype(np.float64), m.astype(np.float64),
+                                 v.astype(np.float64), 7, 1e-3)
+    # FP32 against FP64: each moment within a few FP32 roundings of its two terms
+    eps = np.finfo(np.float32).eps
+    m64, v64, g64 = m.astype(np.float64), v.astype(np.float64), g.astype(np.float64)
+    bm = 4 * eps * (0.9 * np.abs(m64) + 0.1 * np.abs(g64))
+    bv = 4 * eps * (0.999 * v64 + 0.001 * g64 * g64)
+    assert np.all(np.abs(t[2].cpu().numpy() - r_m) <= bm)
+    assert np.all(np.abs(t[3].cpu().numpy() - r_v) <= bv)
+    np.testing.assert_allclose(t[0].cpu().numpy(), r_th, rtol=1e-6, atol=1e-7)
+
+
+def test_cnn_patches_match_oracle():
+    frames = [S.make_frame(S.spec_small(snr_db=0.0), 1, i) for i in range(3)]
+    Ps = [O.frame_periodogram(f.Y, f.A, n_pad=1024, m_pad=256, n_cp=32, zc_root=1).astype(np.float32)
+          for f in frames]
+    k = 3
+    peaks = np.zeros((3, k, 5), np.int32)
+    npk = np.zeros(3, np.int32)
+    for f, P in enumerate(Ps):
+        pk = O.find_peaks(P.astype(np.float64), k)
+        npk[f] = len(pk) - (1 if f == 2 else 0)  # frame 2 reports one peak fewer
+        for i, (row, r, _) in enumerate(pk):
+            peaks[f, i, 0], peaks[f, i, 1] = row - 128, r
+    say("cnn patches")
+    pt, valid = radar.cnn_patches(torch.from_numpy(np.stack(Ps)).cuda(), torch.from_numpy(peaks).cuda(),
+                                  torch.from_numpy(npk).cuda())
+    pt, valid = pt.cpu().numpy(), valid.cpu().numpy()
+    for f, P in enumerate(Ps):
+        for i in range(k):
+            n = f * k + i
+            if i >= npk[f]:
+                assert valid[n] == 0 and np.all(pt[n] == 0)
+                continue
+            assert valid[n] == 1
+            ref = C.patch_input(P.astype(np.float64), int(peaks[f, i, 0]) + 128, int(peaks[f, i, 1]))
+            np.testing.assert_allclose(pt[n], ref, atol=2e-5)
+
+
+def test_cnn_training_gains_over_grid_cells():
+    from paper_2209_03883_amd import cnn_train as T
+
+    say("cnn training data")
+    train = T.make_patches(1536, 1)
+    held = T.make_patches(384, 2)
+    say(f"train {train.patches.shape[0]} patches ({train.dropped} dropped), held-out {held.patches.shape[0]}")
+    theta, losses = T.train(cnn_init.init_params(0), train, 1500)
+    say(f"loss first 20 steps {losses[:20].mean():.4f}, last 100 {losses[-100:].mean():.4f}")
+    rep = T.rmse_report(theta, held)
+    say(f"held-out RMSE (range, Doppler) cells: {rep}")
+    assert np.all(np.isfinite(losses)) and losses[-100:].mean() < 0.5 * losses[:20].mean()
+    # the trained network places held-out peaks closer than their grid cells
+    assert rep["cnn"][0] < 0.7 * rep["grid"][0] and rep["cnn"][1] < 0.7 * rep["grid"][1]
