@@ -158,6 +158,47 @@ def time_extras(radar, torch, Yd, Ad, cfg, ws, peaks, n_peaks, status, stream, B
                                              for k in ("taps", "doppler", "range", "peaks")}
         del P
 
+    # the CNN refiner: inference on 8192 patches cut from the benchmark frames'
+    # periodograms around their peaks (the frames' 32 x 8 patches, tiled), and
+    # one training step of 256 patches
+    import numpy as np
+    from synth import cnn_init
+
+    P = torch.empty((B, cfg.m_pad, cfg.n_pad), dtype=torch.float32, device=Yd.device)
+    radar.frame_process(Yd, Ad, cfg, K, P=P, workspace=ws, peaks=peaks, n_peaks=n_peaks, status=status,
+                        stream=stream)
+    pat, _ = radar.cnn_patches(P, peaks, n_peaks)
+    del P
+    nb = 8192
+    pat = pat.repeat((nb + pat.shape[0] - 1) // pat.shape[0], 1, 1)[:nb].contiguous()
+    theta = torch.from_numpy(cnn_init.init_params(0)).to(Yd.device)
+    cws = radar.CnnWorkspace(nb, False, Yd.device)
+    for _ in range(warmup):
+        radar.cnn_forward(theta, pat, workspace=cws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        radar.cnn_forward(theta, pat, workspace=cws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    flops = 11247656  # per patch: conv1 589824, conv2 4718592, conv3 4718592, conv4 1179648, dense 41000
+    out["cnn_inference"] = {"patches": nb, "ms": dt * 1e3, "patches_per_s": nb / dt,
+                            "tflops": nb * flops / dt / 1e12, "mfma_bf16_peak_tflops": 2500.0}
+    tws = radar.CnnWorkspace(256, True, Yd.device)
+    lab = torch.zeros((256, 2), dtype=torch.float32, device=Yd.device)
+    mom, vel = torch.zeros_like(theta), torch.zeros_like(theta)
+    loss = torch.empty(1, dtype=torch.float32, device=Yd.device)
+    xb = pat[:256].contiguous()
+    for t in range(warmup):
+        radar.cnn_train_step(theta, mom, vel, t + 1, 1e-3, xb, lab, loss, workspace=tws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(steps):
+        radar.cnn_train_step(theta, mom, vel, warmup + t + 1, 1e-3, xb, lab, loss, workspace=tws)
+    torch.cuda.synchronize()
+    out["cnn_train_step_ms_batch256"] = (time.perf_counter() - t0) / steps * 1e3
+    del np
+
     sft = radar.sft_desc(K)
     ws_sft = radar.new_workspace(radar.sft_workspace_bytes(cfg, sft, B), Yd.device)
     for _ in range(warmup):
