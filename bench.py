@@ -34,7 +34,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--frames", type=int, default=32, help="frames per step")
+    ap.add_argument("--frames", type=int, default=128, help="frames per step")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="CPU work budget for the oracle baseline (0 disables it)")
     ap.add_argument("--no-extras", action="store_true",
@@ -76,9 +76,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the range kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel sources."""
+def measured_traffic(frames):
+    """HBM bytes of one range-kernel launch over `frames` frames, from the
+    committed rocprofv3 counter summary (per-frame bytes of the launch it
+    measured), if that was taken on the current kernel sources."""
     path = os.path.join(ROOT, "profiles", "k3_range_power_full_frame_traffic.json")
     try:
         with open(path) as fh:
@@ -87,7 +88,7 @@ def measured_traffic():
         return None
     if rec.get("source_hash") != kernel_source_hash():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec["hbm_bytes_per_launch"] / rec["frames_per_launch"] * frames
 
 
 def cpu_baseline(frames, budget_s):
@@ -325,10 +326,13 @@ def main():
     torch.cuda.set_device(dev)
     B = args.frames
     print(f"[bench] generating {B} frames", file=sys.stderr, flush=True)
-    frames = [S.make_frame(S.spec_full(snr_db=0.0), 2, i) for i in range(B)]
-    Y, A = S.frames_to_complex64(frames)
-    Yd = torch.from_numpy(Y).to(dev)
-    Ad = torch.from_numpy(A).to(dev)
+    # the frames are drawn on the GPU (same recipe and seeds as the host generator)
+    from synth import frames_torch as G
+
+    drawn = [G.make_frame(S.spec_full(snr_db=0.0), 2, i, device=dev) for i in range(B)]
+    Yd = torch.stack([d[0] for d in drawn])
+    Ad = torch.stack([d[1] for d in drawn])
+    del drawn
     cfg = radar.Config(N, M, PAD * N, PAD * M, NCP, zc_root=ROOT_ZC, window=radar.WIN_HANN)
     P = torch.empty((B, PAD * M, PAD * N), dtype=torch.float32, device=dev)
     ws = radar.new_workspace(radar.workspace_bytes(cfg, B, K), dev)
@@ -374,7 +378,7 @@ def main():
     # U [M'][N_cp] complex64 and write P [M'][N'] float32, per frame
     k3_bytes = B * (PAD * M * NCP * 8 + PAD * M * PAD * N * 4)
     achieved = k3_bytes / (k3_ms * 1e-3) / 1e9
-    traffic = measured_traffic()
+    traffic = measured_traffic(B)
 
     out = {
         "metric": METRIC,
@@ -411,7 +415,8 @@ def main():
     }
     if args.cpu_seconds > 0:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(frames[:2], args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline([S.make_frame(S.spec_full(snr_db=0.0), 2, i) for i in range(2)],
+                                           args.cpu_seconds)
     print(json.dumps(out), flush=True)
     del np
 
