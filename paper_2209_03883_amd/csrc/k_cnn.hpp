@@ -372,6 +372,184 @@ __global__ void __launch_bounds__(256) k_fc1_dgrad(const __bf16* a4, const float
   dz4[t] = bf2f(a4[t]) > 0.0f ? s : 0.0f;
 }
 
+// ------------------------------------------------- fused inference kernel
+// The whole network for one patch per work-group iteration, every activation
+// resident in LDS (BF16, NHWC, zero halo for the next layer's padding) and
+// every weight resident in registers across patches:
+//   s_in [34][34] FP32 input, s_a1 [34][34][CP], s_a2 [18][18][CP],
+//   s_a3 [18][18][CP], s_a4 [8][8][32]; pixels CP = 40 channels (80 bytes, an
+//   odd multiple of 16) apart, so the 16-byte operand reads of 16 consecutive
+//   pixels fall in distinct bank groups (2-way for the stride-2 layers).
+// Four waves, one per SIMD.  conv1 runs on the matrix cores too: K = 9 taps
+// padded to 16, with the input and weights split into BF16 hi + lo parts
+// (hi*hi + hi*lo + lo*hi in FP32), so its outputs match an FP32 convolution
+// to about 2^-16.  conv2..conv4 are 32-channel x 32-pixel tiles, two per wave
+// at a time (independent accumulators hide the MFMA latency).  The dense layers
+// are work-group reductions with each thread's slice of the 2048 -> 10 weights in
+// registers.  Persistent: work-group b takes patches b, b + gridDim.x, ...;
+// only the patch (4 KB) and the two outputs touch HBM.
+constexpr int kFusedThreads = 256;
+struct FusedLds {
+  static constexpr int CP = 40;                 // channel stride of the padded activations
+  static constexpr int IN = 34 * 34;            // floats
+  static constexpr int A1 = 34 * 34 * CP;       // bf16
+  static constexpr int A2 = 18 * 18 * CP;
+  static constexpr int A3 = 18 * 18 * CP;
+  static constexpr int A4 = 8 * 8 * 32;
+  static constexpr size_t BYTES = IN * 4 + (size_t)(A1 + A2 + A3 + A4) * 2 + 4 * 11 * 4;
+};
+
+// 18 A fragments of one 32->32 layer (W[co][tap][ci], co = lane % 32)
+__device__ __forceinline__ void load_conv_frags(bf16x8_t (&a)[18], const __bf16* wb, int h, int i) {
+#pragma unroll
+  for (int q = 0; q < 18; ++q) {
+    const int tap = q >> 1, c0 = 16 * (q & 1) + 8 * h;
+    a[q] = *reinterpret_cast<const bf16x8_t*>(wb + (i * 9 + tap) * 32 + c0);
+  }
+}
+
+// Two 32-channel x 32-pixel tiles (pixels (oy0, ox0) and (oy1, ox1) of this
+// lane's column) of a 32->32 convolution from an LDS input with WP columns.
+template <int S>
+__device__ __forceinline__ void conv_tiles_lds(const __bf16* src, int WP, int oy0, int ox0, int oy1, int ox1,
+                                               const bf16x8_t (&a)[18], int h, f32x16_t& c0, f32x16_t& c1) {
+  c0 = {};
+  c1 = {};
+#pragma unroll
+  for (int q = 0; q < 18; ++q) {
+    const int tap = q >> 1, ky = tap / 3, kx = tap - ky * 3, ch = 16 * (q & 1) + 8 * h;
+    const bf16x8_t b0 =
+        *reinterpret_cast<const bf16x8_t*>(src + ((S * oy0 + ky) * WP + S * ox0 + kx) * FusedLds::CP + ch);
+    const bf16x8_t b1 =
+        *reinterpret_cast<const bf16x8_t*>(src + ((S * oy1 + ky) * WP + S * ox1 + kx) * FusedLds::CP + ch);
+    c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[q], b0, c0, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[q], b1, c1, 0, 0, 0);
+  }
+}
+
+// bias + ReLU of a tile into a BF16 NHWC destination pixel
+__device__ __forceinline__ void store_tile(const f32x16_t& c, const float* bias, __bf16* dst, int h) {
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int ch = 8 * g + 4 * h;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) dst[ch + j] = (__bf16)fmaxf(c[4 * g + j] + bias[ch + j], 0.0f);
+  }
+}
+
+__global__ void __launch_bounds__(kFusedThreads) k_cnn_fused(const float* x, const float* theta, const __bf16* wb,
+                                                             int B, float* out) {
+  extern __shared__ float fsm[];
+  float* s_in = fsm;
+  __bf16* s_a1 = reinterpret_cast<__bf16*>(s_in + FusedLds::IN);
+  __bf16* s_a2 = s_a1 + FusedLds::A1;
+  __bf16* s_a3 = s_a2 + FusedLds::A2;
+  __bf16* s_a4 = s_a3 + FusedLds::A3;
+  float* s_red = reinterpret_cast<float*>(s_a4 + FusedLds::A4);  // [4 waves][11]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, i = lane & 31;
+  // zero every buffer once: the halos stay zero, interiors are rewritten per patch
+  for (int t = tid; t < FusedLds::IN; t += kFusedThreads) s_in[t] = 0.0f;
+  for (int t = tid; t < FusedLds::A1 + FusedLds::A2 + FusedLds::A3 + FusedLds::A4; t += kFusedThreads)
+    s_a1[t] = (__bf16)0.0f;
+  // weights, kept in registers for every patch
+  bf16x8_t w1h, w1l;  // conv1 as A[co][tap], taps 9..15 zero
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int tap = 8 * h + e;
+    const float v = tap < 9 ? theta[kOffConv1W + i * 9 + tap] : 0.0f;
+    const __bf16 hi = (__bf16)v;
+    w1h[e] = hi;
+    w1l[e] = (__bf16)(v - (float)hi);
+  }
+  bf16x8_t a2[18], a3[18], a4[18];
+  load_conv_frags(a2, wb, h, i);
+  load_conv_frags(a3, wb + 9216, h, i);
+  load_conv_frags(a4, wb + 2 * 9216, h, i);
+  float wf[8][10];  // dense 2048 -> 10: inputs tid + 256 r, r < 8
+#pragma unroll
+  for (int r = 0; r < 8; ++r)
+#pragma unroll
+    for (int j = 0; j < 10; ++j) wf[r][j] = theta[kOffFc1W + j * 2048 + tid + 256 * r];
+  __syncthreads();
+
+  for (int p = blockIdx.x; p < B; p += gridDim.x) {
+    const float* xp = x + (int64_t)p * 1024;
+    for (int t = tid; t < 1024; t += kFusedThreads) s_in[((t >> 5) + 1) * 34 + (t & 31) + 1] = xp[t];
+    __syncthreads();
+    // conv1: 32 tiles of 32 pixels, 8 per wave; B[tap][pixel] = input shifted by the tap
+#pragma unroll 2
+    for (int tt = 0; tt < 8; ++tt) {
+      const int pix = (wave * 8 + tt) * 32 + i, y = pix >> 5, xx = pix & 31;
+      bf16x8_t bh, bl;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int tap = 8 * h + e;
+        const float v = tap < 9 ? s_in[(y + tap / 3) * 34 + xx + tap % 3] : 0.0f;
+        const __bf16 hi = (__bf16)v;
+        bh[e] = hi;
+        bl[e] = (__bf16)(v - (float)hi);
+      }
+      f32x16_t c = {};
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1l, bh, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1h, bl, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1h, bh, c, 0, 0, 0);
+      store_tile(c, theta + kOffConv1B, s_a1 + ((y + 1) * 34 + xx + 1) * FusedLds::CP, h);
+    }
+    __syncthreads();
+    f32x16_t c0, c1;
+    // conv2: 32x32 -> 16x16, 8 tiles, two per wave
+    {
+      const int p0 = (2 * wave) * 32 + i, p1 = p0 + 32;
+      conv_tiles_lds<2>(s_a1, 34, p0 >> 4, p0 & 15, p1 >> 4, p1 & 15, a2, h, c0, c1);
+      store_tile(c0, theta + kOffConv2B, s_a2 + (((p0 >> 4) + 1) * 18 + (p0 & 15) + 1) * FusedLds::CP, h);
+      store_tile(c1, theta + kOffConv2B, s_a2 + (((p1 >> 4) + 1) * 18 + (p1 & 15) + 1) * FusedLds::CP, h);
+    }
+    __syncthreads();
+    // conv3: 16x16 -> 16x16
+    {
+      const int p0 = (2 * wave) * 32 + i, p1 = p0 + 32;
+      conv_tiles_lds<1>(s_a2, 18, p0 >> 4, p0 & 15, p1 >> 4, p1 & 15, a3, h, c0, c1);
+      store_tile(c0, theta + kOffConv3B, s_a3 + (((p0 >> 4) + 1) * 18 + (p0 & 15) + 1) * FusedLds::CP, h);
+      store_tile(c1, theta + kOffConv3B, s_a3 + (((p1 >> 4) + 1) * 18 + (p1 & 15) + 1) * FusedLds::CP, h);
+    }
+    __syncthreads();
+    // conv4: 16x16 -> 8x8, 2 tiles (wave 0)
+    if (wave == 0) {
+      const int p0 = i, p1 = 32 + i;
+      conv_tiles_lds<2>(s_a3, 18, p0 >> 3, p0 & 7, p1 >> 3, p1 & 7, a4, h, c0, c1);
+      store_tile(c0, theta + kOffConv4B, s_a4 + p0 * 32, h);
+      store_tile(c1, theta + kOffConv4B, s_a4 + p1 * 32, h);
+    }
+    __syncthreads();
+    // dense 2048 -> 10 (ReLU) -> 2
+    float acc[10] = {};
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const float v = bf2f(s_a4[tid + 256 * r]);
+#pragma unroll
+      for (int j = 0; j < 10; ++j) acc[j] = fmaf(wf[r][j], v, acc[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < 10; ++j) {
+      float v = acc[j];
+#pragma unroll
+      for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
+      if (lane == 0) s_red[wave * 11 + j] = v;
+    }
+    __syncthreads();
+    if (tid < 2) {
+      float o = theta[kOffFc2B + tid];
+#pragma unroll
+      for (int j = 0; j < 10; ++j) {
+        const float z = theta[kOffFc1B + j] + s_red[j] + s_red[11 + j] + s_red[22 + j] + s_red[33 + j];
+        o = fmaf(theta[kOffFc2W + tid * 10 + j], fmaxf(z, 0.0f), o);
+      }
+      out[(int64_t)p * 2 + tid] = o;
+    }
+    __syncthreads();  // s_in and s_red are rewritten for the next patch
+  }
+}
+
 // -------------------------------------------------------------------- Adam
 // omb1 = 1 - b1 and omb2 = 1 - b2 are rounded once from exact values (1 - 0.999f
 // in FP32 would carry a 1.3e-5 relative error into every second moment).

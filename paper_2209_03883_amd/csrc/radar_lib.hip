@@ -422,22 +422,24 @@ CnnWs cnn_ws_layout(int B, bool train) {
   };
   const size_t b = (size_t)B;
   w.wb = take(3 * 9216 * sizeof(__bf16));
+  if (!train) {  // inference runs fused: every activation stays in LDS
+    w.total = off;
+    return w;
+  }
   w.a1 = take(b * 32768 * sizeof(__bf16));
   w.a2 = take(b * 8192 * sizeof(__bf16));
   w.a3 = take(b * 8192 * sizeof(__bf16));
   w.a4 = take(b * 2048 * sizeof(__bf16));
   w.z5 = take(b * 10 * sizeof(float));
   w.out = take(b * 2 * sizeof(float));
-  if (train) {
-    w.dout = take(b * 2 * sizeof(float));
-    w.dz5 = take(b * 10 * sizeof(float));
-    w.dz4 = take(b * 2048 * sizeof(float));
-    w.dz3 = take(b * 8192 * sizeof(float));
-    w.dz2 = take(b * 8192 * sizeof(float));
-    w.dz1 = take(b * 32768 * sizeof(float));
-    w.part = take(b * 9248 * sizeof(float));
-    w.grad = take(radar::kCnnParams * sizeof(float));
-  }
+  w.dout = take(b * 2 * sizeof(float));
+  w.dz5 = take(b * 10 * sizeof(float));
+  w.dz4 = take(b * 2048 * sizeof(float));
+  w.dz3 = take(b * 8192 * sizeof(float));
+  w.dz2 = take(b * 8192 * sizeof(float));
+  w.dz1 = take(b * 32768 * sizeof(float));
+  w.part = take(b * 9248 * sizeof(float));
+  w.grad = take(radar::kCnnParams * sizeof(float));
   w.total = off;
   return w;
 }
@@ -447,17 +449,34 @@ size_t wgrad_lds(int H, int W) {
   return (size_t)(H / S) * (W / S) * 32 * sizeof(float) + (size_t)(H + 2) * (W + 2) * 32 * sizeof(__bf16);
 }
 
+std::mutex g_cnn_mu;
 int cnn_attrs_done = 0;
 int cnn_setup() {
+  std::lock_guard<std::mutex> lock(g_cnn_mu);
   if (cnn_attrs_done) return RADAR_OK;
   const int need = (int)wgrad_lds<2>(32, 32);  // the largest weight-gradient tile (conv2)
   if (hipFuncSetAttribute(reinterpret_cast<const void*>(radar::k_conv_wgrad<2>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, need) != hipSuccess)
+                          hipFuncAttributeMaxDynamicSharedMemorySize, need) != hipSuccess ||
+      hipFuncSetAttribute(reinterpret_cast<const void*>(radar::k_cnn_fused),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)radar::FusedLds::BYTES) != hipSuccess)
     return RADAR_E_HIP;
   cnn_attrs_done = 1;
   return RADAR_OK;
 }
 
+// Inference: the whole network per patch in one persistent kernel.
+int cnn_forward_fused(const float* theta, const float* x, int B, const CnnWs& w, char* ws, float* out,
+                      hipStream_t s) {
+  __bf16* wb = reinterpret_cast<__bf16*>(ws + w.wb);
+  hipLaunchKernelGGL(radar::k_cnn_weights_bf16, dim3((3 * 9216 + 255) / 256), dim3(256), 0, s, theta, wb);
+  const int grid = std::min(B, g_num_cus > 0 ? g_num_cus : 256);
+  hipLaunchKernelGGL(radar::k_cnn_fused, dim3(grid), dim3(radar::kFusedThreads), radar::FusedLds::BYTES, s, x, theta,
+                     wb, B, out);
+  RADAR_HIP_CHECK(hipGetLastError());
+  return RADAR_OK;
+}
+
+// The layer-by-layer forward of training (keeps every activation for the backward pass).
 int cnn_forward(const float* theta, const float* x, int B, const CnnWs& w, char* ws, float* out, hipStream_t s) {
   __bf16* wb = reinterpret_cast<__bf16*>(ws + w.wb);
   __bf16* a1 = reinterpret_cast<__bf16*>(ws + w.a1);
@@ -1087,7 +1106,11 @@ int radar_cnn_forward(const float* theta, const float* patches, int32_t batch, f
   if (!theta || !patches || !out || !ws || batch < 1 || batch > 65536) return RADAR_E_ARG;
   const CnnWs w = cnn_ws_layout(batch, false);
   if (ws_bytes < w.total) return RADAR_E_WORKSPACE;
-  return cnn_forward(theta, patches, batch, w, static_cast<char*>(ws), out, reinterpret_cast<hipStream_t>(hip_stream));
+  int rc = ensure_init();  // the CU count sizes the persistent grid
+  if (rc == RADAR_OK) rc = cnn_setup();
+  if (rc != RADAR_OK) return rc;
+  return cnn_forward_fused(theta, patches, batch, w, static_cast<char*>(ws), out,
+                           reinterpret_cast<hipStream_t>(hip_stream));
 }
 
 int radar_cnn_gradient(const float* theta, const float* patches, const float* labels, int32_t batch, float* grad,
