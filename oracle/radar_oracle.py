@@ -461,3 +461,38 @@ def fps_sft(Y, A, *, zc_root=None, zc_shift=0, dirs=SFT_DIRECTIONS, k=8, pfa=SFT
     z = None if zc_root is None else zc_sequence(n, zc_root, zc_shift)
     S = sft_slices(ls_estimate(Y, A, z), dirs)
     return sft_to_peaks(sft_decode(S, n, m, dirs, k, pfa, tol), n, m)
+
+
+# --------------------------------------------------------------------------
+# Threshold detection (Sec. II-B.2, Eq. 18)
+#
+# Eq. 18 declares a target where P(s, r) exceeds sigma^2 ln(P_fa); with
+# ln(P_fa) < 0 the sign is garbled.  Reading: for white noise each periodogram
+# cell is the squared magnitude of a circular complex Gaussian, so its power
+# is exponential with mean sigma_P^2 and P(P > eta) = exp(-eta / sigma_P^2);
+# the threshold for false-alarm probability P_fa is eta = -ln(P_fa) sigma_P^2.
+# sigma_P^2 follows from the chain of the receiver: the LS estimate (Eq. 16)
+# carries noise of variance sigma_H^2 = sigma^2 mean(1/|a|^2) per resource
+# element (sigma^2 per received element); DFT-CE keeps the N_cp taps, which
+# by Parseval leaves the noise power of a cell inside the cyclic-prefix range
+# box unchanged; the windowed transform of Eq. 17 then gives
+#     sigma_P^2 = sigma_H^2 * sum_l w_l^2 * sum_k w_k^2 / (N M).
+# Detections are the local maxima of P (as find_peaks) at or above eta.
+# --------------------------------------------------------------------------
+def cfar_noise_power(A, noise_power: float, window_kind: int = WINDOW_HANN) -> float:
+    """sigma_P^2: mean noise power of a periodogram cell (inside the CP range box)."""
+    A = np.asarray(A, dtype=np.complex128)
+    m, n = A.shape
+    sigma_h2 = noise_power * float(np.mean(1.0 / (A.real ** 2 + A.imag ** 2)))
+    wk, wl = window(n, window_kind), window(m, window_kind)
+    return sigma_h2 * float(np.sum(wl * wl)) * float(np.sum(wk * wk)) / (n * m)
+
+
+def cfar_threshold(A, noise_power: float, pfa: float, window_kind: int = WINDOW_HANN) -> float:
+    """eta = -ln(P_fa) sigma_P^2 (Eq. 18, reading above)."""
+    return -np.log(pfa) * cfar_noise_power(A, noise_power, window_kind)
+
+
+def detect_threshold(P: np.ndarray, eta: float, k: int):
+    """The local maxima of P at or above eta, ranked as find_peaks, at most k."""
+    return [pk for pk in find_peaks(P, k) if pk[2] >= eta]

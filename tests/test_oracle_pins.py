@@ -473,3 +473,42 @@ def test_sft_agrees_with_periodogram_at_high_snr(seed):
     det = O.fps_sft(f.Y, f.A, zc_root=1, k=5)
     P = O.frame_periodogram(f.Y, f.A, n_pad=256, m_pad=64, n_cp=256, window_kind=O.WINDOW_RECT, zc_root=1)
     assert sorted((s, r) for s, r, _ in det) == sorted((row - 32, c) for row, c, _ in O.find_peaks(P, 5))
+
+
+# ------------------------------------------- threshold detection (Eq. 18)
+@pytest.mark.parametrize("wk,closed", [(O.WINDOW_RECT, 1.0), (O.WINDOW_HANN, 3.0 / 8.0),
+                                       (O.WINDOW_HAMMING, 0.54 ** 2 + 0.46 ** 2 / 2.0)])
+def test_window_energy_closed_forms(wk, closed):
+    # sum of w^2 for the periodic windows: N (a0^2 + a1^2 / 2)
+    for n in (16, 64, 1024):
+        assert float(np.sum(O.window(n, wk) ** 2)) == pytest.approx(closed * n, rel=1e-12)
+
+
+@pytest.mark.parametrize("n_cp,wk,qam", [(64, O.WINDOW_HANN, 16), (256, O.WINDOW_RECT, 4), (64, O.WINDOW_HAMMING, 16)])
+def test_threshold_false_alarm_rate_on_noise(n_cp, wk, qam):
+    # noise only: inside the CP range box a cell exceeds eta with probability
+    # P_fa (exponential cell power); outside the box DFT-CE removed the noise
+    n, m, pfa, sigma2 = 256, 64, 1e-2, 0.5
+    spec = S.FrameSpec(n_sub=n, n_sym=m, qam=qam, zc_root=3, n_targets=0, snr_db=-10 * np.log10(sigma2))
+    hits = tot = 0
+    for i in range(6):
+        f = S.make_frame(spec, 88, i)
+        P = O.frame_periodogram(f.Y, f.A, n_pad=4 * n, m_pad=4 * m, n_cp=n_cp, window_kind=wk, zc_root=3)
+        eta = O.cfar_threshold(f.A, sigma2, pfa, wk)
+        box = P[:, 8:4 * (n_cp - 2)]  # range cells well inside [0, N_cp)
+        hits += int(np.sum(box >= eta))
+        tot += box.size
+        # the mean cell power inside the box is sigma_P^2
+        assert float(np.mean(box)) == pytest.approx(eta / -np.log(pfa), rel=0.1)
+    assert hits / tot == pytest.approx(pfa, rel=0.15)
+
+
+def test_threshold_detection_keeps_targets_drops_noise():
+    spec = S.FrameSpec(n_sub=256, n_sym=64, qam=16, zc_root=1, n_targets=3, snr_db=-5.0, on_grid=True,
+                       rho_min=1, rho_max=60, nu_abs_max=31)
+    f = S.make_frame(spec, 89, 0)
+    P = O.frame_periodogram(f.Y, f.A, n_pad=1024, m_pad=256, n_cp=64, zc_root=1)
+    eta = O.cfar_threshold(f.A, 10 ** 0.5, 1e-6)
+    det = O.detect_threshold(P, eta, 20)
+    assert sorted((s - 128, r) for s, r, _ in det) == sorted((int(v * 4), int(r * 4)) for r, v in zip(f.rho, f.nu))
+    assert all(v >= eta for _, _, v in det)
