@@ -70,7 +70,8 @@ enum { RADAR_ST_ZERO_SYMBOL = 1u, RADAR_ST_NONFINITE = 2u };
 enum {
   RADAR_FLAG_REFINE = 1,   /* sub-cell refinement of the peaks (radar_frame_process) */
   RADAR_FLAG_BF16X3 = 2,   /* Doppler and range FFTs' radix-16 stages on BF16 matrix cores, split operands */
-  RADAR_FLAG_FP16X3 = 4    /* the same with FP16 operands and per-column power-of-two scaling */
+  RADAR_FLAG_FP16X3 = 4,   /* the same with FP16 operands and per-column power-of-two scaling */
+  RADAR_FLAG_THRESHOLD = 8 /* keep only peaks at or above the detection threshold of Eq. 18 */
 };
 
 /* One frame shape.  Names follow the paper: N subcarriers, M OFDM symbols,
@@ -88,6 +89,8 @@ typedef struct {
   int32_t window;               /* RADAR_WIN_*, applied separably over k and l */
   int32_t flags;                /* RADAR_FLAG_* bits, 0 for none */
   int64_t ld;                   /* elements between consecutive OFDM symbols, >= N */
+  float pfa;                    /* RADAR_FLAG_THRESHOLD: false-alarm probability per cell, (0, 1) */
+  float noise_power;            /* RADAR_FLAG_THRESHOLD: noise power sigma^2 per received element, > 0 */
 } radar_frame_desc;
 
 /* One detected peak of P.  s is the signed Doppler index (row - M'/2), r the
@@ -136,6 +139,13 @@ int radar_init(void);
  *   the products hi*hi, hi*lo and lo*hi accumulate in FP32; twiddles, windows,
  *   the taps stage and |.|^2 stay FP32.  These forms exist for N' = 4N,
  *   4 N_cp <= N, N >= 256 (RADAR_E_UNSUPPORTED otherwise).
+ *   With RADAR_FLAG_THRESHOLD the peaks are the paper's detections (Eq. 18):
+ *   local maxima with P >= eta = -ln(pfa) sigma_P^2, at most k, where
+ *   sigma_P^2 = noise_power * mean(1/|a|^2) * sum_l w_l^2 * sum_k w_k^2 / (N M)
+ *   is the mean noise power of a cell inside the cyclic-prefix range box (the
+ *   LS estimate's noise through DFT-CE and the windowed transform; the mean
+ *   of 1/|a|^2 over the frame is taken from A by the taps stage).  n_peaks
+ *   counts only those detections.
  * Y, A:     input frames, frame f at Y + f*frame_stride (elements).
  * P:        output, frame f at P + f*p_frame_stride (floats); must not be NULL;
  *           p_frame_stride >= M'*N' and a multiple of 4; P 16-byte aligned.

@@ -63,6 +63,7 @@ struct FrameRef {
   radar_peak* peaks;
   int32_t* n_peaks;
   uint32_t* status;
+  float eta_factor;  // threshold detection: eta = eta_factor * sum of the frame's 1/|a|^2
 };
 
 // Pointers read from a FrameRef table are generic to the compiler.  The hot

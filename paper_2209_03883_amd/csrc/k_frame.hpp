@@ -31,7 +31,26 @@ struct K1Args {
   int from_h;             // input already is the LS estimate H
   float inv_n;            // 1/N
   const FrameRef* refs;   // per-frame Y, A, status (batch jobs), or null: base + f * frame_stride
+  float* inv_sum;         // [F][M] sum_k 1/|a_{l,k}|^2 per symbol (threshold detection), or null
 };
+
+// Sum over the T threads of one team (T a power of two; teams inside one
+// wave when T <= 64, else whole work-group rows of T threads with LDS `red`
+// of T/64 floats per team).  Every thread of the team gets the sum.
+template <int T>
+__device__ __forceinline__ float team_sum(float v, float* red, int team, int t) {
+#pragma unroll
+  for (int m = (T < 64 ? T : 64) / 2; m > 0; m >>= 1) v += __shfl_xor(v, m);
+  if constexpr (T > 64) {
+    if ((t & 63) == 0) red[team * (T / 64) + (t >> 6)] = v;
+    __syncthreads();
+    v = 0.0f;
+#pragma unroll
+    for (int w = 0; w < T / 64; ++w) v += red[team * (T / 64) + w];
+    __syncthreads();
+  }
+  return v;
+}
 
 // K1: one team per OFDM symbol.
 template <int N>
@@ -50,6 +69,7 @@ __global__ void __launch_bounds__(kBlock) k1_taps(K1Args a) {
   const RADAR_GLOBAL float2* y = gptr(a.refs ? a.refs[f].Y : a.Y + f * a.frame_stride) + lc * a.ld;
   const RADAR_GLOBAL float2* x = gptr(a.refs ? a.refs[f].A : a.A + f * a.frame_stride) + lc * a.ld;
   uint32_t st = 0;
+  float isum = 0.0f;
   float2 v[16];
 #pragma unroll
   for (int e = 0; e < 16; ++e) v[e] = gload2(y + t + T * e);
@@ -69,7 +89,13 @@ __global__ void __launch_bounds__(kBlock) k1_taps(K1Args a) {
       const float den = cabs2(s[e]);
       st |= den == 0.0f ? 1u : 0u;
       const float inv = den == 0.0f ? 0.0f : __builtin_amdgcn_rcpf(den);
+      isum += inv;
       v[e] = cscale(cmulc(h, s[e]), inv);            // y conj(z) conj(a) / |a|^2
+    }
+    if (a.inv_sum) {
+      __shared__ float red[T > 64 ? TEAMS * (T / 64) : 1];
+      isum = team_sum<T>(isum, red, team, t);
+      if (active && t == 0) a.inv_sum[(int64_t)f * a.M + l] = isum;
     }
   }
 #pragma unroll
@@ -130,6 +156,7 @@ __global__ void __launch_bounds__(K1p<N>::BLOCK) k1_taps_p(K1Args a, int total_g
     const RADAR_GLOBAL float2* y = gptr(a.refs ? a.refs[f].Y : a.Y + f * a.frame_stride) + l * a.ld;
     const RADAR_GLOBAL float2* x = gptr(a.refs ? a.refs[f].A : a.A + f * a.frame_stride) + l * a.ld;
     uint32_t st = 0;
+    float isum = 0.0f;
     float2 v[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) v[e] = gload2(y + t + T * e);
@@ -148,7 +175,12 @@ __global__ void __launch_bounds__(K1p<N>::BLOCK) k1_taps_p(K1Args a, int total_g
         const float den = cabs2(sv[e]);
         st |= den == 0.0f ? 1u : 0u;
         const float inv = den == 0.0f ? 0.0f : __builtin_amdgcn_rcpf(den);
+        isum += inv;
         v[e] = cscale(cmulc(h, sv[e]), inv);          // y conj(z) conj(a) / |a|^2
+      }
+      if (a.inv_sum) {
+        isum = team_sum<T>(isum, nullptr, 0, t);
+        if (t == 0) a.inv_sum[gsym] = isum;
       }
     }
 #pragma unroll

@@ -232,13 +232,25 @@ __global__ void __launch_bounds__(256) k_peak_rows_listed(const float* P, int64_
 }
 
 // Step 4: the k best keys over the scanned rows of a frame, one wavefront per
-// frame (grid F, 64 threads).
+// frame (grid F, 64 threads).  With inv_sum (threshold detection, Eq. 18) the
+// list stops at the first peak below eta = eta_factor * sum_l inv_sum[f][l];
+// the peaks come in descending P, so what is kept is exactly the top-k local
+// maxima at or above eta.
 __global__ void __launch_bounds__(64) k_peak_merge(const uint64_t* cand, const int32_t* cnt, int m_pad, int n_pad,
                                                    int k, radar_peak* peaks, int32_t* n_peaks,
-                                                   const FrameRef* refs) {
+                                                   const FrameRef* refs, const float* inv_sum, int M,
+                                                   float eta_factor) {
   const int f = blockIdx.x;
   const int count = cnt[f] * k;
   const uint64_t* c = cand + (int64_t)f * m_pad * k;
+  float eta = -__builtin_huge_valf();
+  if (inv_sum) {
+    float acc = 0.0f;  // fixed order: lane-strided partial sums, then a butterfly
+    for (int l = threadIdx.x; l < M; l += 64) acc += inv_sum[(int64_t)f * M + l];
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) acc += __shfl_xor(acc, m);
+    eta = (refs ? refs[f].eta_factor : eta_factor) * acc;
+  }
   uint64_t last = ~0ull;
   int i = 0;
   for (; i < k; ++i) {
@@ -249,12 +261,14 @@ __global__ void __launch_bounds__(64) k_peak_merge(const uint64_t* cand, const i
     }
     best = wave_max_u64(best);
     if (best == 0) break;
+    const float p = ord_value((uint32_t)(best >> 32));
+    if (p < eta) break;
     if (threadIdx.x == 0) {
       const uint32_t flat = 0xFFFFFFFFu - (uint32_t)best;
       radar_peak pk;
       pk.s = (int32_t)(flat / (uint32_t)n_pad) - (m_pad >> 1);
       pk.r = (int32_t)(flat % (uint32_t)n_pad);
-      pk.p = ord_value((uint32_t)(best >> 32));
+      pk.p = p;
       pk.s_off = 0.0f;
       pk.r_off = 0.0f;
       (refs ? refs[f].peaks : peaks + (int64_t)f * k)[i] = pk;

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -43,7 +44,11 @@ int validate_desc(const radar_frame_desc* d) {
   if (d->n_cp < 1 || d->n_cp > N) return RADAR_E_ARG;
   if (d->window < RADAR_WIN_RECT || d->window > RADAR_WIN_HAMMING) return RADAR_E_ARG;
   if (d->zc_mode != RADAR_ZC_NONE && d->zc_mode != RADAR_ZC_DIAG) return RADAR_E_ARG;
-  if ((d->flags & ~(RADAR_FLAG_REFINE | RADAR_FLAG_BF16X3 | RADAR_FLAG_FP16X3)) != 0) return RADAR_E_ARG;
+  if ((d->flags & ~(RADAR_FLAG_REFINE | RADAR_FLAG_BF16X3 | RADAR_FLAG_FP16X3 | RADAR_FLAG_THRESHOLD)) != 0)
+    return RADAR_E_ARG;
+  if ((d->flags & RADAR_FLAG_THRESHOLD) &&
+      !(d->pfa > 0.0f && d->pfa < 1.0f && d->noise_power > 0.0f && d->noise_power <= FLT_MAX))
+    return RADAR_E_ARG;
   if ((d->flags & RADAR_FLAG_BF16X3) && (d->flags & RADAR_FLAG_FP16X3)) return RADAR_E_ARG;
   if (d->ld < N) return RADAR_E_ARG;
   if (!is_pow2(N) || !is_pow2(M) || N < 16 || N > 4096 || M < 16 || M > 4096) return RADAR_E_UNSUPPORTED;
@@ -77,6 +82,7 @@ PeakWs peak_ws_layout(int m_pad, int n_frames, int k, size_t base) {
 struct FrameWs {
   size_t taps, U;
   PeakWs pk;
+  size_t inv_sum;  // [F][M] floats with RADAR_FLAG_THRESHOLD, else == total (no region)
   size_t total;
 };
 
@@ -86,8 +92,24 @@ FrameWs frame_ws_layout(const radar_frame_desc* d, int n_frames, int k) {
   w.taps = 0;
   w.U = align256(F * d->n_sym * d->n_cp * sizeof(float2));
   w.pk = peak_ws_layout(d->m_pad, n_frames, k, w.U + align256(F * d->m_pad * d->n_cp * sizeof(float2)));
-  w.total = w.pk.total;
+  w.inv_sum = w.pk.total;
+  w.total = w.inv_sum + ((d->flags & RADAR_FLAG_THRESHOLD) ? align256(F * d->n_sym * sizeof(float)) : 0);
   return w;
+}
+
+// sum_{n<L} w_n^2 of the periodic windows (full periods of the cosine, L >= 16)
+double window_energy(int kind, int L) {
+  if (kind == RADAR_WIN_HANN) return 0.375 * L;                  // 1/4 + 1/8
+  if (kind == RADAR_WIN_HAMMING) return (0.54 * 0.54 + 0.5 * 0.46 * 0.46) * L;
+  return (double)L;
+}
+
+// eta = eta_factor * sum_{l,k} 1/|a_{l,k}|^2: -ln(pfa) sigma^2 mean(1/|a|^2)
+// sum_l w_l^2 sum_k w_k^2 / (N M), the mean taken as the sum over N M.
+float eta_factor_of(const radar_frame_desc* d) {
+  const double nm = (double)d->n_sub * (double)d->n_sym;
+  return (float)(-std::log((double)d->pfa) * (double)d->noise_power * window_energy(d->window, d->n_sym) *
+                 window_energy(d->window, d->n_sub) / (nm * nm));
 }
 
 int ensure_init() { return radar_init(); }
@@ -244,6 +266,7 @@ int enqueue_transforms(const radar_frame_desc* d, int F, const float2* in, const
   a1.from_h = from_h;
   a1.inv_n = 1.0f / (float)N;
   a1.refs = refs;
+  a1.inv_sum = (d->flags & RADAR_FLAG_THRESHOLD) ? reinterpret_cast<float*>(ws + w.inv_sum) : nullptr;
   int slot = timer_open(RADAR_STAGE_TAPS, s);
 #define K1_CALL(n) launch_k1_n<n>(a1, M, F, s)
   RADAR_SIZE_SWITCH(N, K1_CALL)
@@ -336,8 +359,10 @@ int enqueue_refine(const radar_frame_desc* d, int F, int k, const float2* taps, 
 }
 
 // Peak search from P and its row maxima (already in the workspace).
+// With inv_sum (threshold detection) the merge keeps only peaks at or above eta.
 int enqueue_peaks(const float* P, int64_t p_stride, int m_pad, int n_pad, int F, int k, const PeakWs& w, char* ws,
-                  radar_peak* peaks, int32_t* n_peaks, hipStream_t s, const radar::FrameRef* refs = nullptr) {
+                  radar_peak* peaks, int32_t* n_peaks, hipStream_t s, const radar::FrameRef* refs = nullptr,
+                  const float* inv_sum = nullptr, int M = 0, float eta_factor = 0.0f) {
   float* rowmax = reinterpret_cast<float*>(ws + w.rowmax);
   float* tau = reinterpret_cast<float*>(ws + w.tau);
   int32_t* cnt = reinterpret_cast<int32_t*>(ws + w.cnt);
@@ -352,7 +377,7 @@ int enqueue_peaks(const float* P, int64_t p_stride, int m_pad, int n_pad, int F,
                      p_stride, m_pad, n_pad, k, tau, list, cnt, cand, refs);
   RADAR_HIP_CHECK(hipGetLastError());
   hipLaunchKernelGGL(radar::k_peak_merge, dim3(F), dim3(64), 0, s, cand, cnt, m_pad, n_pad, k, peaks, n_peaks,
-                     refs);
+                     refs, inv_sum, M, eta_factor);
   RADAR_HIP_CHECK(hipGetLastError());
   timer_close(RADAR_STAGE_PEAKS, slot, s);
   return RADAR_OK;
@@ -636,7 +661,11 @@ int enqueue_group(const radar_batch& b, const BatchGroup& g, hipStream_t s) {
   int rc = hipGetLastError() == hipSuccess ? RADAR_OK : RADAR_E_HIP;
   if (rc == RADAR_OK)
     rc = enqueue_transforms(&g.d, F, nullptr, nullptr, 0, 0, nullptr, 0, nullptr, w, scratch, s, refs);
-  if (rc == RADAR_OK) rc = enqueue_peaks(nullptr, 0, g.d.m_pad, g.d.n_pad, F, g.k, w.pk, scratch, nullptr, nullptr, s, refs);
+  const float* inv_sum =
+      (g.d.flags & RADAR_FLAG_THRESHOLD) ? reinterpret_cast<const float*>(scratch + w.inv_sum) : nullptr;
+  if (rc == RADAR_OK)
+    rc = enqueue_peaks(nullptr, 0, g.d.m_pad, g.d.n_pad, F, g.k, w.pk, scratch, nullptr, nullptr, s, refs, inv_sum,
+                       g.d.n_sym);
   if (rc == RADAR_OK && (g.d.flags & RADAR_FLAG_REFINE))
     rc = enqueue_refine(&g.d, F, g.k, reinterpret_cast<const float2*>(scratch + w.taps), nullptr, nullptr, refs, s);
   g_tune = saved;
@@ -816,7 +845,10 @@ int radar_frame_process(const radar_frame_desc* d, int32_t n_frames, const radar
   rc = enqueue_transforms(d, n_frames, reinterpret_cast<const float2*>(Y), reinterpret_cast<const float2*>(A),
                           frame_stride, 0, P, p_frame_stride, status, w, wsb, s);
   if (rc != RADAR_OK) return rc;
-  rc = enqueue_peaks(P, p_frame_stride, d->m_pad, d->n_pad, n_frames, k, w.pk, wsb, peaks, n_peaks, s);
+  const bool thr = (d->flags & RADAR_FLAG_THRESHOLD) != 0;
+  rc = enqueue_peaks(P, p_frame_stride, d->m_pad, d->n_pad, n_frames, k, w.pk, wsb, peaks, n_peaks, s, nullptr,
+                     thr ? reinterpret_cast<const float*>(wsb + w.inv_sum) : nullptr, d->n_sym,
+                     thr ? eta_factor_of(d) : 0.0f);
   if (rc != RADAR_OK || !(d->flags & RADAR_FLAG_REFINE)) return rc;
   return enqueue_refine(d, n_frames, k, reinterpret_cast<const float2*>(wsb + w.taps), peaks, n_peaks, nullptr, s);
 }
@@ -825,7 +857,7 @@ int radar_periodogram(const radar_frame_desc* d, int32_t n_frames, const radar_c
                       float* P, int64_t p_frame_stride, void* ws, size_t ws_bytes, void* hip_stream) {
   int rc = check_frame_common(d, n_frames, frame_stride, p_frame_stride, P);
   if (rc != RADAR_OK) return rc;
-  if (!H || !ws || (d->flags & RADAR_FLAG_REFINE)) return RADAR_E_ARG;
+  if (!H || !ws || (d->flags & (RADAR_FLAG_REFINE | RADAR_FLAG_THRESHOLD))) return RADAR_E_ARG;
   if (d->zc_mode != RADAR_ZC_NONE) return RADAR_E_ARG;
   const FrameWs w = frame_ws_layout(d, n_frames, 1);
   if (ws_bytes < w.total) return RADAR_E_WORKSPACE;
@@ -981,7 +1013,7 @@ int radar_batch_create(const radar_frame_job* jobs, int32_t n_jobs, int32_t flag
     for (size_t j = 0; j < g.jobs.size(); ++j) {
       const radar_frame_job& jb = jobs[g.jobs[j]];
       refs[j] = {reinterpret_cast<const float2*>(jb.Y), reinterpret_cast<const float2*>(jb.A), jb.P, jb.peaks,
-                 jb.n_peaks, jb.status};
+                 jb.n_peaks, jb.status, (jb.d.flags & RADAR_FLAG_THRESHOLD) ? eta_factor_of(&jb.d) : 0.0f};
     }
     if (hipMemcpyAsync(b->ws + g.refs_off, refs.data(), refs.size() * sizeof(radar::FrameRef),
                        hipMemcpyHostToDevice, s) != hipSuccess ||

@@ -26,7 +26,7 @@ RADAR_E_NOT_COPRIME = -5
 WIN_RECT, WIN_HANN, WIN_HAMMING = 0, 1, 2
 ZC_NONE, ZC_DIAG = 0, 1
 ST_ZERO_SYMBOL, ST_NONFINITE = 1, 2
-FLAG_REFINE, FLAG_BF16X3, FLAG_FP16X3 = 1, 2, 4
+FLAG_REFINE, FLAG_BF16X3, FLAG_FP16X3, FLAG_THRESHOLD = 1, 2, 4, 8
 
 EXPORTED = (
     "radar_version", "radar_status_string", "radar_init",
@@ -56,6 +56,7 @@ class FrameDesc(ctypes.Structure):
         ("zc_root", ctypes.c_int32), ("zc_shift", ctypes.c_int32),
         ("window", ctypes.c_int32), ("flags", ctypes.c_int32),
         ("ld", ctypes.c_int64),
+        ("pfa", ctypes.c_float), ("noise_power", ctypes.c_float),
     ]
 
 
@@ -168,13 +169,18 @@ class Config:
     window: int = WIN_HANN
     refine: bool = False
     precision: int = 0          # 0 (FP32), FLAG_BF16X3 or FLAG_FP16X3
+    threshold: bool = False     # Eq. 18 detection (pfa, noise_power)
+    pfa: float = 1e-2
+    noise_power: float = 0.0
 
     def desc(self, ld: int | None = None) -> FrameDesc:
         return FrameDesc(self.n_sub, self.n_sym, self.n_pad, self.m_pad, self.n_cp,
                          ZC_NONE if self.zc_root is None else ZC_DIAG,
                          0 if self.zc_root is None else int(self.zc_root), int(self.zc_shift),
-                         int(self.window), (FLAG_REFINE if self.refine else 0) | int(self.precision),
-                         int(self.n_sub if ld is None else ld))
+                         int(self.window),
+                         (FLAG_REFINE if self.refine else 0) | int(self.precision)
+                         | (FLAG_THRESHOLD if self.threshold else 0),
+                         int(self.n_sub if ld is None else ld), float(self.pfa), float(self.noise_power))
 
 
 def _stream_ptr(stream) -> int:

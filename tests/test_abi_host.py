@@ -59,6 +59,10 @@ def test_workspace_size_arithmetic():
         U = F * 4096 * 256 * 8
         assert _ws(cfg, F, 8) == _al(taps) + _al(U) + _peak_ws(F, 4096, 8)
     assert radar.lib().radar_detect_workspace_size(4096, 4096, 2, 8) == _peak_ws(2, 4096, 8)
+    # threshold detection adds the per-symbol sums of 1/|a|^2, [F][M] floats
+    thr = radar.Config(1024, 1024, 4096, 4096, 256, zc_root=7, threshold=True, noise_power=1.0)
+    for F in (1, 3):
+        assert _ws(thr, F, 8) == _ws(cfg, F, 8) + _al(F * 1024 * 4)
 
 
 @pytest.mark.parametrize("bad,code", [
@@ -117,13 +121,37 @@ def test_detect_rejects():
 def test_flags_validation():
     L = radar.lib()
     d = radar.Config(256, 64, 1024, 256, 32, zc_root=1).desc()
-    d.flags = 8  # unknown bit
+    d.flags = 16  # unknown bit
     assert L.radar_frame_workspace_size(ctypes.byref(d), 1, 3) == 0
     ok = radar.Config(256, 64, 1024, 256, 32, refine=True)
     need = L.radar_frame_workspace_size(ctypes.byref(ok.desc()), 1, 3)
     assert need > 0
     # the periodogram entry finds no peaks: the refine flag is an argument error
     assert L.radar_periodogram(ctypes.byref(ok.desc()), 1, 256, 0, 256, 0, 256, need, None) == radar.RADAR_E_ARG
+
+
+@pytest.mark.parametrize("pfa,noise,ok", [
+    (1e-2, 1.0, True), (1e-6, 1e-9, True), (0.0, 1.0, False), (1.0, 1.0, False), (-0.1, 1.0, False),
+    (float("nan"), 1.0, False), (1e-2, 0.0, False), (1e-2, -1.0, False), (1e-2, float("inf"), False),
+    (1e-2, float("nan"), False),
+])
+def test_threshold_validation(pfa, noise, ok):
+    L = radar.lib()
+    cfg = radar.Config(256, 64, 1024, 256, 32, zc_root=1, threshold=True, pfa=pfa, noise_power=noise)
+    assert (L.radar_frame_workspace_size(ctypes.byref(cfg.desc()), 1, 3) > 0) == ok
+    # without the flag the two fields are ignored
+    cfg.threshold = False
+    assert L.radar_frame_workspace_size(ctypes.byref(cfg.desc()), 1, 3) > 0
+
+
+def test_threshold_rejected_by_periodogram_and_sft():
+    L = radar.lib()
+    cfg = radar.Config(256, 64, 1024, 256, 32, threshold=True, noise_power=1.0)
+    need = L.radar_frame_workspace_size(ctypes.byref(cfg.desc()), 1, 3)
+    assert need > 0
+    assert L.radar_periodogram(ctypes.byref(cfg.desc()), 1, 256, 0, 256, 0, 256, need, None) == radar.RADAR_E_ARG
+    s = radar.sft_desc(8)
+    assert L.radar_fps_sft_workspace_size(ctypes.byref(cfg.desc()), ctypes.byref(s), 1) == 0
 
 
 def test_sft_default_settings():
