@@ -115,8 +115,9 @@ def cpu_baseline(frames, budget_s):
 
 def time_extras(radar, torch, Yd, Ad, cfg, ws, peaks, n_peaks, status, stream, B, steps, warmup):
     """Figures beside the headline: the same step with sub-cell refinement of
-    the k peaks, the same step in the BF16x3 and FP16x3 matrix-core forms, and
-    FPS-SFT (eight directions, K = 8) on the same frames."""
+    the k peaks, with threshold detection (Eq. 18), in the BF16x3 and FP16x3
+    matrix-core forms, the CNN refiner, and FPS-SFT (eight directions, K = 8)
+    on the same frames."""
     import dataclasses
 
     out = {}
@@ -136,7 +137,26 @@ def time_extras(radar, torch, Yd, Ad, cfg, ws, peaks, n_peaks, status, stream, B
     st = radar.timing_stop()
     out["with_refinement_frames_per_s"] = B * steps / dt
     out["refine_us_per_frame"] = st["refine"][0] / max(st["refine"][1], 1) * 1e3 / B
-    del P
+
+    # threshold detection (Eq. 18): the same step keeping only peaks above eta
+    cfg_t = dataclasses.replace(cfg, threshold=True, pfa=1e-7, noise_power=1.0)
+    wst = radar.new_workspace(radar.workspace_bytes(cfg_t, B, K), Yd.device)
+    for _ in range(warmup):
+        radar.frame_process(Yd, Ad, cfg_t, K, P=P, workspace=wst, peaks=peaks, n_peaks=n_peaks, status=status,
+                            stream=stream)
+    radar.timing_start(steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        radar.frame_process(Yd, Ad, cfg_t, K, P=P, workspace=wst, peaks=peaks, n_peaks=n_peaks, status=status,
+                            stream=stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = radar.timing_stop()
+    out["with_threshold_frames_per_s"] = B * steps / dt
+    out["threshold_stage_us_per_frame"] = {k: st[k][0] / max(st[k][1], 1) * 1e3 / B for k in ("taps", "peaks")}
+    out["threshold_mean_detections"] = float(n_peaks.float().mean())
+    del P, wst
 
     # the matrix-core precision forms of the Doppler and range FFTs, same step
     for name, flag in (("bf16x3", radar.FLAG_BF16X3), ("fp16x3", radar.FLAG_FP16X3)):
