@@ -68,6 +68,41 @@ def zc_sequence(n: int, root: int, shift: int = 0) -> np.ndarray:
     return np.cos(ang) + 1j * np.sin(ang)
 
 
+ZC_DIAG = "diag"
+ZC_DENSE = "dense"
+
+
+def zc_matrix(n: int, root: int, shift: int = 0) -> np.ndarray:
+    """The square Zadoff-Chu matrix of Eq. 24 read literally for an N-subcarrier
+    symbol: a length L = N^2 sequence of Eq. 23 (root relatively prime to L)
+    laid out row by row, Z_m[i, j] = Z_seq(i*N + j), D = N."""
+    return zc_sequence(n * n, root, shift).reshape(n, n)
+
+
+def precode_dense(A: np.ndarray, root: int, shift: int = 0) -> np.ndarray:
+    """Precoded symbols A_p = Z_m A (Sec. III-B, Eq. 24 dense reading) per OFDM
+    symbol, scaled by 1/sqrt(N) so that the precoding keeps the symbol energy
+    (Z_m Z_m^H = N I).  A is symbol-major (M, N): row l holds symbol l, so
+    A_p[l, i] = sum_j Z_m[i, j] A[l, j] / sqrt(N)."""
+    A = np.asarray(A, dtype=np.complex128)
+    n = A.shape[1]
+    return A @ zc_matrix(n, root, shift).T / np.sqrt(n)
+
+
+def tx_symbols(A, zc_root=None, zc_shift=0, zc_mode=ZC_DIAG):
+    """The symbols the received elements carry, i.e. what the LS estimate of
+    Eq. 16 divides by: A without precoding, z_k A_{l,k} under the diagonal
+    reading, Z_m A / sqrt(N) under the dense one."""
+    A = np.asarray(A, dtype=np.complex128)
+    if zc_root is None:
+        return A
+    if zc_mode == ZC_DENSE:
+        return precode_dense(A, zc_root, zc_shift)
+    if zc_mode != ZC_DIAG:
+        raise ValueError(f"unknown ZC mode {zc_mode}")
+    return A * zc_sequence(A.shape[1], zc_root, zc_shift)[None, :]
+
+
 # --------------------------------------------------------------------------
 # Spectral division / LS channel estimate (Sec. II-B.2, Eq. 16)
 # --------------------------------------------------------------------------
@@ -80,6 +115,10 @@ def ls_estimate(Y: np.ndarray, A: np.ndarray, z: np.ndarray | None = None) -> np
     symbol) the received element is y = z_k * a * h + noise, so
         h_{k,l} = y_{k,l} / (z_k * a_{k,l}).
     ``z=None`` means no precoding.  Zero symbols raise ZeroDivisionError.
+    Under the dense reading of Eq. 24 (``tx_symbols``) the division is by the
+    precoded symbols A_p themselves: applying Z_m^{-1} to the received frame
+    before the division does not recover h once a target has a delay, since
+    the channel multiplies each subcarrier after the precoding.
     """
     Y = np.asarray(Y, dtype=np.complex128)
     A = np.asarray(A, dtype=np.complex128)
@@ -159,11 +198,9 @@ def periodogram(H: np.ndarray, n_pad: int, m_pad: int, window_kind: int = WINDOW
 
 
 def frame_periodogram(Y, A, *, n_pad, m_pad, n_cp, window_kind=WINDOW_HANN,
-                      zc_root=None, zc_shift=0):
+                      zc_root=None, zc_shift=0, zc_mode=ZC_DIAG):
     """The whole estimator of Fig. 2 / Fig. 3: de-precode, divide, DFT-CE, Eq. 17."""
-    n = np.asarray(Y).shape[1]
-    z = None if zc_root is None else zc_sequence(n, zc_root, zc_shift)
-    H = ls_estimate(Y, A, z)
+    H = ls_estimate(Y, tx_symbols(A, zc_root, zc_shift, zc_mode))
     Hd = dft_ce(H, n_cp)
     return periodogram(Hd, n_pad, m_pad, window_kind)
 
@@ -238,12 +275,11 @@ def bins_to_range_velocity(r: float, s: float, n_pad: int, m_pad: int, delta_f: 
 FINE = 16  # the local grid is the periodogram padded 16x in both axes
 
 
-def windowed_estimate(Y, A, *, n_cp, window_kind=WINDOW_HANN, zc_root=None, zc_shift=0):
+def windowed_estimate(Y, A, *, n_cp, window_kind=WINDOW_HANN, zc_root=None, zc_shift=0, zc_mode=ZC_DIAG):
     """The windowed DFT-CE estimate that Eq. 17 transforms: w_k w_l H'_{l,k}."""
     n = np.asarray(Y).shape[1]
     m = np.asarray(Y).shape[0]
-    z = None if zc_root is None else zc_sequence(n, zc_root, zc_shift)
-    Hd = dft_ce(ls_estimate(Y, A, z), n_cp)
+    Hd = dft_ce(ls_estimate(Y, tx_symbols(A, zc_root, zc_shift, zc_mode)), n_cp)
     return Hd * window(m, window_kind)[:, None] * window(n, window_kind)[None, :]
 
 

@@ -38,6 +38,7 @@ class FrameSpec:
     qam: int = 4                  # 4 (QPSK) or 16
     zc_root: int | None = 1       # transmitter ZC root (None: no precoding)
     zc_shift: int = 0
+    zc_dense: bool = False        # dense Z_m of a length-N^2 sequence instead of diag(z) (Eq. 24)
     n_targets: int = 3
     snr_db: float = 0.0
     on_grid: bool = True          # integer range/Doppler bins
@@ -128,7 +129,15 @@ def make_frame(spec: FrameSpec, config_id: int, frame_index: int) -> Frame:
     echo = np.zeros((m, n), dtype=np.complex128)
     for p in range(spec.n_targets):
         echo += b[p] * np.outer(np.exp(2j * np.pi * l * nu[p] / m), np.exp(-2j * np.pi * k * rho[p] / n))
-    tx = A if spec.zc_root is None else A * tx_precoding_sequence(n, spec.zc_root, spec.zc_shift)[None, :]
+    if spec.zc_root is None:
+        tx = A
+    elif spec.zc_dense:
+        # each symbol multiplied by the N x N matrix Z[i, j] = zc(i N + j) of a
+        # length-N^2 sequence, scaled by 1/sqrt(N) to keep the symbol energy
+        Z = tx_precoding_sequence(n * n, spec.zc_root, spec.zc_shift).reshape(n, n)
+        tx = A @ Z.T / np.sqrt(n)
+    else:
+        tx = A * tx_precoding_sequence(n, spec.zc_root, spec.zc_shift)[None, :]
     Y = tx * echo
     if spec.noise:
         sigma2 = 10.0 ** (-spec.snr_db / 10.0)

@@ -70,6 +70,74 @@ def test_zc_root_must_be_coprime():
         O.zc_phase_index(9, 3)
 
 
+# ------------------------------------------- dense ZC matrix (Eq. 24, literal)
+def test_zc_matrix_worked_example(golden_dir):
+    data = np.loadtxt(os.path.join(golden_dir, "zc_matrix_n2_root1.txt"))
+    Z = O.zc_matrix(2, 1)
+    for i, j, re, im in data:
+        assert Z[int(i), int(j)] == pytest.approx(complex(re, im), abs=1e-15)
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 8, 9, 15, 16, 64, 256])
+def test_zc_matrix_rows_orthogonal(n):
+    # Z_m Z_m^H = N I for every root prime to N and any shift
+    for root in (1, 3, 5, 7):
+        if math.gcd(root, n) != 1:
+            continue
+        for q in (0, 3):
+            Z = O.zc_matrix(n, root, q)
+            np.testing.assert_allclose(Z @ Z.conj().T, n * np.eye(n), atol=1e-12 * n)
+
+
+@pytest.mark.parametrize("n,root,q", [(8, 3, 0), (16, 5, 2), (64, 7, 1), (256, 1, 0), (1024, 7, 0)])
+def test_zc_matrix_factorisation(n, root, q):
+    # (iN + j)^2 = i^2 N^2 + 2ijN + j^2 splits Eq. 24 for even N into
+    # Z_m = D1 F D2: D1(i) = e^{j pi r (i^2 + 2qi/N)}, F(i, j) = e^{j 2 pi r ij/N},
+    # D2(j) = e^{j pi r (j^2 + 2qj)/N^2}; an N-point DFT between two diagonals
+    i = np.arange(n)
+    d1 = np.exp(1j * np.pi * ((root * (i * i + 2 * q * i / n)) % 2))
+    d2 = np.exp(1j * np.pi * root * ((i * i + 2 * q * i) % (2 * n * n)) / (n * n))
+    F = np.exp(2j * np.pi * ((root * np.outer(i, i)) % n) / n)
+    np.testing.assert_allclose(O.zc_matrix(n, root, q), d1[:, None] * F * d2[None, :], atol=1e-9)
+
+
+def test_dense_precoding_keeps_symbol_energy():
+    rng = np.random.default_rng(4)
+    A = rng.standard_normal((5, 64)) + 1j * rng.standard_normal((5, 64))
+    Ap = O.precode_dense(A, 3, 1)
+    np.testing.assert_allclose(np.sum(np.abs(Ap) ** 2, axis=1), np.sum(np.abs(A) ** 2, axis=1), rtol=1e-12)
+    # symbol by symbol, and the literal matrix-vector product
+    Z = O.zc_matrix(64, 3, 1)
+    np.testing.assert_allclose(Ap[2], Z @ A[2] / 8.0, atol=1e-12)
+
+
+def test_dense_precoding_recovers_generator_channel():
+    spec = S.FrameSpec(n_sub=64, n_sym=16, qam=16, zc_root=5, zc_shift=2, zc_dense=True, n_targets=2,
+                       noise=False, on_grid=False, rho_max=14, nu_abs_max=7, rayleigh=True)
+    f = S.make_frame(spec, 99, 0)
+    H = O.ls_estimate(f.Y, O.tx_symbols(f.A, 5, 2, O.ZC_DENSE))
+    k = np.arange(64)
+    l = np.arange(16)
+    ref = sum(f.b[p] * np.outer(np.exp(2j * np.pi * l * f.nu[p] / 16), np.exp(-2j * np.pi * k * f.rho[p] / 64))
+              for p in range(2))
+    np.testing.assert_allclose(H, ref, atol=1e-9)
+    # de-precoding the received frame with Z_m^{-1} first, then dividing by A,
+    # does not give the channel (the reading that Eq. 24's inverse cannot take)
+    Zinv = np.linalg.inv(O.zc_matrix(64, 5, 2) / 8.0)
+    H_lit = (f.Y @ Zinv.T) / f.A
+    assert np.max(np.abs(H_lit - ref)) > 0.1
+
+
+def test_dense_precoding_periodogram_single_target():
+    # noiseless: the LS estimate is the channel itself, so P is the precoding-free P
+    kw = dict(n_sub=128, n_sym=32, qam=16, zc_root=7, n_targets=1, noise=False, rho_max=20, nu_abs_max=10)
+    fd = S.make_frame(S.FrameSpec(zc_dense=True, **kw), 5, 0)
+    fn = S.make_frame(S.FrameSpec(**{**kw, "zc_root": None}), 5, 0)
+    Pd = O.frame_periodogram(fd.Y, fd.A, n_pad=512, m_pad=128, n_cp=32, zc_root=7, zc_mode=O.ZC_DENSE)
+    Pn = O.frame_periodogram(fn.Y, fn.A, n_pad=512, m_pad=128, n_cp=32)
+    np.testing.assert_allclose(Pd, Pn, atol=1e-9 * Pn.max())
+
+
 # ------------------------------------------------------- division (Eq. 16)
 def test_ls_estimate_recovers_generator_channel():
     spec = S.FrameSpec(n_sub=64, n_sym=16, qam=16, zc_root=5, n_targets=2, noise=False,
