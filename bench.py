@@ -115,9 +115,10 @@ def cpu_baseline(frames, budget_s):
 
 def time_extras(radar, torch, Yd, Ad, cfg, ws, peaks, n_peaks, status, stream, B, steps, warmup):
     """Figures beside the headline: the same step with sub-cell refinement of
-    the k peaks, with threshold detection (Eq. 18), in the BF16x3 and FP16x3
-    matrix-core forms, the CNN refiner, and FPS-SFT (eight directions, K = 8)
-    on the same frames."""
+    the k peaks, with threshold detection (Eq. 18), with dense ZC precoding
+    (on frames precoded that way), in the BF16x3 and FP16x3 matrix-core forms,
+    the CNN refiner, and FPS-SFT (eight directions, K = 8) on the same
+    frames."""
     import dataclasses
 
     out = {}
@@ -157,6 +158,39 @@ def time_extras(radar, torch, Yd, Ad, cfg, ws, peaks, n_peaks, status, stream, B
     out["threshold_stage_us_per_frame"] = {k: st[k][0] / max(st[k][1], 1) * 1e3 / B for k in ("taps", "peaks")}
     out["threshold_mean_detections"] = float(n_peaks.float().mean())
     del P, wst
+
+    # dense ZC precoding (Eq. 24 read literally): frames whose transmitter
+    # applied the dense precoding; the FP64 precoding-and-division kernel runs
+    # inside the taps stage
+    from synth import frames as S
+    from synth import frames_torch as G
+
+    spec_z = dataclasses.replace(S.spec_full(snr_db=0.0), zc_dense=True)
+    drawn = [G.make_frame(spec_z, 2, i, device=Yd.device) for i in range(B)]
+    Yz = torch.stack([d[0] for d in drawn])
+    Az = torch.stack([d[1] for d in drawn])
+    del drawn
+    cfg_z = dataclasses.replace(cfg, zc_dense=True)
+    wsz = radar.new_workspace(radar.workspace_bytes(cfg_z, B, K), Yd.device)
+    P = torch.empty((B, cfg.m_pad, cfg.n_pad), dtype=torch.float32, device=Yd.device)
+    for _ in range(warmup):
+        radar.frame_process(Yz, Az, cfg_z, K, P=P, workspace=wsz, peaks=peaks, n_peaks=n_peaks, status=status,
+                            stream=stream)
+    radar.timing_start(steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        radar.frame_process(Yz, Az, cfg_z, K, P=P, workspace=wsz, peaks=peaks, n_peaks=n_peaks, status=status,
+                            stream=stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = radar.timing_stop()
+    if int(status.cpu().max()) != 0:
+        raise RuntimeError("device status bits set on the dense-precoded frames")
+    out["zc_dense_frames_per_s"] = B * steps / dt
+    out["zc_dense_stage_us_per_frame"] = {k: st[k][0] / max(st[k][1], 1) * 1e3 / B
+                                          for k in ("taps", "doppler", "range", "peaks")}
+    del P, wsz, Yz, Az
 
     # the matrix-core precision forms of the Doppler and range FFTs, same step
     for name, flag in (("bf16x3", radar.FLAG_BF16X3), ("fp16x3", radar.FLAG_FP16X3)):

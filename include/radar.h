@@ -64,7 +64,10 @@ enum {
 };
 
 enum { RADAR_WIN_RECT = 0, RADAR_WIN_HANN = 1, RADAR_WIN_HAMMING = 2 };  /* periodic windows */
-enum { RADAR_ZC_NONE = 0, RADAR_ZC_DIAG = 1 };  /* ZC precoding along the subcarriers */
+/* ZC precoding (Sec. III-B).  DIAG: each subcarrier k carries z_k a_k, z the
+ * length-N sequence of Eq. 23.  DENSE: Eq. 24 read literally with L = N^2,
+ * each symbol carries a_p = Z_m a / sqrt(N), Z_m[i][j] = zc_L(i N + j). */
+enum { RADAR_ZC_NONE = 0, RADAR_ZC_DIAG = 1, RADAR_ZC_DENSE = 2 };
 enum { RADAR_ST_ZERO_SYMBOL = 1u, RADAR_ST_NONFINITE = 2u };
 /* radar_frame_desc.flags */
 enum {
@@ -84,8 +87,8 @@ typedef struct {
   int32_t m_pad;                /* M' */
   int32_t n_cp;                 /* N_cp */
   int32_t zc_mode;              /* RADAR_ZC_* */
-  int32_t zc_root;              /* r' of Eq. 23, relatively prime to N */
-  int32_t zc_shift;             /* q' of Eq. 23 */
+  int32_t zc_root;              /* r' of Eq. 23, relatively prime to N (and so to N^2) */
+  int32_t zc_shift;             /* q' of Eq. 23, any integer */
   int32_t window;               /* RADAR_WIN_*, applied separably over k and l */
   int32_t flags;                /* RADAR_FLAG_* bits, 0 for none */
   int64_t ld;                   /* elements between consecutive OFDM symbols, >= N */
@@ -119,6 +122,10 @@ int radar_init(void);
  * For each frame f < n_frames (all sharing *d):
  *   H = Y / (z_k * A)                 Eq. 16 with ZC de-precoding (Sec. III-B,
  *                                     z = Eq. 23 sequence, diagonal reading)
+ *   or H = Y / A_p, A_p = Z_m A / sqrt(N) per symbol (RADAR_ZC_DENSE): the
+ *                                     receiver forms A_p from A as D1 F D2 (two
+ *                                     diagonals around an N-point DFT), one
+ *                                     extra FFT per symbol
  *   H' = DFT_N(trunc_{N_cp}(IDFT_N(H)))   per symbol (Eq. 20-22)
  *   P  = Eq. 17 on H' with the separable periodic window, zero padded to
  *        N' x M', scaled by 1/(N M)

@@ -21,6 +21,10 @@ __device__ float2 g_radar_tw[RADAR_TW_ENTRIES];
 #include "k_refine.hpp"
 #include "k_sft.hpp"
 #include "k_cnn.hpp"
+#include "k_dense.hpp"
+
+__device__ double2 g_root64_hi[1 << (RADAR_ROOT64_LOG2 - 12)];
+__device__ double2 g_root64_lo[1 << 12];
 
 namespace {
 
@@ -43,7 +47,8 @@ int validate_desc(const radar_frame_desc* d) {
   if (d->n_pad < N || d->m_pad < M) return RADAR_E_ARG;
   if (d->n_cp < 1 || d->n_cp > N) return RADAR_E_ARG;
   if (d->window < RADAR_WIN_RECT || d->window > RADAR_WIN_HAMMING) return RADAR_E_ARG;
-  if (d->zc_mode != RADAR_ZC_NONE && d->zc_mode != RADAR_ZC_DIAG) return RADAR_E_ARG;
+  if (d->zc_mode != RADAR_ZC_NONE && d->zc_mode != RADAR_ZC_DIAG && d->zc_mode != RADAR_ZC_DENSE)
+    return RADAR_E_ARG;
   if ((d->flags & ~(RADAR_FLAG_REFINE | RADAR_FLAG_BF16X3 | RADAR_FLAG_FP16X3 | RADAR_FLAG_THRESHOLD)) != 0)
     return RADAR_E_ARG;
   if ((d->flags & RADAR_FLAG_THRESHOLD) &&
@@ -54,7 +59,7 @@ int validate_desc(const radar_frame_desc* d) {
   if (!is_pow2(N) || !is_pow2(M) || N < 16 || N > 4096 || M < 16 || M > 4096) return RADAR_E_UNSUPPORTED;
   if (!is_pow2(d->n_pad) || !is_pow2(d->m_pad)) return RADAR_E_UNSUPPORTED;
   if (d->n_pad / N > 8 || d->n_pad > RADAR_TW_LMAX || d->m_pad > RADAR_TW_LMAX) return RADAR_E_UNSUPPORTED;
-  if (d->zc_mode == RADAR_ZC_DIAG && (d->zc_root % 2) == 0) return RADAR_E_NOT_COPRIME;  // N is a power of two
+  if (d->zc_mode != RADAR_ZC_NONE && (d->zc_root % 2) == 0) return RADAR_E_NOT_COPRIME;  // N is a power of two
   if ((d->flags & RADAR_FLAG_REFINE) && (d->m_pad / M > 16 || d->n_pad / N > 16 || M > 1024))
     return RADAR_E_UNSUPPORTED;
   // the matrix-core forms exist for the 4x range-padding kernels
@@ -82,7 +87,8 @@ PeakWs peak_ws_layout(int m_pad, int n_frames, int k, size_t base) {
 struct FrameWs {
   size_t taps, U;
   PeakWs pk;
-  size_t inv_sum;  // [F][M] floats with RADAR_FLAG_THRESHOLD, else == total (no region)
+  size_t inv_sum;  // [F][M] floats with RADAR_FLAG_THRESHOLD (else an empty region)
+  size_t H;        // [F][M][N] LS estimate with RADAR_ZC_DENSE (else an empty region)
   size_t total;
 };
 
@@ -93,7 +99,8 @@ FrameWs frame_ws_layout(const radar_frame_desc* d, int n_frames, int k) {
   w.U = align256(F * d->n_sym * d->n_cp * sizeof(float2));
   w.pk = peak_ws_layout(d->m_pad, n_frames, k, w.U + align256(F * d->m_pad * d->n_cp * sizeof(float2)));
   w.inv_sum = w.pk.total;
-  w.total = w.inv_sum + ((d->flags & RADAR_FLAG_THRESHOLD) ? align256(F * d->n_sym * sizeof(float)) : 0);
+  w.H = w.inv_sum + ((d->flags & RADAR_FLAG_THRESHOLD) ? align256(F * d->n_sym * sizeof(float)) : 0);
+  w.total = w.H + (d->zc_mode == RADAR_ZC_DENSE ? align256(F * d->n_sym * (size_t)d->n_sub * sizeof(float2)) : 0);
   return w;
 }
 
@@ -192,6 +199,18 @@ void launch_k1p_n(const radar::K1Args& a, int M, int F, hipStream_t s) {
   if (grid * C::WAVES > total) grid = (total + C::WAVES - 1) / C::WAVES;
   hipLaunchKernelGGL(radar::k1_taps_p<N>, dim3(grid), dim3(C::BLOCK), 0, s, a, total);
 }
+template <int N>
+void launch_dense_n(const radar::DenseArgs& a, hipStream_t s) {
+  // persistent: as many work-groups as fit on the device at once
+  static int per_cu = 0;
+  if (per_cu == 0 && (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, radar::k_dense_ls<N>,
+                                                                     radar::kDenseThreads, 0) != hipSuccess ||
+                      per_cu < 1))
+    per_cu = 1;
+  int grid = (g_num_cus > 0 ? g_num_cus : 256) * per_cu;
+  if (grid > a.total) grid = a.total;
+  hipLaunchKernelGGL(radar::k_dense_ls<N>, dim3(grid), dim3(radar::kDenseThreads), 0, s, a);
+}
 template <int N, radar::Prec PR>
 void launch_k3x4p_n(const radar::K3Args& a, int m_pad, int F, hipStream_t s) {
   using C = radar::K3p<N>;
@@ -249,6 +268,7 @@ int enqueue_transforms(const radar_frame_desc* d, int F, const float2* in, const
   float2* taps = reinterpret_cast<float2*>(ws + w.taps);
   float2* U = reinterpret_cast<float2*>(ws + w.U);
 
+  float* inv_sum = (d->flags & RADAR_FLAG_THRESHOLD) ? reinterpret_cast<float*>(ws + w.inv_sum) : nullptr;
   radar::K1Args a1{};
   a1.Y = in;
   a1.A = A;
@@ -258,16 +278,47 @@ int enqueue_transforms(const radar_frame_desc* d, int F, const float2* in, const
   a1.status = status;
   a1.M = M;
   a1.n_cp = d->n_cp;
-  const int64_t two_n = 2 * (int64_t)N;
-  const bool zc_on = d->zc_mode == RADAR_ZC_DIAG;
-  a1.zc_root = zc_on ? (uint32_t)(((d->zc_root % two_n) + two_n) % two_n) : 0u;
-  a1.zc_shift = zc_on ? (uint32_t)(((d->zc_shift % two_n) + two_n) % two_n) : 0u;
+  // ZC root and shift reduced modulo 2N (diagonal) or 2N^2 (dense: the phases
+  // of the length-N^2 sequence)
+  const bool dense = d->zc_mode == RADAR_ZC_DENSE;
+  const int64_t period = dense ? 2 * (int64_t)N * N : 2 * (int64_t)N;
+  const bool zc_on = d->zc_mode != RADAR_ZC_NONE;
+  a1.zc_root = zc_on ? (uint32_t)(((d->zc_root % period) + period) % period) : 0u;
+  a1.zc_shift = zc_on ? (uint32_t)(((d->zc_shift % period) + period) % period) : 0u;
   a1.window = d->window;
   a1.from_h = from_h;
   a1.inv_n = 1.0f / (float)N;
   a1.refs = refs;
-  a1.inv_sum = (d->flags & RADAR_FLAG_THRESHOLD) ? reinterpret_cast<float*>(ws + w.inv_sum) : nullptr;
+  a1.inv_sum = inv_sum;
   int slot = timer_open(RADAR_STAGE_TAPS, s);
+  if (dense) {
+    // FP64 precoding and division first; the taps kernel then reads the estimate
+    radar::DenseArgs ad{};
+    ad.Y = in;
+    ad.A = A;
+    ad.ld = d->ld;
+    ad.frame_stride = frame_stride;
+    ad.refs = refs;
+    ad.status = status;
+    ad.H = reinterpret_cast<float2*>(ws + w.H);
+    ad.inv_sum = inv_sum;
+    ad.M = M;
+    ad.total = F * M;
+    ad.zc_root = a1.zc_root;
+    ad.zc_shift = a1.zc_shift;
+#define KD_CALL(n) launch_dense_n<n>(ad, s)
+    RADAR_SIZE_SWITCH(N, KD_CALL)
+#undef KD_CALL
+    RADAR_HIP_CHECK(hipGetLastError());
+    a1.Y = ad.H;
+    a1.A = nullptr;
+    a1.ld = N;
+    a1.frame_stride = (int64_t)M * N;
+    a1.from_h = 1;
+    a1.refs = nullptr;
+    a1.status = nullptr;
+    a1.inv_sum = nullptr;
+  }
 #define K1_CALL(n) launch_k1_n<n>(a1, M, F, s)
   RADAR_SIZE_SWITCH(N, K1_CALL)
 #undef K1_CALL
@@ -393,7 +444,10 @@ int validate_sft(const radar_frame_desc* d, const radar_sft_desc* sd, SftPlan* p
   if (!d || !sd) return RADAR_E_ARG;
   const int N = d->n_sub, M = d->n_sym;
   if (N <= 0 || M <= 0 || d->ld < N || d->flags != 0 || sd->flags != 0) return RADAR_E_ARG;
-  if (d->zc_mode != RADAR_ZC_NONE && d->zc_mode != RADAR_ZC_DIAG) return RADAR_E_ARG;
+  if (d->zc_mode != RADAR_ZC_NONE && d->zc_mode != RADAR_ZC_DIAG && d->zc_mode != RADAR_ZC_DENSE)
+    return RADAR_E_ARG;
+  // the slices gather single elements; dense precoding mixes whole symbols
+  if (d->zc_mode == RADAR_ZC_DENSE) return RADAR_E_UNSUPPORTED;
   if (sd->n_dirs < 1 || sd->n_dirs > radar::kSftMaxDirs) return RADAR_E_ARG;
   if (sd->k < 1 || sd->k > radar::kSftMaxK) return RADAR_E_ARG;
   if (!(sd->pfa > 0.0f && sd->pfa < 1.0f) || !(sd->tol > 0.0f && sd->tol <= 1.0f)) return RADAR_E_ARG;
@@ -803,6 +857,21 @@ int radar_init(void) {
         for (int k = 0; k < N; ++k) tab[off + b * N + k] = w((long long)k * b, (long long)F * N);
     }
   if (hipMemcpyToSymbol(HIP_SYMBOL(g_radar_tw), tab.data(), tab.size() * sizeof(float2), 0,
+                        hipMemcpyHostToDevice) != hipSuccess)
+    return RADAR_E_HIP;
+  // FP64 roots exp(+2 pi i x / 2^25), x = hi * 2^12 + lo, for the dense precoding stage
+  std::vector<double2> r_hi(1 << (RADAR_ROOT64_LOG2 - 12)), r_lo(1 << 12);
+  for (size_t i = 0; i < r_hi.size(); ++i) {
+    const double ang = 2.0 * M_PI * (double)i / (double)r_hi.size();
+    r_hi[i] = make_double2(std::cos(ang), std::sin(ang));
+  }
+  for (size_t i = 0; i < r_lo.size(); ++i) {
+    const double ang = 2.0 * M_PI * (double)i / (double)(1 << RADAR_ROOT64_LOG2);
+    r_lo[i] = make_double2(std::cos(ang), std::sin(ang));
+  }
+  if (hipMemcpyToSymbol(HIP_SYMBOL(g_root64_hi), r_hi.data(), r_hi.size() * sizeof(double2), 0,
+                        hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpyToSymbol(HIP_SYMBOL(g_root64_lo), r_lo.data(), r_lo.size() * sizeof(double2), 0,
                         hipMemcpyHostToDevice) != hipSuccess)
     return RADAR_E_HIP;
   g_init_done[dev] = true;

@@ -24,7 +24,7 @@ RADAR_E_HIP = -4
 RADAR_E_NOT_COPRIME = -5
 
 WIN_RECT, WIN_HANN, WIN_HAMMING = 0, 1, 2
-ZC_NONE, ZC_DIAG = 0, 1
+ZC_NONE, ZC_DIAG, ZC_DENSE = 0, 1, 2
 ST_ZERO_SYMBOL, ST_NONFINITE = 1, 2
 FLAG_REFINE, FLAG_BF16X3, FLAG_FP16X3, FLAG_THRESHOLD = 1, 2, 4, 8
 
@@ -172,10 +172,11 @@ class Config:
     threshold: bool = False     # Eq. 18 detection (pfa, noise_power)
     pfa: float = 1e-2
     noise_power: float = 0.0
+    zc_dense: bool = False      # Eq. 24 read literally (L = N^2) instead of the diagonal reading
 
     def desc(self, ld: int | None = None) -> FrameDesc:
         return FrameDesc(self.n_sub, self.n_sym, self.n_pad, self.m_pad, self.n_cp,
-                         ZC_NONE if self.zc_root is None else ZC_DIAG,
+                         ZC_NONE if self.zc_root is None else (ZC_DENSE if self.zc_dense else ZC_DIAG),
                          0 if self.zc_root is None else int(self.zc_root), int(self.zc_shift),
                          int(self.window),
                          (FLAG_REFINE if self.refine else 0) | int(self.precision)

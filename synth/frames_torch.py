@@ -10,12 +10,19 @@ arithmetic.
 
 from __future__ import annotations
 
+import functools
 import math
 
 import numpy as np
 import torch
 
 from synth import frames as S
+
+
+@functools.lru_cache(maxsize=4)
+def _dense_matrix(n: int, root: int, shift: int) -> np.ndarray:
+    # the transmitter's N x N matrix Z[i, j] = zc(i N + j) of a length-N^2 sequence
+    return S.tx_precoding_sequence(n * n, root, shift).reshape(n, n)
 
 
 def make_frame(spec: S.FrameSpec, config_id: int, frame_index: int, device="cuda"):
@@ -40,7 +47,10 @@ def make_frame(spec: S.FrameSpec, config_id: int, frame_index: int, device="cuda
         rng_ph = torch.exp(-2j * math.pi * k * float(rho[p]) / n)
         echo += complex(b[p]) * torch.outer(dop, rng_ph)
     tx = A.to(torch.complex128)
-    if spec.zc_root is not None:
+    if spec.zc_root is not None and spec.zc_dense:
+        Z = torch.from_numpy(_dense_matrix(n, spec.zc_root, spec.zc_shift)).to(device)
+        tx = (tx @ Z.transpose(0, 1).contiguous()) / math.sqrt(n)
+    elif spec.zc_root is not None:
         z = torch.from_numpy(S.tx_precoding_sequence(n, spec.zc_root, spec.zc_shift)).to(device)
         tx = tx * z[None, :]
     Y = tx * echo

@@ -154,6 +154,24 @@ def test_threshold_rejected_by_periodogram_and_sft():
     assert L.radar_fps_sft_workspace_size(ctypes.byref(cfg.desc()), ctypes.byref(s), 1) == 0
 
 
+def test_dense_precoding_validation():
+    L = radar.lib()
+    ok = radar.Config(256, 64, 1024, 256, 32, zc_root=7, zc_shift=-3, zc_dense=True)
+    assert ok.desc().zc_mode == radar.ZC_DENSE
+    # plus the FP64 stage's LS estimate, [F][M][N] complex64
+    assert L.radar_frame_workspace_size(ctypes.byref(ok.desc()), 2, 3) == (
+        _ws(radar.Config(256, 64, 1024, 256, 32), 2, 3) + _al(2 * 64 * 256 * 8))
+    even = radar.Config(256, 64, 1024, 256, 32, zc_root=4, zc_dense=True)
+    d = even.desc()
+    assert L.radar_frame_workspace_size(ctypes.byref(d), 1, 3) == 0
+    # FPS-SFT gathers single elements: the dense transform is not offered there
+    s = radar.sft_desc(8)
+    assert L.radar_fps_sft_workspace_size(ctypes.byref(ok.desc()), ctypes.byref(s), 1) == 0
+    bad = ok.desc()
+    bad.zc_mode = 3
+    assert L.radar_frame_workspace_size(ctypes.byref(bad), 1, 3) == 0
+
+
 def test_sft_default_settings():
     d = radar.sft_desc(8)
     assert (d.n_dirs, d.k, d.flags) == (8, 8, 0)

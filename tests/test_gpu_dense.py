@@ -1,0 +1,204 @@
+"""GPU parity of dense Zadoff-Chu precoding (Eq. 24 read literally,
+RADAR_ZC_DENSE) against the FP64 oracle, through the C ABI.
+
+The GPU forms the precoded symbols A_p = Z_m A / sqrt(N) from A itself (two
+diagonals around an N-point FFT per symbol) and divides by them; the oracle
+multiplies by the literal N x N matrix of the length-N^2 sequence.  Inputs are
+drawn by a transmitter that applies its own dense precoding.
+"""
+
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import radar_oracle as O
+from synth import frames as S
+from tests.gpu_util import P_TOL_FP32, check_topk_property, compare_peak_indices, normwise_error, oracle_ranked, \
+    rounded, say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+radar = pytest.importorskip("paper_2209_03883_amd.radar")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    radar.lib()
+
+
+def _run(frames, cfg, k):
+    Y, A = S.frames_to_complex64(frames)
+    P, peaks, n_peaks, status = radar.frame_process(torch.from_numpy(Y).cuda(), torch.from_numpy(A).cuda(), cfg, k)
+    torch.cuda.synchronize()
+    return P.cpu().numpy(), radar.unpack_peaks(peaks, n_peaks.cpu()), status.cpu().numpy()
+
+
+def _oracle_P(frame, cfg):
+    return O.frame_periodogram(rounded(frame.Y), rounded(frame.A), n_pad=cfg.n_pad, m_pad=cfg.m_pad, n_cp=cfg.n_cp,
+                               window_kind=cfg.window, zc_root=cfg.zc_root, zc_shift=cfg.zc_shift,
+                               zc_mode=O.ZC_DENSE)
+
+
+def _check(P_gpu, pk_gpu, frame, cfg, k, label, tol=P_TOL_FP32):
+    P_ref = _oracle_P(frame, cfg)
+    err = normwise_error(P_gpu, P_ref)
+    say(f"{label}: normwise P error {err:.3e}")
+    assert err <= tol, (label, err)
+    assert check_topk_property(P_gpu, pk_gpu, k) is None
+    ref = oracle_ranked(O, P_ref, k)
+    assert compare_peak_indices([(s, r) for s, r, *_ in pk_gpu], ref, P_ref) is not None, (label, pk_gpu, ref)
+    return P_ref
+
+
+def _spec(n, m, root, shift, snr_db, n_cp, n_targets=2):
+    return S.FrameSpec(n_sub=n, n_sym=m, qam=16, zc_root=root, zc_shift=shift, zc_dense=True, n_targets=n_targets,
+                       snr_db=snr_db, on_grid=False, rho_min=0.0, rho_max=max(1.0, min(n_cp, n) - 1.0),
+                       nu_abs_max=m / 2 - 1, rayleigh=True, min_sep=1.5)
+
+
+@pytest.mark.parametrize("snr_db", [10.0, 0.0])
+def test_small_workload_dense(snr_db):
+    cfg = radar.Config(256, 64, 1024, 256, 32, zc_root=1, window=radar.WIN_HANN, zc_dense=True)
+    frames = [S.make_frame(S.FrameSpec(n_sub=256, n_sym=64, qam=4, zc_root=1, zc_dense=True, n_targets=3,
+                                       snr_db=snr_db), 6, i) for i in range(3)]
+    say(f"dense precoding, small workload, {snr_db} dB")
+    P, pk, st = _run(frames, cfg, 3)
+    for f, frame in enumerate(frames):
+        assert st[f] == 0
+        _check(P[f], pk[f], frame, cfg, 3, f"frame {f}")
+
+
+# (N, M, N', M', N_cp, root, shift): the generic taps kernel (N < 256, N >= 2048)
+# and the persistent one (256 <= N <= 1024); roots and shifts beyond 2N and
+# negative shifts exercise the reductions modulo 2N^2
+DENSE_SHAPES = [
+    (16, 16, 64, 32, 16, 3, 0),
+    (64, 32, 256, 64, 16, 5, -7),
+    (256, 16, 1024, 64, 64, 1001, 12345),
+    (512, 32, 2048, 64, 128, 7, 3),
+    (1024, 16, 4096, 32, 256, 7, 0),
+    (2048, 16, 8192, 32, 512, 9, 1),
+    (4096, 16, 16384, 16, 1024, 4095, -1),
+]
+
+
+@pytest.mark.parametrize("shape", DENSE_SHAPES, ids=[f"{s[0]}x{s[1]}-r{s[5]}-q{s[6]}" for s in DENSE_SHAPES])
+def test_dense_shapes(shape):
+    n, m, n_pad, m_pad, n_cp, root, shift = shape
+    cfg = radar.Config(n, m, n_pad, m_pad, n_cp, zc_root=root, zc_shift=shift, zc_dense=True)
+    frame = S.make_frame(_spec(n, m, root, shift, 10.0, n_cp), 60, n)
+    say(f"dense shape {shape}")
+    P, pk, st = _run([frame], cfg, 3)
+    assert st[0] == 0
+    _check(P[0], pk[0], frame, cfg, 3, f"shape {shape}")
+
+
+@pytest.mark.parametrize("snr_db", [10.0, -10.0])
+def test_full_frame_dense(snr_db):
+    cfg = radar.Config(1024, 1024, 4096, 4096, 256, zc_root=7, zc_dense=True)
+    frame = S.make_frame(dataclasses.replace(S.spec_full(snr_db=snr_db), zc_dense=True), 61, 0)
+    say(f"dense precoding, full frame, {snr_db} dB")
+    P, pk, st = _run([frame], cfg, 8)
+    assert st[0] == 0
+    _check(P[0], pk[0], frame, cfg, 8, f"full {snr_db} dB")
+
+
+def test_dense_differs_from_diagonal_and_matches_its_own_transmitter():
+    # the same frame decoded under the wrong reading loses the targets
+    spec = S.FrameSpec(n_sub=256, n_sym=64, qam=16, zc_root=3, zc_dense=True, n_targets=2, noise=False,
+                       rho_max=30, nu_abs_max=20)
+    frame = S.make_frame(spec, 62, 0)
+    dense = radar.Config(256, 64, 1024, 256, 64, zc_root=3, zc_dense=True)
+    diag = radar.Config(256, 64, 1024, 256, 64, zc_root=3)
+    say("dense vs diagonal reading")
+    _, pk_d, _ = _run([frame], dense, 2)
+    _, pk_g, _ = _run([frame], diag, 2)
+    want = sorted((int(round(v * 4)), int(round(r * 4))) for r, v in zip(frame.rho, frame.nu))
+    assert sorted((s, r) for s, r, *_ in pk_d[0]) == want
+    assert sorted((s, r) for s, r, *_ in pk_g[0]) != want
+
+
+def test_dense_with_threshold_detection():
+    frames = [S.make_frame(S.FrameSpec(n_sub=256, n_sym=64, qam=4, zc_root=1, zc_dense=True, n_targets=3,
+                                       snr_db=0.0), 63, i) for i in range(2)]
+    cfg = radar.Config(256, 64, 1024, 256, 32, zc_root=1, zc_dense=True, threshold=True, pfa=1e-3, noise_power=1.0)
+    say("dense precoding with threshold detection")
+    P, pk, _ = _run(frames, cfg, 64)
+    for f, frame in enumerate(frames):
+        P_ref = _oracle_P(frame, cfg)
+        assert normwise_error(P[f], P_ref) <= P_TOL_FP32
+        # eta from the symbols the division used: the precoded ones
+        eta = O.cfar_threshold(O.precode_dense(rounded(frame.A), 1), 1.0, 1e-3, cfg.window)
+        det = O.detect_threshold(P_ref, eta, 64)
+        half = cfg.m_pad // 2
+        ref = [(row - half, r, v) for row, r, v in det]
+        assert 0 < len(det) < 64
+        assert len(pk[f]) == len(ref)
+        assert compare_peak_indices([(s, r) for s, r, *_ in pk[f]], ref, P_ref) is not None
+        say(f"frame {f}: {len(pk[f])} detections")
+
+
+def test_dense_batch_matches_frames_alone():
+    shapes = [(256, 64, 1024, 256, 32, 1), (1024, 16, 4096, 64, 256, 7), (2048, 16, 8192, 32, 512, 3)]
+    jobs, alone = [], []
+    for i, (n, m, nq, mq, ncp, root) in enumerate(shapes):
+        cfg = radar.Config(n, m, nq, mq, ncp, zc_root=root, zc_dense=True)
+        f = S.make_frame(_spec(n, m, root, 0, 5.0, ncp), 64, i)
+        Y, A = S.frames_to_complex64([f])
+        jobs.append((torch.from_numpy(Y[0]).cuda(), torch.from_numpy(A[0]).cuda(), cfg, 4))
+        alone.append(_run([f], cfg, 4))
+    say("dense precoding in a batch")
+    b = radar.Batch(jobs, graph=True)
+    b.launch()
+    torch.cuda.synchronize()
+    for i in range(len(jobs)):
+        P, pk, st = b.results(i)
+        assert st == 0
+        np.testing.assert_array_equal(P, alone[i][0][0])
+        assert pk == alone[i][1][0]
+    b.close()
+
+
+def _hits(pk, rho, nu, n_pad_over_n=4, m_pad_over_m=4, m_pad=4096):
+    hit = 0
+    for r0, v0 in zip(rho, nu):
+        for s, r, *_ in pk:
+            ds = (s - v0 * m_pad_over_m + m_pad / 2) % m_pad - m_pad / 2
+            if abs(r - r0 * n_pad_over_n) <= 2 and abs(ds) <= 2:
+                hit += 1
+                break
+    return hit
+
+
+def test_dense_precoding_noise_enhancement():
+    """Under the dense reading the receiver divides by precoded symbols that
+    are close to complex Gaussian, so the LS estimate's noise grows by
+    mean(1/|a_p|^2) / mean(1/|a|^2) against the diagonal reading (which
+    leaves the statistics unchanged).  Eight full frames at -35 dB per
+    element, the same targets, symbols and noise under both readings: the
+    fraction of targets among the top-8 peaks."""
+    from synth import frames_torch as G
+
+    spec = S.spec_full(snr_db=-35.0)
+    A0 = rounded(S.make_frame(spec, 65, 0).A)
+    gain = float(np.mean(1.0 / np.abs(O.precode_dense(A0, 7)) ** 2) / np.mean(1.0 / np.abs(A0) ** 2))
+    say(f"noise enhancement of the dense reading's LS estimate: {gain:.2f} ({10 * np.log10(gain):.1f} dB)")
+    assert gain > 3.0
+    hits = {}
+    for dense in (False, True):
+        cfg = radar.Config(1024, 1024, 4096, 4096, 256, zc_root=7, zc_dense=dense)
+        h = tot = 0
+        for i in range(8):
+            Y, A, (rho, nu, _) = G.make_frame(dataclasses.replace(spec, zc_dense=dense), 65, i)
+            _, peaks, n_peaks, st = radar.frame_process(Y[None], A[None], cfg, 8)
+            pk = radar.unpack_peaks(peaks, n_peaks.cpu())[0]
+            assert int(st.cpu()[0]) == 0
+            h += _hits(pk, rho, nu)
+            tot += len(rho)
+        hits[dense] = h / tot
+    say(f"targets among the top-8 peaks at -35 dB: diagonal {hits[False]:.3f}, dense {hits[True]:.3f}")
+    assert hits[False] > hits[True]
