@@ -150,6 +150,30 @@ def dft_ce(H: np.ndarray, n_cp: int) -> np.ndarray:
     return np.fft.fft(taps, axis=1)
 
 
+def wiener_tap_weights(tap_power, noise_var_tap: float) -> np.ndarray:
+    """Per-tap LMMSE (Wiener) weights of the LMMSE-based DFT-CE of Sec. III-A
+    (Fig. 5), read as a diagonal estimator in the tap domain: with the tap
+    estimate hhat(n) = h(n) + w(n), E|h(n)|^2 = p(n) and white w of variance
+    s per tap, the linear estimate of h(n) with least mean squared error is
+    g(n) hhat(n), g(n) = p(n) / (p(n) + s)."""
+    p = np.asarray(tap_power, dtype=np.float64)
+    return p / (p + float(noise_var_tap))
+
+
+def lmmse_dft_ce(H: np.ndarray, n_cp: int, weights) -> np.ndarray:
+    """LMMSE-based DFT-CE: Eq. 20, then the kept taps n < N_cp each scaled by
+    its weight (wiener_tap_weights) instead of kept whole (Eq. 21), then
+    Eq. 22.  n_cp = N with the same weights is the LMMSE-based LS-CE."""
+    H = np.asarray(H, dtype=np.complex128)
+    g = np.asarray(weights, dtype=np.float64)
+    if g.shape != (n_cp,):
+        raise ValueError("one weight per kept tap")
+    taps = np.fft.ifft(H, axis=1)
+    taps[:, n_cp:] = 0.0
+    taps[:, :n_cp] *= g[None, :]
+    return np.fft.fft(taps, axis=1)
+
+
 # --------------------------------------------------------------------------
 # Window (Sec. II-B.2, the matrix W of Eq. 17; Hamming in Sec. IV)
 # --------------------------------------------------------------------------
@@ -198,10 +222,11 @@ def periodogram(H: np.ndarray, n_pad: int, m_pad: int, window_kind: int = WINDOW
 
 
 def frame_periodogram(Y, A, *, n_pad, m_pad, n_cp, window_kind=WINDOW_HANN,
-                      zc_root=None, zc_shift=0, zc_mode=ZC_DIAG):
-    """The whole estimator of Fig. 2 / Fig. 3: de-precode, divide, DFT-CE, Eq. 17."""
+                      zc_root=None, zc_shift=0, zc_mode=ZC_DIAG, tap_weights=None):
+    """The whole estimator of Fig. 2 / Fig. 3: de-precode, divide, DFT-CE
+    (LMMSE-based with per-tap weights if given), Eq. 17."""
     H = ls_estimate(Y, tx_symbols(A, zc_root, zc_shift, zc_mode))
-    Hd = dft_ce(H, n_cp)
+    Hd = dft_ce(H, n_cp) if tap_weights is None else lmmse_dft_ce(H, n_cp, tap_weights)
     return periodogram(Hd, n_pad, m_pad, window_kind)
 
 

@@ -163,6 +163,28 @@ def spec_full(snr_db: float = 0.0, n_sub: int = 1024, n_sym: int = 1024, n_targe
                      rayleigh=True)
 
 
+def tap_power_profile(spec: FrameSpec, grid: int = 64) -> np.ndarray:
+    """E|h(n)|^2 of the generator's channel in the tap domain (the IDFT over
+    the subcarriers, with 1/N), n < N: one target of delay rho gives the taps
+    b D(n - rho), D(x) = (1/N) sum_k exp(2 pi i k x / N), so the profile is
+    n_targets E|b|^2 E_rho |D(n - rho)|^2 over the spec's range distribution
+    (integer bins, or `grid` points per bin for off-grid delays).  The
+    second-order statistics a receiver with prior knowledge of the scene would
+    use; separation between targets is ignored."""
+    n = spec.n_sub
+    if spec.on_grid:
+        rhos = np.arange(int(spec.rho_min), int(spec.rho_max) + 1, dtype=np.float64)
+    else:
+        cnt = max(2, int(np.ceil((spec.rho_max - spec.rho_min) * grid)))
+        rhos = spec.rho_min + (np.arange(cnt) + 0.5) * (spec.rho_max - spec.rho_min) / cnt
+    x = np.arange(n, dtype=np.float64)[:, None] - rhos[None, :]
+    # |D(x)|^2 = sin^2(pi x) / (N^2 sin^2(pi x / N)), 1 where x is a multiple of N
+    den = (n * np.sin(np.pi * x / n)) ** 2
+    small = den < 1e-24
+    d2 = np.where(small, 1.0, np.sin(np.pi * x) ** 2 / np.where(small, 1.0, den))
+    return spec.n_targets * d2.mean(axis=1)  # E|b|^2 = 1 (unit phasor or CN(0, 1))
+
+
 def frames_to_complex64(frames):
     """Stack frames as contiguous complex64 arrays (F, M, N) for the GPU path."""
     Y = np.stack([f.Y for f in frames]).astype(np.complex64)

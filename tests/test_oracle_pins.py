@@ -5,6 +5,7 @@ paper prints (tests/golden), closed forms, invariants, brute-force sums on tiny
 inputs, and the independent channel model of the synthetic frame generator.
 """
 
+import dataclasses
 import math
 import os
 
@@ -136,6 +137,73 @@ def test_dense_precoding_periodogram_single_target():
     Pd = O.frame_periodogram(fd.Y, fd.A, n_pad=512, m_pad=128, n_cp=32, zc_root=7, zc_mode=O.ZC_DENSE)
     Pn = O.frame_periodogram(fn.Y, fn.A, n_pad=512, m_pad=128, n_cp=32)
     np.testing.assert_allclose(Pd, Pn, atol=1e-9 * Pn.max())
+
+
+# ------------------------------------------- LMMSE-based DFT-CE (Fig. 5)
+@pytest.mark.parametrize("p,s", [(1.0, 1.0), (4.0, 0.5), (0.1, 2.0), (1e-3, 1e-3)])
+def test_wiener_weight_mse_closed_form(p, s):
+    # h ~ CN(0, p), hhat = h + w, w ~ CN(0, s): E|g hhat - h|^2 = p s / (p + s),
+    # below both the raw estimate's s and the zero estimate's p
+    rng = np.random.default_rng(7)
+    n = 400000
+    h = (rng.standard_normal(n) + 1j * rng.standard_normal(n)) * np.sqrt(p / 2)
+    x = h + (rng.standard_normal(n) + 1j * rng.standard_normal(n)) * np.sqrt(s / 2)
+    g = float(O.wiener_tap_weights([p], s)[0])
+    mse = float(np.mean(np.abs(g * x - h) ** 2))
+    assert mse == pytest.approx(p * s / (p + s), rel=0.02)
+    assert mse < min(p, s)
+    # and g is the minimiser: nudging it either way costs
+    assert mse < float(np.mean(np.abs(1.05 * g * x - h) ** 2)) and mse < float(np.mean(np.abs(0.95 * g * x - h) ** 2))
+
+
+def test_lmmse_dft_ce_unit_weights_is_dft_ce():
+    rng = np.random.default_rng(8)
+    H = rng.standard_normal((4, 64)) + 1j * rng.standard_normal((4, 64))
+    np.testing.assert_allclose(O.lmmse_dft_ce(H, 16, np.ones(16)), O.dft_ce(H, 16), atol=1e-13)
+    # weights far above the noise tend to 1; zero prior power removes the tap
+    g = O.wiener_tap_weights(np.r_[np.full(8, 1e12), np.zeros(8)], 1.0)
+    np.testing.assert_allclose(g, np.r_[np.ones(8), np.zeros(8)], atol=1e-11)
+
+
+def test_tap_power_profile():
+    on = S.FrameSpec(n_sub=64, n_sym=8, n_targets=3, on_grid=True, rho_min=2, rho_max=9)
+    p = S.tap_power_profile(on)
+    np.testing.assert_allclose(p[2:10], 3 / 8, rtol=1e-12)
+    assert np.max(np.abs(np.r_[p[:2], p[10:]])) < 1e-12
+    off = S.FrameSpec(n_sub=128, n_sym=8, n_targets=5, on_grid=False, rho_min=1.0, rho_max=20.0)
+    q = S.tap_power_profile(off)
+    assert float(q.sum()) == pytest.approx(5.0, rel=1e-9)  # Parseval: each target brings unit energy
+    # one delay, brute force: taps of exp(-2 pi i k rho / N) by the IDFT sum
+    k = np.arange(128)
+    taps = np.array([np.mean(np.exp(-2j * np.pi * k * 7.3 / 128) * np.exp(2j * np.pi * k * n / 128))
+                     for n in range(128)])
+    one = S.tap_power_profile(dataclasses.replace(off, n_targets=1, rho_min=7.3, rho_max=7.3 + 1e-9), grid=1)
+    np.testing.assert_allclose(one, np.abs(taps) ** 2, atol=1e-9)
+
+
+def test_lmmse_estimators_mse_ordering():
+    # Fig. 5: channel MSE of LMMSE-based DFT-CE < DFT-CE < LS-CE, and
+    # LMMSE-based LS-CE < LS-CE, on the generator's frames with its own prior
+    spec = S.FrameSpec(n_sub=256, n_sym=32, qam=16, zc_root=3, n_targets=4, snr_db=-5.0, on_grid=False,
+                       rho_min=1.0, rho_max=40.0, nu_abs_max=15.0, rayleigh=True)
+    n_cp = 64
+    prior = S.tap_power_profile(spec)
+    sigma2 = 10 ** (5.0 / 10)
+    err = {"ls": 0.0, "lmmse_ls": 0.0, "dft": 0.0, "lmmse_dft": 0.0}
+    for i in range(6):
+        f = S.make_frame(spec, 90, i)
+        H = O.ls_estimate(f.Y, O.tx_symbols(f.A, 3))
+        k, l = np.arange(256), np.arange(32)
+        true = sum(f.b[p] * np.outer(np.exp(2j * np.pi * l * f.nu[p] / 32), np.exp(-2j * np.pi * k * f.rho[p] / 256))
+                   for p in range(spec.n_targets))
+        s_tap = sigma2 * float(np.mean(1.0 / np.abs(f.A) ** 2)) / 256
+        est = {"ls": H, "dft": O.dft_ce(H, n_cp),
+               "lmmse_ls": O.lmmse_dft_ce(H, 256, O.wiener_tap_weights(prior, s_tap)),
+               "lmmse_dft": O.lmmse_dft_ce(H, n_cp, O.wiener_tap_weights(prior[:n_cp], s_tap))}
+        for key, v in est.items():
+            err[key] += float(np.mean(np.abs(v - true) ** 2))
+    assert err["lmmse_dft"] < err["dft"] < err["ls"]
+    assert err["lmmse_ls"] < err["ls"]
 
 
 # ------------------------------------------------------- division (Eq. 16)
