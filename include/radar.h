@@ -94,6 +94,9 @@ typedef struct {
   int64_t ld;                   /* elements between consecutive OFDM symbols, >= N */
   float pfa;                    /* RADAR_FLAG_THRESHOLD: false-alarm probability per cell, (0, 1) */
   float noise_power;            /* RADAR_FLAG_THRESHOLD: noise power sigma^2 per received element, > 0 */
+  const float *tap_weights;     /* device, n_cp floats g(n) scaling the kept DFT-CE taps (LMMSE-based
+                                   DFT-CE, Sec. III-A / Fig. 5; see radar_tap_wiener_weights), or NULL
+                                   for plain DFT-CE; 4-byte aligned, caller-owned */
 } radar_frame_desc;
 
 /* One detected peak of P.  s is the signed Doppler index (row - M'/2), r the
@@ -126,7 +129,9 @@ int radar_init(void);
  *                                     receiver forms A_p from A as D1 F D2 (two
  *                                     diagonals around an N-point DFT), one
  *                                     extra FFT per symbol
- *   H' = DFT_N(trunc_{N_cp}(IDFT_N(H)))   per symbol (Eq. 20-22)
+ *   H' = DFT_N(trunc_{N_cp}(IDFT_N(H)))   per symbol (Eq. 20-22); with
+ *                                     d->tap_weights, kept tap n is scaled by
+ *                                     tap_weights[n] (LMMSE-based DFT-CE)
  *   P  = Eq. 17 on H' with the separable periodic window, zero padded to
  *        N' x M', scaled by 1/(N M)
  *   peaks = the k largest 3x3 cyclic local maxima of P, ranked by
@@ -167,6 +172,22 @@ int radar_frame_process(const radar_frame_desc *d, int32_t n_frames,
                         float *P, int64_t p_frame_stride,
                         int32_t k, radar_peak *peaks, int32_t *n_peaks, uint32_t *status,
                         void *ws, size_t ws_bytes, void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * radar_tap_wiener_weights -- per-tap LMMSE weights of the LMMSE-based DFT-CE
+ * (Sec. III-A, Fig. 5), host only, no GPU call.
+ *
+ * With the tap estimate hhat(n) = h(n) + w(n) (the IDFT over the subcarriers
+ * of the LS estimate, 1/N included), prior tap power p(n) = E|h(n)|^2 and
+ * white noise of variance noise_var_tap per tap (sigma^2 mean(1/|a|^2) / N),
+ * the least-mean-square linear estimate of h(n) is g(n) hhat(n) with
+ *   g(n) = p(n) / (p(n) + noise_var_tap).
+ * tap_power: host, n doubles >= 0; weights: host, n floats out.
+ * RADAR_E_ARG on NULL pointers, n < 1, a negative or non-finite power, or
+ * noise_var_tap < 0 or non-finite (noise_var_tap = 0 gives 1 where p > 0, 0
+ * where p = 0).
+ * ------------------------------------------------------------------------ */
+int radar_tap_wiener_weights(const double *tap_power, int32_t n, double noise_var_tap, float *weights);
 
 /* ------------------------------------------------------------------------
  * radar_periodogram -- Eq. 17 from a channel estimate the caller already has.

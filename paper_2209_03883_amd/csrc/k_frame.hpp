@@ -32,6 +32,7 @@ struct K1Args {
   float inv_n;            // 1/N
   const FrameRef* refs;   // per-frame Y, A, status (batch jobs), or null: base + f * frame_stride
   float* inv_sum;         // [F][M] sum_k 1/|a_{l,k}|^2 per symbol (threshold detection), or null
+  const float* tap_w;     // [n_cp] LMMSE weights of the kept taps, or null (plain DFT-CE)
 };
 
 // Sum over the T threads of one team (T a power of two; teams inside one
@@ -108,7 +109,7 @@ __global__ void __launch_bounds__(kBlock) k1_taps(K1Args a) {
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
     const int n = t + T * e;
-    if (n < a.n_cp) out[n] = cscale(v[e], scale);
+    if (n < a.n_cp) out[n] = cscale(v[e], a.tap_w ? scale * a.tap_w[n] : scale);
   }
   if (st) {
     uint32_t* sp = a.refs ? a.refs[f].status : (a.status ? a.status + f : nullptr);
@@ -192,7 +193,7 @@ __global__ void __launch_bounds__(K1p<N>::BLOCK) k1_taps_p(K1Args a, int total_g
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int n = t + T * e;
-      if (n < a.n_cp) out[n] = cscale(v[e], scale);
+      if (n < a.n_cp) out[n] = cscale(v[e], a.tap_w ? scale * a.tap_w[n] : scale);
     }
     if (st) {
       uint32_t* sp = a.refs ? a.refs[f].status : (a.status ? a.status + f : nullptr);

@@ -56,6 +56,7 @@ int validate_desc(const radar_frame_desc* d) {
     return RADAR_E_ARG;
   if ((d->flags & RADAR_FLAG_BF16X3) && (d->flags & RADAR_FLAG_FP16X3)) return RADAR_E_ARG;
   if (d->ld < N) return RADAR_E_ARG;
+  if (reinterpret_cast<uintptr_t>(d->tap_weights) & 3) return RADAR_E_ARG;
   if (!is_pow2(N) || !is_pow2(M) || N < 16 || N > 4096 || M < 16 || M > 4096) return RADAR_E_UNSUPPORTED;
   if (!is_pow2(d->n_pad) || !is_pow2(d->m_pad)) return RADAR_E_UNSUPPORTED;
   if (d->n_pad / N > 8 || d->n_pad > RADAR_TW_LMAX || d->m_pad > RADAR_TW_LMAX) return RADAR_E_UNSUPPORTED;
@@ -290,6 +291,7 @@ int enqueue_transforms(const radar_frame_desc* d, int F, const float2* in, const
   a1.inv_n = 1.0f / (float)N;
   a1.refs = refs;
   a1.inv_sum = inv_sum;
+  a1.tap_w = d->tap_weights;
   int slot = timer_open(RADAR_STAGE_TAPS, s);
   if (dense) {
     // FP64 precoding and division first; the taps kernel then reads the estimate
@@ -448,6 +450,7 @@ int validate_sft(const radar_frame_desc* d, const radar_sft_desc* sd, SftPlan* p
     return RADAR_E_ARG;
   // the slices gather single elements; dense precoding mixes whole symbols
   if (d->zc_mode == RADAR_ZC_DENSE) return RADAR_E_UNSUPPORTED;
+  if (d->tap_weights) return RADAR_E_ARG;  // no DFT-CE taps on this path
   if (sd->n_dirs < 1 || sd->n_dirs > radar::kSftMaxDirs) return RADAR_E_ARG;
   if (sd->k < 1 || sd->k > radar::kSftMaxK) return RADAR_E_ARG;
   if (!(sd->pfa > 0.0f && sd->pfa < 1.0f) || !(sd->tol > 0.0f && sd->tol <= 1.0f)) return RADAR_E_ARG;
@@ -649,7 +652,7 @@ struct BatchGroup {
 bool same_group(const radar_frame_desc& a, int ka, const radar_frame_desc& b, int kb) {
   return ka == kb && a.n_sub == b.n_sub && a.n_sym == b.n_sym && a.n_pad == b.n_pad && a.m_pad == b.m_pad &&
          a.n_cp == b.n_cp && a.zc_mode == b.zc_mode && a.zc_root == b.zc_root && a.zc_shift == b.zc_shift &&
-         a.window == b.window && a.flags == b.flags && a.ld == b.ld;
+         a.window == b.window && a.flags == b.flags && a.ld == b.ld && a.tap_weights == b.tap_weights;
 }
 
 int validate_job(const radar_frame_job& j) {
@@ -875,6 +878,18 @@ int radar_init(void) {
                         hipMemcpyHostToDevice) != hipSuccess)
     return RADAR_E_HIP;
   g_init_done[dev] = true;
+  return RADAR_OK;
+}
+
+int radar_tap_wiener_weights(const double* tap_power, int32_t n, double noise_var_tap, float* weights) {
+  if (!tap_power || !weights || n < 1 || !(noise_var_tap >= 0.0) || !std::isfinite(noise_var_tap))
+    return RADAR_E_ARG;
+  for (int32_t i = 0; i < n; ++i)
+    if (!(tap_power[i] >= 0.0) || !std::isfinite(tap_power[i])) return RADAR_E_ARG;
+  for (int32_t i = 0; i < n; ++i) {
+    const double p = tap_power[i], den = p + noise_var_tap;
+    weights[i] = den > 0.0 ? (float)(p / den) : 0.0f;
+  }
   return RADAR_OK;
 }
 

@@ -36,7 +36,7 @@ EXPORTED = (
     "radar_batch_workspace_size", "radar_batch_create", "radar_batch_launch", "radar_batch_info",
     "radar_batch_destroy",
     "radar_cnn_param_count", "radar_cnn_workspace_size", "radar_cnn_patches", "radar_cnn_forward",
-    "radar_cnn_gradient", "radar_cnn_adam", "radar_cnn_train_step",
+    "radar_cnn_gradient", "radar_cnn_adam", "radar_cnn_train_step", "radar_tap_wiener_weights",
 )
 BATCH_GRAPH, BATCH_TUNE = 1, 2
 STAGES = ("taps", "doppler", "range", "peaks", "refine", "sft_slices", "sft_decode")
@@ -57,6 +57,7 @@ class FrameDesc(ctypes.Structure):
         ("window", ctypes.c_int32), ("flags", ctypes.c_int32),
         ("ld", ctypes.c_int64),
         ("pfa", ctypes.c_float), ("noise_power", ctypes.c_float),
+        ("tap_weights", ctypes.c_void_p),
     ]
 
 
@@ -125,6 +126,9 @@ def lib() -> ctypes.CDLL:
     L.radar_batch_destroy.restype = None
     L.radar_batch_destroy.argtypes = [vp]
     fp = ctypes.c_void_p
+    L.radar_tap_wiener_weights.restype = ctypes.c_int
+    L.radar_tap_wiener_weights.argtypes = [ctypes.POINTER(ctypes.c_double), i32, ctypes.c_double,
+                                           ctypes.POINTER(ctypes.c_float)]
     L.radar_cnn_param_count.restype = i32
     L.radar_cnn_workspace_size.restype = sz
     L.radar_cnn_workspace_size.argtypes = [i32, i32]
@@ -173,6 +177,7 @@ class Config:
     pfa: float = 1e-2
     noise_power: float = 0.0
     zc_dense: bool = False      # Eq. 24 read literally (L = N^2) instead of the diagonal reading
+    tap_weights: torch.Tensor | None = None  # n_cp float32 on the device: LMMSE-based DFT-CE
 
     def desc(self, ld: int | None = None) -> FrameDesc:
         return FrameDesc(self.n_sub, self.n_sym, self.n_pad, self.m_pad, self.n_cp,
@@ -181,7 +186,16 @@ class Config:
                          int(self.window),
                          (FLAG_REFINE if self.refine else 0) | int(self.precision)
                          | (FLAG_THRESHOLD if self.threshold else 0),
-                         int(self.n_sub if ld is None else ld), float(self.pfa), float(self.noise_power))
+                         int(self.n_sub if ld is None else ld), float(self.pfa), float(self.noise_power),
+                         self._tap_weights_ptr())
+
+    def _tap_weights_ptr(self):
+        w = self.tap_weights
+        if w is None:
+            return None
+        if w.dtype != torch.float32 or w.dim() != 1 or w.numel() != self.n_cp or not w.is_contiguous():
+            raise ValueError("tap_weights must be a contiguous float32 vector of n_cp entries")
+        return w.data_ptr()
 
 
 def _stream_ptr(stream) -> int:
@@ -203,6 +217,16 @@ def _as_frames(x: torch.Tensor, cfg: Config, name: str) -> torch.Tensor:
 
 def _frame_stride(x: torch.Tensor) -> int:
     return int(x.stride(0)) if x.shape[0] > 1 else int(x.shape[1] * x.stride(1))
+
+
+def tap_wiener_weights(tap_power, noise_var_tap: float) -> list:
+    """radar_tap_wiener_weights: g(n) = p(n) / (p(n) + noise_var_tap), as floats."""
+    p = [float(v) for v in tap_power]
+    n = len(p)
+    src = (ctypes.c_double * n)(*p)
+    dst = (ctypes.c_float * n)()
+    _check(lib().radar_tap_wiener_weights(src, n, float(noise_var_tap), dst), "radar_tap_wiener_weights")
+    return list(dst)
 
 
 def workspace_bytes(cfg: Config, n_frames: int, k: int = 1) -> int:

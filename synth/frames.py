@@ -177,12 +177,14 @@ def tap_power_profile(spec: FrameSpec, grid: int = 64) -> np.ndarray:
     else:
         cnt = max(2, int(np.ceil((spec.rho_max - spec.rho_min) * grid)))
         rhos = spec.rho_min + (np.arange(cnt) + 0.5) * (spec.rho_max - spec.rho_min) / cnt
-    x = np.arange(n, dtype=np.float64)[:, None] - rhos[None, :]
-    # |D(x)|^2 = sin^2(pi x) / (N^2 sin^2(pi x / N)), 1 where x is a multiple of N
-    den = (n * np.sin(np.pi * x / n)) ** 2
-    small = den < 1e-24
-    d2 = np.where(small, 1.0, np.sin(np.pi * x) ** 2 / np.where(small, 1.0, den))
-    return spec.n_targets * d2.mean(axis=1)  # E|b|^2 = 1 (unit phasor or CN(0, 1))
+    acc = np.zeros(n)
+    for c0 in range(0, rhos.size, 256):
+        x = np.arange(n, dtype=np.float64)[:, None] - rhos[None, c0:c0 + 256]
+        # |D(x)|^2 = sin^2(pi x) / (N^2 sin^2(pi x / N)), 1 where x is a multiple of N
+        den = (n * np.sin(np.pi * x / n)) ** 2
+        small = den < 1e-24
+        acc += np.where(small, 1.0, np.sin(np.pi * x) ** 2 / np.where(small, 1.0, den)).sum(axis=1)
+    return spec.n_targets * acc / rhos.size  # E|b|^2 = 1 (unit phasor or CN(0, 1))
 
 
 def frames_to_complex64(frames):

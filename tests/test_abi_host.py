@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -170,6 +171,34 @@ def test_dense_precoding_validation():
     bad = ok.desc()
     bad.zc_mode = 3
     assert L.radar_frame_workspace_size(ctypes.byref(bad), 1, 3) == 0
+
+
+def test_tap_wiener_weights_host():
+    from oracle import radar_oracle as O
+
+    p = [0.0, 1e-3, 0.5, 2.0, 1e6]
+    g = radar.tap_wiener_weights(p, 0.25)
+    np.testing.assert_allclose(g, O.wiener_tap_weights(p, 0.25).astype(np.float32), rtol=1e-7)
+    assert radar.tap_wiener_weights([0.0, 3.0], 0.0) == [0.0, 1.0]
+    L = radar.lib()
+    src = (ctypes.c_double * 2)(1.0, -1.0)
+    dst = (ctypes.c_float * 2)()
+    assert L.radar_tap_wiener_weights(src, 2, 1.0, dst) == radar.RADAR_E_ARG      # negative power
+    src = (ctypes.c_double * 2)(1.0, 1.0)
+    assert L.radar_tap_wiener_weights(src, 2, -1.0, dst) == radar.RADAR_E_ARG     # negative noise
+    assert L.radar_tap_wiener_weights(src, 2, float("nan"), dst) == radar.RADAR_E_ARG
+    assert L.radar_tap_wiener_weights(src, 0, 1.0, dst) == radar.RADAR_E_ARG
+
+
+def test_tap_weights_validation():
+    L = radar.lib()
+    d = radar.Config(256, 64, 1024, 256, 32, zc_root=1).desc()
+    d.tap_weights = 4096 + 2  # misaligned device address (never dereferenced here)
+    assert L.radar_frame_workspace_size(ctypes.byref(d), 1, 3) == 0
+    d.tap_weights = 4096
+    assert L.radar_frame_workspace_size(ctypes.byref(d), 1, 3) > 0
+    s = radar.sft_desc(8)
+    assert L.radar_fps_sft_workspace_size(ctypes.byref(d), ctypes.byref(s), 1) == 0
 
 
 def test_sft_default_settings():
