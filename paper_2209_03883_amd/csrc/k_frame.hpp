@@ -548,9 +548,23 @@ struct K3p {
   using Inv = PlanLayout<N, INV, 1>;
 };
 
+// Phase 0 of the range IDFT (r = 4 r1) without a transform: the windowed
+// spectrum's inverse at the native bins is the three-tap filter c0 u[r1] +
+// c1 (u[r1-1] + u[r1+1]) of the taps (zero beyond N/4, u[N] = u[0]).
+template <int N>
+__device__ __forceinline__ float2 phase0_filter(const float2* ub, int r1, float c0, float c1) {
+  constexpr int Q = N / 4;
+  if (r1 <= Q) return cadd(cscale(ub[r1], c0), cscale(cadd(ub[r1 - 1], ub[r1 + 1]), c1));
+  if (r1 == N - 1) return cscale(ub[0], c1);
+  return make_float2(0.0f, 0.0f);
+}
+
 template <int N, Prec PR = Prec::FP32>
 __global__ void __launch_bounds__(K3p<N>::BLOCK) k3_range_power_x4p(K3Args a, int total_groups) {
   using C = K3p<N>;
+  // one 16-byte store per four-phase group where holding two phases fits in
+  // registers (no scratch): measured for the FP32 form at N >= 512
+  constexpr bool kOneStore = PR == Prec::FP32 && N >= 512;
   typename DftFor<PR>::type df;
   df.init();
   constexpr int T = C::T;
@@ -575,7 +589,7 @@ __global__ void __launch_bounds__(K3p<N>::BLOCK) k3_range_power_x4p(K3Args a, in
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int g = lane / T;
-  const int t = lane - g * T;
+  const int t0 = lane - g * T;
   float2* lds = xch[wave][g];
   float2* ub = ubuf[wave][g] + 1;                        // ub[i] = u[i], i in [-1, N/4+1]
   const float2 wc = window_coeffs(a.window);
@@ -586,6 +600,11 @@ __global__ void __launch_bounds__(K3p<N>::BLOCK) k3_range_power_x4p(K3Args a, in
     const int f = grow / a.m_pad;
     const int row = grow - f * a.m_pad;
     const float2* in = a.U + (int64_t)grow * a.n_cp;
+    // the team lane, opaque to the optimiser, so that the per-element LDS
+    // addresses are formed again for every row rather than held in registers
+    // (an empty asm statement emits no instruction)
+    int t = t0;
+    asm volatile("" : "+v"(t));
     {
       float2 uv[Q / T];
 #pragma unroll
@@ -611,46 +630,70 @@ __global__ void __launch_bounds__(K3p<N>::BLOCK) k3_range_power_x4p(K3Args a, in
     for (int e = 0; e < 16; ++e) X[e] = cscale(X[e], wc.x - wc.y * cwin[t + T * e]);
 
     RADAR_GLOBAL float* dst = gptr(a.refs ? a.refs[f].P : a.P + (int64_t)f * a.p_stride) + (int64_t)row * (4 * N);
-    float mx = 0.0f;
-    float p_first[16];
+    if constexpr (kOneStore) {
+      // phases 1, 2, 3 in turn; X dies after the last twiddle product, so
+      // holding p1 and p2 through the last transform costs no more registers
+      // than X did, and each four-phase group of P leaves in one 16-byte store
+      float p1[16], p2[16];
 #pragma unroll
-    for (int b = 2; b <= 4; ++b) {
-      const int phase = b == 4 ? 1 : b;
-      float2 gv[16];
+      for (int phase = 1; phase <= 3; ++phase) {
+        float2 gv[16];
 #pragma unroll
-      for (int e = 0; e < 16; ++e) gv[e] = cmulc(X[e], tab[C::PH + (phase - 1) * N + t + T * e]);
-      fft_stages<N, 16, 1, true>(gv, lds, t, true, tw_inv, df);
-      if (phase == 2) {
-#pragma unroll
-        for (int e = 0; e < 16; ++e) p_first[e] = cabs2(gv[e]) * a.scale;
-      } else if (phase == 3) {
+        for (int e = 0; e < 16; ++e) gv[e] = cmulc(X[e], tab[C::PH + (phase - 1) * N + t + T * e]);
+        fft_stages<N, 16, 1, true>(gv, lds, t, true, tw_inv, df);
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-          const float p3 = cabs2(gv[e]) * a.scale;
-          gstore2(dst + 2 * (2 * (t + T * e) + 1), p_first[e], p3);
-          mx = fmaxf(mx, fmaxf(p_first[e], p3));
+          const float pv = cabs2(gv[e]) * a.scale;
+          if (phase == 1) p1[e] = pv;
+          else if (phase == 2) p2[e] = pv;
+          else gv[e].x = pv;  // p3
         }
-      } else {
+        if (phase == 3) {
+          float mx = 0.0f;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) p_first[e] = cabs2(gv[e]) * a.scale;
+          for (int e = 0; e < 16; ++e) {
+            const float p0 = cabs2(phase0_filter<N>(ub, t + T * e, c0, c1)) * a.scale;
+            gstore4(dst + 4 * (t + T * e), p0, p1[e], p2[e], gv[e].x);
+            mx = fmaxf(mx, fmaxf(fmaxf(p0, p1[e]), fmaxf(p2[e], gv[e].x)));
+          }
+#pragma unroll
+          for (int m = T / 2; m > 0; m >>= 1) mx = fmaxf(mx, __shfl_xor(mx, m));
+          if (t == 0) a.rowmax[grow] = mx;
+        }
       }
-    }
+    } else {
+      // phases 2 and 3 leave as one 8-byte store, then phase 1 and phase 0
+      float mx = 0.0f;
+      float p_first[16];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int r1 = t + T * e;
-      float2 gz = make_float2(0.0f, 0.0f);
-      if (r1 <= Q) {
-        gz = cadd(cscale(ub[r1], c0), cscale(cadd(ub[r1 - 1], ub[r1 + 1]), c1));
-      } else if (r1 == N - 1) {
-        gz = cscale(ub[0], c1);  // u[N] = u[0]
+      for (int b = 2; b <= 4; ++b) {
+        const int phase = b == 4 ? 1 : b;
+        float2 gv[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) gv[e] = cmulc(X[e], tab[C::PH + (phase - 1) * N + t + T * e]);
+        fft_stages<N, 16, 1, true>(gv, lds, t, true, tw_inv, df);
+        if (phase == 3) {
+#pragma unroll
+          for (int e = 0; e < 16; ++e) {
+            const float p3 = cabs2(gv[e]) * a.scale;
+            gstore2(dst + 2 * (2 * (t + T * e) + 1), p_first[e], p3);
+            mx = fmaxf(mx, fmaxf(p_first[e], p3));
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < 16; ++e) p_first[e] = cabs2(gv[e]) * a.scale;
+        }
       }
-      const float p0 = cabs2(gz) * a.scale;
-      gstore2(dst + 4 * r1, p0, p_first[e]);
-      mx = fmaxf(mx, fmaxf(p0, p_first[e]));
-    }
 #pragma unroll
-    for (int m = T / 2; m > 0; m >>= 1) mx = fmaxf(mx, __shfl_xor(mx, m));
-    if (t == 0) a.rowmax[grow] = mx;
+      for (int e = 0; e < 16; ++e) {
+        const float p0 = cabs2(phase0_filter<N>(ub, t + T * e, c0, c1)) * a.scale;
+        gstore2(dst + 4 * (t + T * e), p0, p_first[e]);
+        mx = fmaxf(mx, fmaxf(p0, p_first[e]));
+      }
+#pragma unroll
+      for (int m = T / 2; m > 0; m >>= 1) mx = fmaxf(mx, __shfl_xor(mx, m));
+      if (t == 0) a.rowmax[grow] = mx;
+    }
     // the next row's tap writes must follow this row's reads of ub
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   }
