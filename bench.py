@@ -287,6 +287,25 @@ def _match_errors(truth_rho, truth_nu, det, n, m):
     return [(dr[i, j], dv[i, j]) for i, j in zip(rows, cols)]
 
 
+def device_copy_gbs(torch, dev, mib=2048, reps=5):
+    """Bandwidth of a plain device-to-device copy of `mib` MiB (read + write
+    bytes over time, HIP events): the practical HBM ceiling beside the 8 TB/s
+    datasheet figure."""
+    n = mib * (1 << 20) // 4
+    src = torch.empty(n, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    t1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * n * 4 * reps / (t0.elapsed_time(t1) * 1e-3) / 1e9
+    del src, dst
+    return gbs
+
+
 def time_batch(radar, torch, n_frames, steps):
     """The uneven Monte-Carlo batch: n_frames frames of random N x M shapes in
     one autotuned, graph-captured plan (4x padding both axes, N_cp = N/4, Hann,
@@ -424,6 +443,7 @@ def main():
         print(f"[bench] batch {({k: v for k, v in extras.items() if k.startswith('batch_') and 'rmse' not in k})}",
               file=sys.stderr, flush=True)
 
+    copy_gbs = device_copy_gbs(torch, dev)
     frames_done = B * args.steps
     fps = frames_done / dt
     rng_ms, rng_n = stages["range"]
@@ -454,6 +474,8 @@ def main():
             "frames_per_step": B,
             "periodogram_materialised": True,
             "hbm_roofline_frames_per_s": HBM_PEAK_GBS * 1e9 / (16 * N * M + 4 * PAD * N * PAD * M),
+            "device_copy_gbs": copy_gbs,
+            "k3_frac_of_device_copy": achieved / copy_gbs,
             "stage_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in stages.items() if v[1]},
             **extras,
         },

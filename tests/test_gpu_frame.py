@@ -229,3 +229,34 @@ def test_detect_topk_fewer_peaks_than_k():
     torch.cuda.synchronize()
     assert int(n_peaks.cpu()[0]) == 1
     assert radar.unpack_peaks(peaks, n_peaks.cpu())[0][0][:3] == (3 - 8, 9, 100.0)
+
+
+def test_bench_launch_configuration_sampled():
+    """The launch the benchmark times: 128 full frames drawn on the GPU (same
+    recipe and seeds), one radar_frame_process call, top-8.  Every frame is
+    clean with eight peaks; three sampled frames match the oracle run on the
+    same complex64 inputs."""
+    from synth import frames_torch as G
+
+    B = 128
+    drawn = [G.make_frame(S.spec_full(snr_db=0.0), 2, i) for i in range(B)]
+    Yd = torch.stack([d[0] for d in drawn])
+    Ad = torch.stack([d[1] for d in drawn])
+    cfg = radar.Config(1024, 1024, 4096, 4096, 256, zc_root=7, window=radar.WIN_HANN)
+    say("bench launch configuration: 128 full frames in one call")
+    P, peaks, n_peaks, status = radar.frame_process(Yd, Ad, cfg, 8)
+    torch.cuda.synchronize()
+    assert int(status.abs().max().cpu()) == 0
+    assert bool((n_peaks == 8).all().cpu())
+    pk_all = radar.unpack_peaks(peaks, n_peaks.cpu())
+    for f in (0, 64, 127):
+        Pf = P[f].cpu().numpy()
+        Y = Yd[f].cpu().numpy().astype(np.complex128)
+        A = Ad[f].cpu().numpy().astype(np.complex128)
+        P_ref = O.frame_periodogram(Y, A, n_pad=4096, m_pad=4096, n_cp=256, window_kind=radar.WIN_HANN, zc_root=7)
+        err = normwise_error(Pf, P_ref)
+        say(f"frame {f}: normwise P error {err:.3e}")
+        assert err <= P_TOL_FP32
+        assert check_topk_property(Pf, pk_all[f], 8) is None
+        assert compare_peak_indices([(s, r) for s, r, *_ in pk_all[f]], oracle_ranked(O, P_ref, 8), P_ref) is not None
+    del P, Yd, Ad
