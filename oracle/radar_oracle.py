@@ -557,3 +557,64 @@ def cfar_threshold(A, noise_power: float, pfa: float, window_kind: int = WINDOW_
 def detect_threshold(P: np.ndarray, eta: float, k: int):
     """The local maxima of P at or above eta, ranked as find_peaks, at most k."""
     return [pk for pk in find_peaks(P, k) if pk[2] >= eta]
+
+
+# --------------------------------------------------------------------------
+# Time-domain frame simulation (Sec. II-B.1, Eq. 1-2 and Eq. 7-10)
+#
+# Time is counted in samples T0 = 1/(N df).  Symbol l occupies samples
+# [l Ns, (l+1) Ns), Ns = N + Ng, with its cyclic prefix first; the
+# transmitted waveform (Eq. 1-2) is, for t in that interval,
+#     x(t) = (1/N) sum_k a_{l,k} exp(+2 pi i k (t - l Ns - Ng) / N).
+# A point target p (Eq. 7-8) returns b_p exp(+2 pi i fD_p t) x(t - alpha_p(t))
+# with the delay alpha_p(t) = rho_p + B_p t (rho in samples, i.e. native
+# range bins).  Doppler is given in bins of the M-point Doppler DFT, so
+# fD_p T0 = nu_p / (M Ns) and the per-sample CFO is eps_p = nu_p N / (M Ns)
+# subcarrier spacings; the time-scale factor is B_p = fD_p / fc = eps_p df / fc.
+# Reading: the time-scale term is taken at the start of each symbol's useful
+# part (t_l = l Ns + Ng) and held through that symbol, so it moves the delay
+# from symbol to symbol (range migration); the drift inside one symbol (B N,
+# about 1e-3 samples at the paper's parameters) is dropped.  The receiver
+# removes the prefix and takes the N-point DFT of each symbol's useful part.
+# Eq. 11 is this model with eps_p -> 0 and B_p -> 0.
+# --------------------------------------------------------------------------
+def ofdm_waveform(A, n_guard: int, t) -> np.ndarray:
+    """x(t) of Eq. 1-2 at (real) sample times t, zero outside the frame."""
+    A = np.asarray(A, dtype=np.complex128)
+    m, n = A.shape
+    ns = n + n_guard
+    t = np.asarray(t, dtype=np.float64)
+    sym = np.floor(t / ns).astype(np.int64)
+    out = np.zeros(t.shape, dtype=np.complex128)
+    k = np.arange(n, dtype=np.float64)
+    for i in range(t.size):
+        if 0 <= sym[i] < m:
+            u = t[i] - sym[i] * ns - n_guard
+            out[i] = np.sum(A[sym[i]] * np.exp(2j * np.pi * k * u / n)) / n
+    return out
+
+
+def simulate_frame(A, targets, *, n_guard: int, fc_over_df: float, noise=None) -> np.ndarray:
+    """Received frequency-domain frame Y (M, N) of the time-domain model above.
+
+    targets: iterable of (rho, nu, b) with rho in samples, nu in Doppler bins,
+    b complex.  noise: optional (M, N) added after the receiver's DFT."""
+    A = np.asarray(A, dtype=np.complex128)
+    m, n = A.shape
+    ns = n + n_guard
+    mm = np.arange(n, dtype=np.float64)
+    kk = np.arange(n, dtype=np.float64)
+    dft = np.exp(-2j * np.pi * np.outer(kk, mm) / n)  # receiver DFT, rows k', columns m
+    Y = np.zeros((m, n), dtype=np.complex128)
+    for l in range(m):
+        t = l * ns + n_guard + mm                      # the useful part's sample times
+        y = np.zeros(n, dtype=np.complex128)
+        for rho, nu, b in targets:
+            eps = nu * n / (m * ns)
+            B = eps / fc_over_df
+            delay = rho + B * (l * ns + n_guard)       # alpha at the symbol's start
+            y += b * np.exp(2j * np.pi * nu * t / (m * ns)) * ofdm_waveform(A, n_guard, t - delay)
+        Y[l] = dft @ y
+    if noise is not None:
+        Y = Y + np.asarray(noise, dtype=np.complex128)
+    return Y

@@ -206,6 +206,73 @@ def test_lmmse_estimators_mse_ordering():
     assert err["lmmse_ls"] < err["ls"]
 
 
+# ----------------------------------- time-domain frame model (Eq. 1-2, 7-10)
+def _qpsk(rng, m, n):
+    return (rng.choice([-1.0, 1.0], (m, n)) + 1j * rng.choice([-1.0, 1.0], (m, n))) / np.sqrt(2.0)
+
+
+def test_time_domain_static_target_is_eq11():
+    # no motion, delay inside the prefix: the received symbol is a times the
+    # channel's phase ramp, exactly (Eq. 11 holds with equality)
+    rng = np.random.default_rng(21)
+    A = _qpsk(rng, 8, 32)
+    for rho in (0.0, 3.0, 5.5, 8.0):
+        Y = O.simulate_frame(A, [(rho, 0.0, 0.7 - 0.2j)], n_guard=8, fc_over_df=320833.0)
+        k = np.arange(32)
+        np.testing.assert_allclose(Y, (0.7 - 0.2j) * A * np.exp(-2j * np.pi * k * rho / 32)[None, :], atol=1e-12)
+
+
+def test_time_domain_ici_closed_form():
+    # one active subcarrier k0, Doppler eps subcarrier spacings: the receiver
+    # sees |D(eps - q)| at k0 + q, D(x) = sin(pi x) / (N sin(pi x / N))
+    m, n, ng = 4, 64, 16
+    A = np.zeros((m, n), complex)
+    k0 = 20
+    A[:, k0] = 1.0
+    for nu in (0.3, 1.7, -2.2):
+        eps = nu * n / (m * (n + ng))
+        Y = O.simulate_frame(A, [(2.0, nu, 1.0)], n_guard=ng, fc_over_df=320833.0)
+        for q in range(-3, 4):
+            x = eps - q
+            ref = abs(np.sin(np.pi * x) / (n * np.sin(np.pi * x / n)))
+            assert abs(Y[1, k0 + q]) == pytest.approx(ref, rel=1e-9, abs=1e-13)
+
+
+def test_time_domain_range_migration_phase():
+    # the time-scale factor moves the delay by B (l Ns + Ng) from symbol to
+    # symbol: the phase of one subcarrier follows it (a small fc/df makes the
+    # effect large)
+    m, n, ng, fc_df, nu, rho = 6, 32, 8, 40.0, 1.5, 2.0
+    A = np.zeros((m, n), complex)
+    k0 = 9
+    A[:, k0] = 1.0
+    Y = O.simulate_frame(A, [(rho, nu, 1.0)], n_guard=ng, fc_over_df=fc_df)
+    ns = n + ng
+    eps = nu * n / (m * ns)
+    B = eps / fc_df
+    dsum = np.sum(np.exp(2j * np.pi * eps * np.arange(n) / n)) / n
+    for l in range(m):
+        tl = l * ns + ng
+        ref = np.exp(2j * np.pi * nu * tl / (m * ns)) * np.exp(-2j * np.pi * k0 * (rho + B * tl) / n) * dsum
+        assert Y[l, k0] == pytest.approx(ref, abs=1e-12)
+
+
+def test_time_domain_slow_targets_approach_eq11():
+    # as the Doppler shrinks, the frame approaches Eq. 11 (the generator's
+    # frequency-domain model) up to the constant phase of the prefix
+    rng = np.random.default_rng(22)
+    m, n, ng = 16, 64, 16
+    A = _qpsk(rng, m, n)
+    k, l = np.arange(n), np.arange(m)
+    errs = []
+    for nu in (2.0, 0.2, 0.02):
+        Y = O.simulate_frame(A, [(4.0, nu, 1.0)], n_guard=ng, fc_over_df=320833.0)
+        eq11 = A * np.outer(np.exp(2j * np.pi * l * nu / m), np.exp(-2j * np.pi * k * 4.0 / n))
+        eq11 *= np.exp(2j * np.pi * nu * ng / (m * (n + ng)))
+        errs.append(float(np.max(np.abs(Y - eq11))))
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 0.01
+
+
 # ------------------------------------------------------- division (Eq. 16)
 def test_ls_estimate_recovers_generator_channel():
     spec = S.FrameSpec(n_sub=64, n_sym=16, qam=16, zc_root=5, n_targets=2, noise=False,
