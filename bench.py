@@ -116,9 +116,9 @@ def cpu_baseline(frames, budget_s):
 def time_extras(radar, torch, Yd, Ad, cfg, ws, peaks, n_peaks, status, stream, B, steps, warmup):
     """Figures beside the headline: the same step with sub-cell refinement of
     the k peaks, with threshold detection (Eq. 18), with dense ZC precoding
-    (on frames precoded that way), in the BF16x3 and FP16x3 matrix-core forms,
-    the CNN refiner, and FPS-SFT (eight directions, K = 8) on the same
-    frames."""
+    (on frames precoded that way), the time-domain frame simulation, in the
+    BF16x3 and FP16x3 matrix-core forms, the CNN refiner, and FPS-SFT (eight
+    directions, K = 8) on the same frames."""
     import dataclasses
 
     out = {}
@@ -191,6 +191,25 @@ def time_extras(radar, torch, Yd, Ad, cfg, ws, peaks, n_peaks, status, stream, B
     out["zc_dense_stage_us_per_frame"] = {k: st[k][0] / max(st[k][1], 1) * 1e3 / B
                                           for k in ("taps", "doppler", "range", "peaks")}
     del P, wsz, Yz, Az
+
+    # the time-domain frame simulation (Eq. 1-2, 7-10): B frames of eight
+    # moving targets from the same symbols
+    gen = torch.Generator(device=Yd.device)
+    gen.manual_seed(9)
+    tg = torch.rand((B, 8, 4), generator=gen, device=Yd.device)
+    tg[:, :, 0] = tg[:, :, 0] * 200.0 + 10.0                      # delays well inside the 256-sample prefix
+    tg[:, :, 1] = (tg[:, :, 1] - 0.5) * (cfg.n_sym - 2)          # Doppler over the unambiguous range
+    tg[:, :, 2:] = tg[:, :, 2:] - 0.5
+    nt = torch.full((B,), 8, dtype=torch.int32, device=Yd.device)
+    for _ in range(warmup):
+        radar.simulate_frames(Ad, tg, nt, n_guard=cfg.n_cp, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        Ysim, _ = radar.simulate_frames(Ad, tg, nt, n_guard=cfg.n_cp, stream=stream)
+    torch.cuda.synchronize()
+    out["simulate_frames_per_s_8_targets"] = B * steps / (time.perf_counter() - t0)
+    del Ysim, tg, nt
 
     # the matrix-core precision forms of the Doppler and range FFTs, same step
     for name, flag in (("bf16x3", radar.FLAG_BF16X3), ("fp16x3", radar.FLAG_FP16X3)):

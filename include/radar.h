@@ -68,7 +68,8 @@ enum { RADAR_WIN_RECT = 0, RADAR_WIN_HANN = 1, RADAR_WIN_HAMMING = 2 };  /* peri
  * length-N sequence of Eq. 23.  DENSE: Eq. 24 read literally with L = N^2,
  * each symbol carries a_p = Z_m a / sqrt(N), Z_m[i][j] = zc_L(i N + j). */
 enum { RADAR_ZC_NONE = 0, RADAR_ZC_DIAG = 1, RADAR_ZC_DENSE = 2 };
-enum { RADAR_ST_ZERO_SYMBOL = 1u, RADAR_ST_NONFINITE = 2u };
+enum { RADAR_ST_ZERO_SYMBOL = 1u, RADAR_ST_NONFINITE = 2u,
+       RADAR_ST_ISI = 4u /* radar_simulate_frames: a target's delay left [0, n_guard] */ };
 /* radar_frame_desc.flags */
 enum {
   RADAR_FLAG_REFINE = 1,   /* sub-cell refinement of the peaks (radar_frame_process) */
@@ -378,6 +379,50 @@ int radar_cnn_adam(float *theta, const float *grad, float *m, float *v, int32_t 
 int radar_cnn_train_step(float *theta, float *m, float *v, int32_t step, float lr, const float *patches,
                          const float *labels, int32_t batch, float *loss, void *ws, size_t ws_bytes,
                          void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * radar_simulate_frames -- received frames from the time-domain model of
+ * Sec. II-B.1 (Eq. 1-2 transmitter with cyclic prefix, Eq. 7-10 moving point
+ * targets), to test how far Eq. 11's frequency-domain model holds.
+ *
+ * Time in samples T0 = 1/(N df); symbol l's useful part starts at
+ * t_l = l (N + n_guard) + n_guard.  Target p has delay rho (samples = native
+ * range bins), Doppler nu (bins of the M-point Doppler DFT) and amplitude b;
+ * its CFO is eps = nu N / (M (N + n_guard)) subcarrier spacings and its
+ * time-scale factor B = eps / fc_over_df, so its delay during symbol l is
+ * d_l = rho + B t_l (held through the symbol).  While 0 <= d_l <= n_guard:
+ *   Y[l][k'] = sum_m e^{-2 pi i k' m/N} sum_p b_p e^{+2 pi i nu_p (t_l + m)/(M (N + n_guard))}
+ *              (1/N) sum_k A[l][k] e^{+2 pi i k (m - d_l)/N}      (+ noise[l][k'])
+ * which keeps the inter-carrier interference (eps) and the range migration
+ * (B) that Eq. 11 drops.  A delay outside [0, n_guard] sets RADAR_ST_ISI
+ * in status[f] (the frame then lacks the inter-symbol interference).
+ * A:        device, frame f at A + f*frame_stride, [M][ld] (the symbols on the
+ *           subcarriers, after any precoding).
+ * targets:  device, [n_frames][max_targets]; n_targets: device, [n_frames]
+ *           (entries beyond n_targets[f] are ignored; clamped to [0, max]).
+ * noise:    device, same layout as Y, added after the DFT, or NULL.
+ * Y:        device output, same layout as A.  status: device, [n_frames]
+ *           words ORed with RADAR_ST_ISI (not cleared), or NULL.
+ * Sizes: N, M powers of two in [16, 4096]; 0 <= n_guard <= N; ld >= N;
+ * 1 <= max_targets <= 1024; fc_over_df > 0 and finite.  No workspace.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  float rho, nu;                /* delay (samples), Doppler (bins) */
+  float b_re, b_im;             /* complex amplitude */
+} radar_sim_target;
+
+typedef struct {
+  int32_t n_sub;                /* N */
+  int32_t n_sym;                /* M */
+  int32_t n_guard;              /* cyclic prefix in samples */
+  int32_t max_targets;
+  int64_t ld;
+  double fc_over_df;            /* carrier over subcarrier spacing (Table I: 77e9 / 240e3) */
+} radar_sim_desc;
+
+int radar_simulate_frames(const radar_sim_desc *d, int32_t n_frames, const radar_cf32 *A, int64_t frame_stride,
+                          const radar_sim_target *targets, const int32_t *n_targets,
+                          const radar_cf32 *noise, radar_cf32 *Y, uint32_t *status, void *hip_stream);
 
 /* ------------------------------------------------------------------------
  * Stage timing -- a profiling aid, off by default.

@@ -22,6 +22,7 @@ __device__ float2 g_radar_tw[RADAR_TW_ENTRIES];
 #include "k_sft.hpp"
 #include "k_cnn.hpp"
 #include "k_dense.hpp"
+#include "k_sim.hpp"
 
 __device__ double2 g_root64_hi[1 << (RADAR_ROOT64_LOG2 - 12)];
 __device__ double2 g_root64_lo[1 << 12];
@@ -878,6 +879,45 @@ int radar_init(void) {
                         hipMemcpyHostToDevice) != hipSuccess)
     return RADAR_E_HIP;
   g_init_done[dev] = true;
+  return RADAR_OK;
+}
+
+int radar_simulate_frames(const radar_sim_desc* d, int32_t n_frames, const radar_cf32* A, int64_t frame_stride,
+                          const radar_sim_target* targets, const int32_t* n_targets, const radar_cf32* noise,
+                          radar_cf32* Y, uint32_t* status, void* hip_stream) {
+  if (!d || !A || !targets || !n_targets || !Y) return RADAR_E_ARG;
+  const int N = d->n_sub, M = d->n_sym;
+  if (N <= 0 || M <= 0 || d->ld < N || d->n_guard < 0 || d->n_guard > N) return RADAR_E_ARG;
+  if (d->max_targets < 1 || d->max_targets > 1024) return RADAR_E_ARG;
+  if (!(d->fc_over_df > 0.0) || !std::isfinite(d->fc_over_df)) return RADAR_E_ARG;
+  if (n_frames < 1 || n_frames > 65535) return RADAR_E_ARG;
+  if (!is_pow2(N) || !is_pow2(M) || N < 16 || N > 4096 || M < 16 || M > 4096) return RADAR_E_UNSUPPORTED;
+  const int64_t frame_elems = (int64_t)(M - 1) * d->ld + N;
+  if (n_frames > 1 && frame_stride < frame_elems) return RADAR_E_ARG;
+  int rc = ensure_init();
+  if (rc != RADAR_OK) return rc;
+  radar::SimArgs a{};
+  a.A = reinterpret_cast<const float2*>(A);
+  a.ld = d->ld;
+  a.frame_stride = frame_stride;
+  a.targets = targets;
+  a.n_targets = n_targets;
+  a.max_targets = d->max_targets;
+  a.noise = reinterpret_cast<const float2*>(noise);
+  a.Y = reinterpret_cast<float2*>(Y);
+  a.status = status;
+  a.M = M;
+  a.n_guard = d->n_guard;
+  a.fc_over_df = d->fc_over_df;
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+#define SIM_CALL(n)                                                                              \
+  {                                                                                              \
+    constexpr int TEAMS = radar::kBlock / ((n) / 16);                                            \
+    hipLaunchKernelGGL(radar::k_simulate<n>, dim3((M + TEAMS - 1) / TEAMS, n_frames), dim3(radar::kBlock), 0, s, a); \
+  }
+  RADAR_SIZE_SWITCH(N, SIM_CALL)
+#undef SIM_CALL
+  RADAR_HIP_CHECK(hipGetLastError());
   return RADAR_OK;
 }
 

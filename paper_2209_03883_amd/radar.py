@@ -25,7 +25,7 @@ RADAR_E_NOT_COPRIME = -5
 
 WIN_RECT, WIN_HANN, WIN_HAMMING = 0, 1, 2
 ZC_NONE, ZC_DIAG, ZC_DENSE = 0, 1, 2
-ST_ZERO_SYMBOL, ST_NONFINITE = 1, 2
+ST_ZERO_SYMBOL, ST_NONFINITE, ST_ISI = 1, 2, 4
 FLAG_REFINE, FLAG_BF16X3, FLAG_FP16X3, FLAG_THRESHOLD = 1, 2, 4, 8
 
 EXPORTED = (
@@ -37,6 +37,7 @@ EXPORTED = (
     "radar_batch_destroy",
     "radar_cnn_param_count", "radar_cnn_workspace_size", "radar_cnn_patches", "radar_cnn_forward",
     "radar_cnn_gradient", "radar_cnn_adam", "radar_cnn_train_step", "radar_tap_wiener_weights",
+    "radar_simulate_frames",
 )
 BATCH_GRAPH, BATCH_TUNE = 1, 2
 STAGES = ("taps", "doppler", "range", "peaks", "refine", "sft_slices", "sft_decode")
@@ -67,6 +68,13 @@ class Peak(ctypes.Structure):
 
 
 PEAK_WORDS = ctypes.sizeof(Peak) // 4  # 5 x 32-bit words
+
+
+class SimDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_sub", ctypes.c_int32), ("n_sym", ctypes.c_int32), ("n_guard", ctypes.c_int32),
+        ("max_targets", ctypes.c_int32), ("ld", ctypes.c_int64), ("fc_over_df", ctypes.c_double),
+    ]
 
 
 class FrameJob(ctypes.Structure):
@@ -126,6 +134,8 @@ def lib() -> ctypes.CDLL:
     L.radar_batch_destroy.restype = None
     L.radar_batch_destroy.argtypes = [vp]
     fp = ctypes.c_void_p
+    L.radar_simulate_frames.restype = ctypes.c_int
+    L.radar_simulate_frames.argtypes = [ctypes.POINTER(SimDesc), i32, vp, i64, vp, vp, vp, vp, vp, vp]
     L.radar_tap_wiener_weights.restype = ctypes.c_int
     L.radar_tap_wiener_weights.argtypes = [ctypes.POINTER(ctypes.c_double), i32, ctypes.c_double,
                                            ctypes.POINTER(ctypes.c_float)]
@@ -217,6 +227,36 @@ def _as_frames(x: torch.Tensor, cfg: Config, name: str) -> torch.Tensor:
 
 def _frame_stride(x: torch.Tensor) -> int:
     return int(x.stride(0)) if x.shape[0] > 1 else int(x.shape[1] * x.stride(1))
+
+
+def simulate_frames(A: torch.Tensor, targets: torch.Tensor, n_targets: torch.Tensor, *, n_guard: int,
+                    fc_over_df: float = 77e9 / 240e3, noise: torch.Tensor | None = None, stream=None):
+    """radar_simulate_frames: received frames (F, M, N) complex64 from the
+    time-domain model, and the per-frame status words.
+
+    A: (F, M, N) complex64 CUDA (contiguous rows); targets: (F, T, 4) float32
+    CUDA rows (rho, nu, b_re, b_im); n_targets: (F,) int32 CUDA."""
+    L = lib()
+    if A.dim() == 2:
+        A = A[None]
+    if not A.is_cuda or A.dtype != torch.complex64 or A.stride(2) != 1:
+        raise TypeError("A must be a complex64 CUDA tensor (F, M, N) with contiguous rows")
+    if targets.dtype != torch.float32 or targets.dim() != 3 or targets.shape[2] != 4 or not targets.is_contiguous():
+        raise TypeError("targets must be a contiguous float32 tensor (F, T, 4)")
+    if n_targets.dtype != torch.int32 or n_targets.numel() != A.shape[0]:
+        raise TypeError("n_targets must be int32 with one entry per frame")
+    F, M, N = A.shape
+    Y = torch.empty((F, M, N), dtype=torch.complex64, device=A.device)
+    status = torch.zeros(F, dtype=torch.int32, device=A.device)
+    if noise is not None and (noise.shape != Y.shape or noise.dtype != torch.complex64 or not noise.is_contiguous()):
+        raise TypeError("noise must be a contiguous complex64 tensor shaped like A")
+    if A.stride() != Y.stride():
+        A = A.contiguous()
+    d = SimDesc(N, M, int(n_guard), int(targets.shape[1]), int(A.stride(1)), float(fc_over_df))
+    _check(L.radar_simulate_frames(ctypes.byref(d), F, A.data_ptr(), int(A.stride(0)), targets.data_ptr(),
+                                   n_targets.data_ptr(), None if noise is None else noise.data_ptr(), Y.data_ptr(),
+                                   status.data_ptr(), _stream_ptr(stream)), "radar_simulate_frames")
+    return Y, status
 
 
 def tap_wiener_weights(tap_power, noise_var_tap: float) -> list:

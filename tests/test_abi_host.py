@@ -201,6 +201,16 @@ def test_tap_weights_validation():
     assert L.radar_fps_sft_workspace_size(ctypes.byref(d), ctypes.byref(s), 1) == 0
 
 
+@pytest.mark.parametrize("change", [dict(n_sub=100), dict(n_guard=-1), dict(n_guard=65), dict(max_targets=0),
+                                    dict(fc_over_df=0.0), dict(fc_over_df=float("inf")), dict(ld=32)])
+def test_simulate_validation(change):
+    L = radar.lib()
+    base = dict(n_sub=64, n_sym=16, n_guard=16, max_targets=4, ld=64, fc_over_df=320833.0)
+    d = radar.SimDesc(**{**base, **change})
+    rc = L.radar_simulate_frames(ctypes.byref(d), 1, 4096, 0, 4096, 4096, None, 4096, None, None)
+    assert rc in (radar.RADAR_E_ARG, radar.RADAR_E_UNSUPPORTED)
+
+
 def test_sft_default_settings():
     d = radar.sft_desc(8)
     assert (d.n_dirs, d.k, d.flags) == (8, 8, 0)
