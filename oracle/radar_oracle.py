@@ -618,3 +618,13 @@ def simulate_frame(A, targets, *, n_guard: int, fc_over_df: float, noise=None) -
     if noise is not None:
         Y = Y + np.asarray(noise, dtype=np.complex128)
     return Y
+
+
+def papr(A) -> np.ndarray:
+    """Peak-to-average power ratio of Eq. 25 per OFDM symbol, linear: the
+    transmitted samples x_n (n < N, the N-point IDFT of the symbol's
+    subcarriers; the cyclic prefix repeats samples and leaves it unchanged),
+    max |x_n|^2 / mean |x_n|^2.  A is symbol-major (M, N)."""
+    x = np.fft.ifft(np.asarray(A, dtype=np.complex128), axis=1)
+    p = x.real ** 2 + x.imag ** 2
+    return p.max(axis=1) / p.mean(axis=1)

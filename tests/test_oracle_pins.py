@@ -273,6 +273,24 @@ def test_time_domain_slow_targets_approach_eq11():
     assert errs[0] > errs[1] > errs[2] and errs[2] < 0.01
 
 
+# --------------------------------------------------------------- PAPR (Eq. 25)
+def test_papr_closed_forms():
+    n = 64
+    one = np.zeros((1, n), complex)
+    one[0, 5] = 2.0 - 1.0j
+    assert O.papr(one)[0] == pytest.approx(1.0, abs=1e-12)      # one subcarrier: constant envelope
+    assert O.papr(np.ones((1, n), complex))[0] == pytest.approx(n, rel=1e-12)  # all in phase: an impulse
+    # a brute-force IDFT for random symbols, and the bound PAPR <= N
+    rng = np.random.default_rng(23)
+    A = rng.standard_normal((3, n)) + 1j * rng.standard_normal((3, n))
+    k = np.arange(n)
+    for l in range(3):
+        x = np.array([np.sum(A[l] * np.exp(2j * np.pi * k * m / n)) for m in range(n)]) / n
+        p = np.abs(x) ** 2
+        assert O.papr(A)[l] == pytest.approx(p.max() / p.mean(), rel=1e-12)
+    assert np.all(O.papr(A) <= n + 1e-9)
+
+
 # ------------------------------------------------------- division (Eq. 16)
 def test_ls_estimate_recovers_generator_channel():
     spec = S.FrameSpec(n_sub=64, n_sym=16, qam=16, zc_root=5, n_targets=2, noise=False,
