@@ -425,6 +425,19 @@ int radar_simulate_frames(const radar_sim_desc *d, int32_t n_frames, const radar
                           const radar_cf32 *noise, radar_cf32 *Y, uint32_t *status, void *hip_stream);
 
 /* ------------------------------------------------------------------------
+ * radar_papr -- peak-to-average power ratio of Eq. 25 per OFDM symbol.
+ *
+ * papr[f*M + l] = max_n |x_n|^2 / mean_n |x_n|^2 (linear) with x the N-point
+ * IDFT of symbol l of frame f (the transmitted samples at the Nyquist rate;
+ * the cyclic prefix repeats samples and leaves the ratio unchanged), 0 for
+ * an all-zero symbol.  A: device, frame f at A + f*frame_stride, [M][ld], the
+ * symbols on the subcarriers after any precoding; papr: device [n_frames][M].
+ * N, M powers of two in [16, 4096]; ld >= N.  No workspace.
+ * ------------------------------------------------------------------------ */
+int radar_papr(int32_t n_sub, int32_t n_sym, int64_t ld, int32_t n_frames, const radar_cf32 *A,
+               int64_t frame_stride, float *papr, void *hip_stream);
+
+/* ------------------------------------------------------------------------
  * Stage timing -- a profiling aid, off by default.
  *
  * radar_timing_start(max_launches) creates HIP events for up to max_launches

@@ -624,7 +624,9 @@ def papr(A) -> np.ndarray:
     """Peak-to-average power ratio of Eq. 25 per OFDM symbol, linear: the
     transmitted samples x_n (n < N, the N-point IDFT of the symbol's
     subcarriers; the cyclic prefix repeats samples and leaves it unchanged),
-    max |x_n|^2 / mean |x_n|^2.  A is symbol-major (M, N)."""
+    max |x_n|^2 / mean |x_n|^2, and 0 for an all-zero symbol.  A is
+    symbol-major (M, N)."""
     x = np.fft.ifft(np.asarray(A, dtype=np.complex128), axis=1)
     p = x.real ** 2 + x.imag ** 2
-    return p.max(axis=1) / p.mean(axis=1)
+    mean = p.mean(axis=1)
+    return np.divide(p.max(axis=1), mean, out=np.zeros_like(mean), where=mean > 0)

@@ -105,4 +105,53 @@ __global__ void __launch_bounds__(kBlock) k_simulate(SimArgs a) {
   if (st && a.status) atomicOr(a.status + f, st);
 }
 
+// Peak-to-average power ratio of Eq. 25 for every OFDM symbol: the N-point
+// IDFT of the symbol's subcarriers (the prefix only repeats samples), then
+// max |x|^2 / mean |x|^2 over the team.  One team per symbol.
+template <int N>
+__global__ void __launch_bounds__(kBlock) k_papr(const float2* A, int64_t ld, int64_t frame_stride, int M,
+                                                 float* papr) {
+  constexpr int T = N / 16;
+  constexpr int TEAMS = kBlock / T;
+  __shared__ float2 lds_all[TEAMS * LdsSize<N>::value];
+  __shared__ float red[2][T > 64 ? TEAMS * (T / 64) : 1];
+  const int team = threadIdx.x / T;
+  const int t = threadIdx.x - team * T;
+  const int f = blockIdx.y;
+  const int l = blockIdx.x * TEAMS + team;
+  const bool active = l < M;
+  const float2* x = A + f * frame_stride + (int64_t)(active ? l : 0) * ld;
+  float2 v[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) v[e] = x[t + T * e];
+  team_fft<N, 16, true>(v, lds_all + team * LdsSize<N>::value, t);
+  float mx = 0.0f, sum = 0.0f;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const float p = cabs2(v[e]);
+    mx = fmaxf(mx, p);
+    sum += p;
+  }
+#pragma unroll
+  for (int m = (T < 64 ? T : 64) / 2; m > 0; m >>= 1) {
+    mx = fmaxf(mx, __shfl_xor(mx, m));
+    sum += __shfl_xor(sum, m);
+  }
+  if constexpr (T > 64) {
+    if ((t & 63) == 0) {
+      red[0][team * (T / 64) + (t >> 6)] = mx;
+      red[1][team * (T / 64) + (t >> 6)] = sum;
+    }
+    __syncthreads();
+    mx = 0.0f;
+    sum = 0.0f;
+#pragma unroll
+    for (int w = 0; w < T / 64; ++w) {
+      mx = fmaxf(mx, red[0][team * (T / 64) + w]);
+      sum += red[1][team * (T / 64) + w];
+    }
+  }
+  if (active && t == 0) papr[(int64_t)f * M + l] = sum > 0.0f ? mx * (float)N / sum : 0.0f;
+}
+
 }  // namespace radar

@@ -119,6 +119,19 @@ def draw_targets(rng: np.random.Generator, spec: FrameSpec):
     return np.array(rho), np.array(nu), b
 
 
+def transmit_symbols(A: np.ndarray, spec: FrameSpec) -> np.ndarray:
+    """The symbols the transmitter puts on the subcarriers: A, or A precoded
+    with the spec's Zadoff-Chu sequence (diagonal), or with the N x N matrix
+    Z[i, j] = zc(i N + j) of a length-N^2 sequence scaled by 1/sqrt(N) (dense)."""
+    n = A.shape[-1]
+    if spec.zc_root is None:
+        return A
+    if spec.zc_dense:
+        Z = tx_precoding_sequence(n * n, spec.zc_root, spec.zc_shift).reshape(n, n)
+        return A @ Z.T / np.sqrt(n)
+    return A * tx_precoding_sequence(n, spec.zc_root, spec.zc_shift)[None, :]
+
+
 def make_frame(spec: FrameSpec, config_id: int, frame_index: int) -> Frame:
     rng = rng_for(config_id, frame_index)
     n, m = spec.n_sub, spec.n_sym
@@ -129,15 +142,7 @@ def make_frame(spec: FrameSpec, config_id: int, frame_index: int) -> Frame:
     echo = np.zeros((m, n), dtype=np.complex128)
     for p in range(spec.n_targets):
         echo += b[p] * np.outer(np.exp(2j * np.pi * l * nu[p] / m), np.exp(-2j * np.pi * k * rho[p] / n))
-    if spec.zc_root is None:
-        tx = A
-    elif spec.zc_dense:
-        # each symbol multiplied by the N x N matrix Z[i, j] = zc(i N + j) of a
-        # length-N^2 sequence, scaled by 1/sqrt(N) to keep the symbol energy
-        Z = tx_precoding_sequence(n * n, spec.zc_root, spec.zc_shift).reshape(n, n)
-        tx = A @ Z.T / np.sqrt(n)
-    else:
-        tx = A * tx_precoding_sequence(n, spec.zc_root, spec.zc_shift)[None, :]
+    tx = transmit_symbols(A, spec)
     Y = tx * echo
     if spec.noise:
         sigma2 = 10.0 ** (-spec.snr_db / 10.0)

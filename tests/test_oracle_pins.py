@@ -280,6 +280,7 @@ def test_papr_closed_forms():
     one[0, 5] = 2.0 - 1.0j
     assert O.papr(one)[0] == pytest.approx(1.0, abs=1e-12)      # one subcarrier: constant envelope
     assert O.papr(np.ones((1, n), complex))[0] == pytest.approx(n, rel=1e-12)  # all in phase: an impulse
+    assert O.papr(np.zeros((1, n), complex))[0] == 0.0                         # nothing sent
     # a brute-force IDFT for random symbols, and the bound PAPR <= N
     rng = np.random.default_rng(23)
     A = rng.standard_normal((3, n)) + 1j * rng.standard_normal((3, n))
