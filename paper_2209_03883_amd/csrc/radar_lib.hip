@@ -203,12 +203,16 @@ void launch_k1p_n(const radar::K1Args& a, int M, int F, hipStream_t s) {
 }
 template <int N>
 void launch_dense_n(const radar::DenseArgs& a, hipStream_t s) {
-  // persistent: as many work-groups as fit on the device at once
-  static int per_cu = 0;
-  if (per_cu == 0 && (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, radar::k_dense_ls<N>,
-                                                                     radar::kDenseThreads, 0) != hipSuccess ||
-                      per_cu < 1))
-    per_cu = 1;
+  // persistent: as many work-groups as fit on the device at once (a static
+  // initialised once, thread-safely, on the first call for this size)
+  static const int per_cu = [] {
+    int v = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, radar::k_dense_ls<N>, radar::kDenseThreads, 0) !=
+            hipSuccess ||
+        v < 1)
+      v = 1;
+    return v;
+  }();
   int grid = (g_num_cus > 0 ? g_num_cus : 256) * per_cu;
   if (grid > a.total) grid = a.total;
   hipLaunchKernelGGL(radar::k_dense_ls<N>, dim3(grid), dim3(radar::kDenseThreads), 0, s, a);
