@@ -630,3 +630,20 @@ def papr(A) -> np.ndarray:
     p = x.real ** 2 + x.imag ** 2
     mean = p.mean(axis=1)
     return np.divide(p.max(axis=1), mean, out=np.zeros_like(mean), where=mean > 0)
+
+
+def hpa(A, q_db: float = 2.0) -> np.ndarray:
+    """The high power amplifier of Eq. 26 applied to each symbol's transmitted
+    samples, returned as the subcarrier symbols of the amplified waveform.
+
+    Reading: an amplitude-only (AM/AM) soft limiter, the phase unchanged,
+        |x'| = |x| / sqrt(1 + (|x| / (xbar 10^{q/10}))^2),
+    xbar the mean of |x_n| over the symbol's N samples (the N-point IDFT; the
+    prefix repeats samples), q the state level in dB (2 in Sec. III-B).  An
+    all-zero symbol stays zero."""
+    A = np.asarray(A, dtype=np.complex128)
+    x = np.fft.ifft(A, axis=1)
+    amp = np.abs(x)
+    sat = amp.mean(axis=1, keepdims=True) * 10.0 ** (q_db / 10.0)
+    ratio = np.divide(amp, sat, out=np.zeros_like(amp), where=sat > 0)
+    return np.fft.fft(x / np.sqrt(1.0 + ratio ** 2), axis=1)

@@ -206,6 +206,36 @@ def test_lmmse_estimators_mse_ordering():
     assert err["lmmse_ls"] < err["ls"]
 
 
+# ---------------------------------------------------------------- HPA (Eq. 26)
+def test_hpa_closed_forms():
+    n = 64
+    rng = np.random.default_rng(24)
+    # one subcarrier: a constant envelope |x| = xbar, so every sample is scaled
+    # by 1 / sqrt(1 + 10^{-q/5})
+    one = np.zeros((2, n), complex)
+    one[0, 9] = 1.5 - 0.5j
+    for q in (0.0, 2.0, 6.0):
+        np.testing.assert_allclose(O.hpa(one, q)[0], one[0] / np.sqrt(1.0 + 10.0 ** (-q / 5.0)), atol=1e-13)
+    assert np.all(O.hpa(one, 2.0)[1] == 0)  # nothing sent, nothing amplified
+    # far below saturation: linear
+    A = rng.standard_normal((3, n)) + 1j * rng.standard_normal((3, n))
+    np.testing.assert_allclose(O.hpa(A, 200.0), A, atol=1e-9)
+    # the output envelope stays below the saturation level, the phase is kept
+    x = np.fft.ifft(A, axis=1)
+    y = np.fft.ifft(O.hpa(A, 2.0), axis=1)
+    sat = np.abs(x).mean(axis=1, keepdims=True) * 10 ** 0.2
+    assert np.all(np.abs(y) < sat)
+    np.testing.assert_allclose(np.angle(y * np.conj(x)), 0.0, atol=1e-9)
+    # brute force, sample by sample
+    k = np.arange(n)
+    for l in range(3):
+        xs = np.array([np.sum(A[l] * np.exp(2j * np.pi * k * m / n)) / n for m in range(n)])
+        s = np.mean(np.abs(xs)) * 10 ** 0.2
+        ys = xs / np.sqrt(1 + (np.abs(xs) / s) ** 2)
+        ref = np.array([np.sum(ys * np.exp(-2j * np.pi * np.arange(n) * kk / n)) for kk in range(n)])
+        np.testing.assert_allclose(O.hpa(A, 2.0)[l], ref, atol=1e-10)
+
+
 # ----------------------------------- time-domain frame model (Eq. 1-2, 7-10)
 def _qpsk(rng, m, n):
     return (rng.choice([-1.0, 1.0], (m, n)) + 1j * rng.choice([-1.0, 1.0], (m, n))) / np.sqrt(2.0)
