@@ -438,6 +438,22 @@ int radar_papr(int32_t n_sub, int32_t n_sym, int64_t ld, int32_t n_frames, const
                int64_t frame_stride, float *papr, void *hip_stream);
 
 /* ------------------------------------------------------------------------
+ * radar_hpa -- the high power amplifier of Eq. 26 on every symbol's
+ * transmitted samples, returned as subcarrier symbols.
+ *
+ * Per symbol: x = IDFT_N(A) (the samples; the prefix repeats them), then the
+ * amplitude-only soft limiter |x'| = |x| / sqrt(1 + (|x| / (xbar 10^{q/10}))^2)
+ * with xbar the mean of |x_n| over the symbol, the phase kept, and
+ * out = DFT_N(x').  Feed out to radar_simulate_frames as the transmitted
+ * symbols while the radar still divides by A.  An all-zero symbol stays zero.
+ * A, out: device, frame f at + f*frame_stride, [M][ld]; out may equal A.
+ * q_db: the state level (2 in Sec. III-B), finite.  N, M powers of two in
+ * [16, 4096]; ld >= N.  No workspace.
+ * ------------------------------------------------------------------------ */
+int radar_hpa(int32_t n_sub, int32_t n_sym, int64_t ld, int32_t n_frames, const radar_cf32 *A,
+              int64_t frame_stride, double q_db, radar_cf32 *out, void *hip_stream);
+
+/* ------------------------------------------------------------------------
  * Stage timing -- a profiling aid, off by default.
  *
  * radar_timing_start(max_launches) creates HIP events for up to max_launches

@@ -18,6 +18,7 @@
 #pragma once
 
 #include "fft.hpp"
+#include "k_frame.hpp"  // team_sum
 
 namespace radar {
 
@@ -152,6 +153,50 @@ __global__ void __launch_bounds__(kBlock) k_papr(const float2* A, int64_t ld, in
     }
   }
   if (active && t == 0) papr[(int64_t)f * M + l] = sum > 0.0f ? mx * (float)N / sum : 0.0f;
+}
+
+// The high power amplifier of Eq. 26 on every symbol's transmitted samples:
+// x = IDFT_N(a), |x'| = |x| / sqrt(1 + (|x| / s)^2) with s = xbar 10^{q/10}
+// (xbar the mean of |x| over the symbol), the phase kept, then a' = DFT_N(x').
+// One team per symbol; in place allowed (out == A).
+template <int N>
+__global__ void __launch_bounds__(kBlock) k_hpa(const float2* A, float2* out, int64_t ld, int64_t frame_stride,
+                                                int M, float sat_factor) {
+  constexpr int T = N / 16;
+  constexpr int TEAMS = kBlock / T;
+  __shared__ float2 lds_all[TEAMS * LdsSize<N>::value];
+  __shared__ float red[T > 64 ? TEAMS * (T / 64) : 1];
+  const int team = threadIdx.x / T;
+  const int t = threadIdx.x - team * T;
+  const int f = blockIdx.y;
+  const int l = blockIdx.x * TEAMS + team;
+  const bool active = l < M;
+  float2* lds = lds_all + team * LdsSize<N>::value;
+  const int64_t off = f * frame_stride + (int64_t)(active ? l : 0) * ld;
+  float2 v[16];
+  float amp[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) v[e] = A[off + t + T * e];
+  team_fft<N, 16, true>(v, lds, t);  // N x (the samples)
+  float sum = 0.0f;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    v[e] = cscale(v[e], 1.0f / N);
+    amp[e] = sqrtf(cabs2(v[e]));
+    sum += amp[e];
+  }
+  sum = team_sum<T>(sum, red, team, t);
+  const float sat = sum * (1.0f / N) * sat_factor;
+  const float inv_sat = sat > 0.0f ? 1.0f / sat : 0.0f;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const float r = amp[e] * inv_sat;
+    v[e] = cscale(v[e], 1.0f / sqrtf(1.0f + r * r));
+  }
+  team_fft<N, 16, false>(v, lds, t);
+  if (!active) return;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) out[off + t + T * e] = v[e];
 }
 
 }  // namespace radar

@@ -947,6 +947,31 @@ int radar_papr(int32_t n_sub, int32_t n_sym, int64_t ld, int32_t n_frames, const
   return RADAR_OK;
 }
 
+int radar_hpa(int32_t n_sub, int32_t n_sym, int64_t ld, int32_t n_frames, const radar_cf32* A, int64_t frame_stride,
+              double q_db, radar_cf32* out, void* hip_stream) {
+  const int N = n_sub, M = n_sym;
+  if (!A || !out || N <= 0 || M <= 0 || ld < N || n_frames < 1 || n_frames > 65535 || !std::isfinite(q_db))
+    return RADAR_E_ARG;
+  if (!is_pow2(N) || !is_pow2(M) || N < 16 || N > 4096 || M < 16 || M > 4096) return RADAR_E_UNSUPPORTED;
+  if (n_frames > 1 && frame_stride < (int64_t)(M - 1) * ld + N) return RADAR_E_ARG;
+  int rc = ensure_init();
+  if (rc != RADAR_OK) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  const float2* a = reinterpret_cast<const float2*>(A);
+  float2* o = reinterpret_cast<float2*>(out);
+  const float sat_factor = (float)std::pow(10.0, q_db / 10.0);
+#define HPA_CALL(n)                                                                                           \
+  {                                                                                                           \
+    constexpr int TEAMS = radar::kBlock / ((n) / 16);                                                         \
+    hipLaunchKernelGGL(radar::k_hpa<n>, dim3((M + TEAMS - 1) / TEAMS, n_frames), dim3(radar::kBlock), 0, s, a, \
+                       o, ld, frame_stride, M, sat_factor);                                                   \
+  }
+  RADAR_SIZE_SWITCH(N, HPA_CALL)
+#undef HPA_CALL
+  RADAR_HIP_CHECK(hipGetLastError());
+  return RADAR_OK;
+}
+
 int radar_tap_wiener_weights(const double* tap_power, int32_t n, double noise_var_tap, float* weights) {
   if (!tap_power || !weights || n < 1 || !(noise_var_tap >= 0.0) || !std::isfinite(noise_var_tap))
     return RADAR_E_ARG;

@@ -37,7 +37,7 @@ EXPORTED = (
     "radar_batch_destroy",
     "radar_cnn_param_count", "radar_cnn_workspace_size", "radar_cnn_patches", "radar_cnn_forward",
     "radar_cnn_gradient", "radar_cnn_adam", "radar_cnn_train_step", "radar_tap_wiener_weights",
-    "radar_simulate_frames", "radar_papr",
+    "radar_simulate_frames", "radar_papr", "radar_hpa",
 )
 BATCH_GRAPH, BATCH_TUNE = 1, 2
 STAGES = ("taps", "doppler", "range", "peaks", "refine", "sft_slices", "sft_decode")
@@ -134,6 +134,8 @@ def lib() -> ctypes.CDLL:
     L.radar_batch_destroy.restype = None
     L.radar_batch_destroy.argtypes = [vp]
     fp = ctypes.c_void_p
+    L.radar_hpa.restype = ctypes.c_int
+    L.radar_hpa.argtypes = [i32, i32, i64, i32, vp, i64, ctypes.c_double, vp, vp]
     L.radar_papr.restype = ctypes.c_int
     L.radar_papr.argtypes = [i32, i32, i64, i32, vp, i64, vp, vp]
     L.radar_simulate_frames.restype = ctypes.c_int
@@ -259,6 +261,20 @@ def simulate_frames(A: torch.Tensor, targets: torch.Tensor, n_targets: torch.Ten
                                    n_targets.data_ptr(), None if noise is None else noise.data_ptr(), Y.data_ptr(),
                                    status.data_ptr(), _stream_ptr(stream)), "radar_simulate_frames")
     return Y, status
+
+
+def hpa(A: torch.Tensor, q_db: float = 2.0, stream=None) -> torch.Tensor:
+    """radar_hpa: the Eq. 26 amplifier on (F, M, N) complex64 CUDA symbols; a new tensor."""
+    L = lib()
+    if A.dim() == 2:
+        A = A[None]
+    if not A.is_cuda or A.dtype != torch.complex64 or not A.is_contiguous():
+        raise TypeError("A must be a contiguous complex64 CUDA tensor (F, M, N)")
+    F, M, N = A.shape
+    out = torch.empty_like(A)
+    _check(L.radar_hpa(N, M, int(A.stride(1)), F, A.data_ptr(), int(A.stride(0)), float(q_db), out.data_ptr(),
+                       _stream_ptr(stream)), "radar_hpa")
+    return out
 
 
 def papr(A: torch.Tensor, stream=None) -> torch.Tensor:
