@@ -263,6 +263,12 @@ struct K2Tile {
   static constexpr int EXCH = LdsSize<M>::value;
   static constexpr int LD = TW + 1;  // padded tile row (limits bank conflicts)
   static constexpr int SH = TW * EXCH > M * LD ? TW * EXCH : M * LD;
+  // the FFT plan's twiddles in LDS where they fit beside the tile (else they
+  // are read from the global table)
+  static constexpr int PLAN = PlanTable<M, 16, 1>::size();
+  static constexpr bool kLdsTw = (SH + PLAN) * 8 <= 150 * 1024;
+  static constexpr int TWN = kLdsTw && PLAN > 0 ? PLAN : 1;
+  using Plan = PlanLayout<M, 0, 1>;
 };
 
 template <int M, int TW, Prec PR = Prec::FP32>
@@ -272,6 +278,8 @@ __global__ void __launch_bounds__((K2Tile<M, TW>::BLOCK)) k2_doppler_tiled(K2Arg
   df.init();
   constexpr int T = C::T, BLOCK = C::BLOCK, LD = C::LD;
   __shared__ float2 sh[C::SH];
+  __shared__ float2 twtab[C::TWN];
+  if constexpr (C::kLdsTw) copy_plan_twiddles<M, 16, 1>(twtab, threadIdx.x, BLOCK);  // ordered by the tile's barrier
   const int team = threadIdx.x / T;
   const int t = threadIdx.x - team * T;
   const int b = blockIdx.y;
@@ -279,11 +287,37 @@ __global__ void __launch_bounds__((K2Tile<M, TW>::BLOCK)) k2_doppler_tiled(K2Arg
   const int n0 = blockIdx.x * TW;
   const int ntap = min(TW, a.n_cp - n0);
 
-  // tile of taps [l][n0 .. n0+TW)
+  // tile of taps [l][n0 .. n0+TW).  Up to M = 1024 each thread issues its
+  // loads eight at a time before the LDS stores: a load per loop iteration
+  // with a wait before each store serialises the memory latency.  The ragged
+  // last tile clamps its column and stores zeros there, so every load is
+  // unconditional and in bounds.  The longest transforms keep the plain loop
+  // (their FFT leaves no registers for the batch).
+  static_assert(M * TW == 16 * BLOCK, "16 tile elements per thread");
+  constexpr bool kBatched = M <= 1024;
   const float2* in = a.taps + (int64_t)f * M * a.n_cp + n0;
-  for (int i = threadIdx.x; i < M * TW; i += BLOCK) {
-    const int l = i / TW, c = i - l * TW;
-    sh[l * LD + c] = c < ntap ? in[(int64_t)l * a.n_cp + c] : make_float2(0.0f, 0.0f);
+  if constexpr (kBatched) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      float2 tv[8];
+#pragma unroll
+      for (int it = 0; it < 8; ++it) {
+        const int i = threadIdx.x + (8 * h + it) * BLOCK;
+        const int l = i / TW, c = i - l * TW;
+        tv[it] = in[(int64_t)l * a.n_cp + (c < ntap ? c : ntap - 1)];
+      }
+#pragma unroll
+      for (int it = 0; it < 8; ++it) {
+        const int i = threadIdx.x + (8 * h + it) * BLOCK;
+        const int l = i / TW, c = i - l * TW;
+        sh[l * LD + c] = c < ntap ? tv[it] : make_float2(0.0f, 0.0f);
+      }
+    }
+  } else {
+    for (int i = threadIdx.x; i < M * TW; i += BLOCK) {
+      const int l = i / TW, c = i - l * TW;
+      sh[l * LD + c] = c < ntap ? in[(int64_t)l * a.n_cp + c] : make_float2(0.0f, 0.0f);
+    }
   }
   __syncthreads();
   float2 v[16];
@@ -298,7 +332,10 @@ __global__ void __launch_bounds__((K2Tile<M, TW>::BLOCK)) k2_doppler_tiled(K2Arg
     }
   }
   __syncthreads();  // the tile is reused as exchange space
-  team_fft<M, 16, false>(v, sh + team * C::EXCH, t, true, df);
+  if constexpr (C::kLdsTw)
+    fft_stages<M, 16, 1, false>(v, sh + team * C::EXCH, t, true, TwLds<typename C::Plan>{twtab}, df);
+  else
+    team_fft<M, 16, false>(v, sh + team * C::EXCH, t, true, df);
   __syncthreads();  // every team is done with its exchange region
 #pragma unroll
   for (int e = 0; e < 16; ++e) sh[(t + T * e) * LD + team] = v[e];
