@@ -139,9 +139,29 @@ __global__ void __launch_bounds__(kDenseThreads) k_dense_ls(DenseArgs a) {
     const int l = sym - f * a.M;
     const float2* y = (a.refs ? a.refs[f].Y : a.Y + f * a.frame_stride) + (int64_t)l * a.ld;
     const float2* x = (a.refs ? a.refs[f].A : a.A + f * a.frame_stride) + (int64_t)l * a.ld;
+    // up to four elements per thread (N <= 1024), every load of the symbol is
+    // issued first (a load per loop iteration with a wait before its use
+    // would serialise the memory latency); longer symbols keep the loads in
+    // the loops, as their transform leaves no registers to hold them
+    constexpr int NT = (N + T - 1) / T;
+    constexpr bool kPre = NT <= 4;
+    float2 xa[kPre ? NT : 1], ya[kPre ? NT : 1];
+    if constexpr (kPre) {
+#pragma unroll
+      for (int it = 0; it < NT; ++it) {
+        const int j = tid + it * T;
+        xa[it] = j < N ? x[j] : make_float2(0.0f, 0.0f);
+        ya[it] = j < N ? y[j] : make_float2(0.0f, 0.0f);
+      }
+    }
     __syncthreads();  // the twiddles are written, the previous symbol's reads are done
-    for (int j = tid; j < N; j += T) {
-      const float2 av = x[j];
+#pragma unroll
+    for (int it = 0; it < NT; ++it) {
+      const int j = tid + it * T;
+      if (j >= N) break;
+      float2 av;
+      if constexpr (kPre) av = xa[it];
+      else av = x[j];
       const uint32_t uj = (uint32_t)j;
       const uint32_t m = (a.zc_root * (uj * uj + 2u * a.zc_shift * uj)) & kPhaseMask;
       double cs, sn;
@@ -153,7 +173,10 @@ __global__ void __launch_bounds__(kDenseThreads) k_dense_ls(DenseArgs a) {
     double isum = 0.0;
     uint32_t st = 0;
     float2* h = a.H + (int64_t)sym * N;
-    for (int i = tid; i < N; i += T) {
+#pragma unroll
+    for (int it = 0; it < NT; ++it) {
+      const int i = tid + it * T;
+      if (i >= N) break;
       const uint32_t ui = (uint32_t)i;
       const double2 xv = s_d[(a.zc_root * ui) & (uint32_t)(N - 1)];
       // D1(i) = exp(+i pi r i^2) exp(+2 pi i rqi/N) = (-1)^i W^{rqi} for odd r
@@ -164,7 +187,9 @@ __global__ void __launch_bounds__(kDenseThreads) k_dense_ls(DenseArgs a) {
       // relative rounding (not the transform's absolute error) is what counts,
       // so the division runs in FP32
       const float2 ap = make_float2((float)(xr * w.x - xi * w.y), (float)(xr * w.y + xi * w.x));
-      const float2 yv = y[i];
+      float2 yv;
+      if constexpr (kPre) yv = ya[it];
+      else yv = y[i];
       const float den = ap.x * ap.x + ap.y * ap.y;
       st |= den == 0.0f ? 1u : 0u;
       const float inv = den == 0.0f ? 0.0f : __builtin_amdgcn_rcpf(den);
