@@ -170,16 +170,39 @@ __global__ void __launch_bounds__(256) k_peak_rows_listed(const float* P, int64_
     const RADAR_GLOBAL float* rm = base + (int64_t)((row - 1) & (m_pad - 1)) * n_pad;
     const RADAR_GLOBAL float* r0 = base + (int64_t)row * n_pad;
     const RADAR_GLOBAL float* rp = base + (int64_t)((row + 1) & (m_pad - 1)) * n_pad;
-    for (int r = threadIdx.x; r < n_pad; r += blockDim.x) {
-      const float v = r0[r];
-      bool pk = v >= th;
-      if (pk) {
-        const int rl = (r - 1) & (n_pad - 1);
-        const int rr = (r + 1) & (n_pad - 1);
-        pk = v >= r0[rl] && v >= r0[rr] && v >= rm[rl] && v >= rm[r] && v >= rm[rr] && v >= rp[rl] &&
-             v >= rp[r] && v >= rp[rr];
+    // eight columns per thread at a time, all nine values of each 3 x 3
+    // neighbourhood loaded before any test (unconditional loads, columns
+    // clamped in bounds; the rows are L2-resident), so the loads overlap
+    // instead of waiting one by one
+    for (int base = threadIdx.x; base < n_pad; base += 8 * (int)blockDim.x) {
+      float nb[8][9];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int r = base + u * (int)blockDim.x;
+        const int rc = r < n_pad ? r : 0;
+        const int rl = (rc - 1) & (n_pad - 1);
+        const int rr = (rc + 1) & (n_pad - 1);
+        nb[u][0] = r0[rc];
+        nb[u][1] = r0[rl];
+        nb[u][2] = r0[rr];
+        nb[u][3] = rm[rl];
+        nb[u][4] = rm[rc];
+        nb[u][5] = rm[rr];
+        nb[u][6] = rp[rl];
+        nb[u][7] = rp[rc];
+        nb[u][8] = rp[rr];
       }
-      s_ord[r] = pk ? ord_bits(v) : 0u;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int r = base + u * (int)blockDim.x;
+        if (r < n_pad) {
+          const float v = nb[u][0];
+          bool pk = v >= th;
+#pragma unroll
+          for (int q = 1; q < 9; ++q) pk = pk && v >= nb[u][q];
+          s_ord[r] = pk ? ord_bits(v) : 0u;
+        }
+      }
     }
     uint64_t* out = cand + ((int64_t)f * m_pad + j) * k;
     const uint32_t flat0 = (uint32_t)row * (uint32_t)n_pad;
