@@ -88,19 +88,32 @@ __global__ void __launch_bounds__(256) k_row_max(const float* P, int64_t p_strid
   if (threadIdx.x == 0) rowmax[(int64_t)f * m_pad + row] = mx;
 }
 
-// Step 2 and the row list of step 3 (grid F, 256 threads, dynamic LDS m_pad
-// words).  Profile peaks are marked in LDS with strided (coalesced) row
+// Step 2 and the row list of step 3 (grid F, 256 threads, dynamic LDS 2 m_pad
+// words).  The row maxima are copied into LDS first, eight loads per thread
+// in flight at a time; profile peaks are marked in LDS with strided row
 // ownership; the k-th largest comes from k rounds of work-group maxima; the
 // row list is written in ascending order from contiguous row chunks.
 __global__ void __launch_bounds__(256) k_peak_threshold(const float* rowmax, int m_pad, int k, float* tau_out,
                                                         int32_t* list, int32_t* cnt_out) {
-  extern __shared__ uint32_t s_prof[];  // ord bits of profile peaks, 0 elsewhere
+  extern __shared__ uint32_t s_prof[];  // ord bits of profile peaks, 0 elsewhere; then the row maxima
   __shared__ uint64_t red[4];
   __shared__ int s_cnt[4];
   const int f = blockIdx.x;
   const int tid = threadIdx.x;
   const int mask = m_pad - 1;
-  const float* m = rowmax + (int64_t)f * m_pad;
+  float* m = reinterpret_cast<float*>(s_prof + m_pad);
+  {
+    const float* g = rowmax + (int64_t)f * m_pad;
+    for (int base = tid; base < m_pad; base += 8 * 256) {
+      float tv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) tv[u] = g[base + u * 256 < m_pad ? base + u * 256 : 0];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (base + u * 256 < m_pad) m[base + u * 256] = tv[u];
+    }
+  }
+  __syncthreads();
   for (int i = tid; i < m_pad; i += 256) {
     const float v = m[i];
     s_prof[i] = (v >= m[(i - 1) & mask] && v >= m[(i + 1) & mask]) ? ord_bits(v) : 0u;

@@ -427,7 +427,7 @@ int enqueue_peaks(const float* P, int64_t p_stride, int m_pad, int n_pad, int F,
   int32_t* list = reinterpret_cast<int32_t*>(ws + w.list);
   uint64_t* cand = reinterpret_cast<uint64_t*>(ws + w.cand);
   const int slot = timer_open(RADAR_STAGE_PEAKS, s);
-  hipLaunchKernelGGL(radar::k_peak_threshold, dim3(F), dim3(256), m_pad * sizeof(uint32_t), s, rowmax, m_pad, k, tau,
+  hipLaunchKernelGGL(radar::k_peak_threshold, dim3(F), dim3(256), 2 * m_pad * sizeof(uint32_t), s, rowmax, m_pad, k, tau,
                      list, cnt);
   RADAR_HIP_CHECK(hipGetLastError());
   const int groups = m_pad < 32 ? m_pad : 32;
@@ -882,6 +882,11 @@ int radar_init(void) {
       hipMemcpyToSymbol(HIP_SYMBOL(g_root64_lo), r_lo.data(), r_lo.size() * sizeof(double2), 0,
                         hipMemcpyHostToDevice) != hipSuccess)
     return RADAR_E_HIP;
+  // the peak threshold kernel holds two words per row of the largest M' in LDS
+  if (hipFuncSetAttribute(reinterpret_cast<const void*>(radar::k_peak_threshold),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, 2 * 16384 * (int)sizeof(uint32_t)) !=
+      hipSuccess)
+    return RADAR_E_HIP;
   g_init_done[dev] = true;
   return RADAR_OK;
 }
@@ -1058,6 +1063,8 @@ int radar_detect_topk(const float* P, int32_t m_pad, int32_t n_pad, int32_t n_fr
   if (n_frames < 1 || n_frames > 65535 || k < 1 || k > 64) return RADAR_E_ARG;
   if (n_frames > 1 && p_frame_stride < (int64_t)m_pad * n_pad) return RADAR_E_ARG;
   if (ws_bytes < radar_detect_workspace_size(m_pad, n_pad, n_frames, k)) return RADAR_E_WORKSPACE;
+  const int rc = ensure_init();
+  if (rc != RADAR_OK) return rc;
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
   hipLaunchKernelGGL(radar::k0_clear, dim3((n_frames + 255) / 256), dim3(256), 0, s, nullptr, n_peaks, n_frames,
                      nullptr);

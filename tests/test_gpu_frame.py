@@ -221,6 +221,26 @@ def test_detect_topk_random_bumps(seed):
         assert [(s, r, np.float32(v)) for s, r, v in want] == [(s, r, np.float32(p)) for s, r, p, _, _ in got[f]]
 
 
+@pytest.mark.parametrize("m_pad,n_pad", [(16384, 32), (32, 16384), (8192, 64)])
+def test_detect_topk_longest_axes(m_pad, n_pad):
+    """The largest M' and N' the peak search accepts (the row-maxima profile
+    and the row scan at their biggest LDS footprints)."""
+    rng = np.random.default_rng(m_pad + n_pad)
+    F = 2
+    Pn = (rng.random((F, m_pad, n_pad)) * 1e-3).astype(np.float32)
+    for f in range(F):
+        for _ in range(20):
+            Pn[f, rng.integers(0, m_pad), rng.integers(0, n_pad)] += np.float32(10 ** rng.uniform(-1, 2))
+    k = 16
+    say(f"detect_topk {m_pad} x {n_pad}")
+    peaks, n_peaks = radar.detect_topk(torch.from_numpy(Pn).cuda(), k)
+    torch.cuda.synchronize()
+    got = radar.unpack_peaks(peaks, n_peaks.cpu())
+    for f in range(F):
+        want = oracle_ranked(O, Pn[f].astype(np.float64), k)
+        assert [(s, r, np.float32(v)) for s, r, v in want] == [(s, r, np.float32(p)) for s, r, p, _, _ in got[f]]
+
+
 def test_detect_topk_fewer_peaks_than_k():
     P = np.zeros((1, 16, 16), np.float32)
     i, j = np.meshgrid(np.arange(16), np.arange(16), indexing="ij")
