@@ -639,9 +639,15 @@ __global__ void __launch_bounds__(K3p<N>::BLOCK) k3_range_power_x4p(K3Args a, in
     const float2* in = a.U + (int64_t)grow * a.n_cp;
     // the team lane, opaque to the optimiser, so that the per-element LDS
     // addresses are formed again for every row rather than held in registers
-    // (an empty asm statement emits no instruction)
+    // (an empty asm statement emits no instruction): what lets the one-store
+    // order fit; the other forms keep the addresses, which costs them no
+    // spill.  The mask restores the known range t < T, which resolves the
+    // phase-0 filter's bounds tests at compile time.
     int t = t0;
-    asm volatile("" : "+v"(t));
+    if constexpr (kOneStore) {
+      asm volatile("" : "+v"(t));
+      t &= T - 1;
+    }
     {
       float2 uv[Q / T];
 #pragma unroll
