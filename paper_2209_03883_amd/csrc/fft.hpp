@@ -220,8 +220,18 @@ __device__ __forceinline__ void fft_stages_tw(float2 (&v)[E], float2* lds, int t
           for (int m = 0; m < R; ++m) v[b + m * NB] = x[m];
         } else if (active) {
           const int base = (j - k) * R + k;
+          if constexpr (NS % 16 == 0 || NS * R <= 16) {
+            // base + m NS never crosses a 16-entry group boundary that
+            // pad(base) has not already counted (NS R <= 16), or crosses
+            // exactly m NS / 16 of them (NS a multiple of 16): the padded
+            // index is pad(base) plus a constant per m
+            const int pb = lds_pad(base);
 #pragma unroll
-          for (int m = 0; m < R; ++m) lds[lds_pad(base + m * NS)] = x[m];
+            for (int m = 0; m < R; ++m) lds[pb + m * NS + (NS % 16 == 0 ? m * NS / 16 : 0)] = x[m];
+          } else {
+#pragma unroll
+            for (int m = 0; m < R; ++m) lds[lds_pad(base + m * NS)] = x[m];
+          }
         }
       }
     }
@@ -230,8 +240,15 @@ __device__ __forceinline__ void fft_stages_tw(float2 (&v)[E], float2* lds, int t
       load_stage_tw<L, E, NS * R>(next, t, active, ts);
       team_sync<T>();
       if (active) {
+        if constexpr (T % 16 == 0) {
+          // t < T and T e a multiple of 16: pad(t + T e) = pad(t) + (T + T/16) e
+          const int pt = lds_pad(t);
 #pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = lds[lds_pad(t + T * e)];
+          for (int e = 0; e < E; ++e) v[e] = lds[pt + (T + T / 16) * e];
+        } else {
+#pragma unroll
+          for (int e = 0; e < E; ++e) v[e] = lds[lds_pad(t + T * e)];
+        }
       }
       if constexpr (T > 64) {
         __syncthreads();

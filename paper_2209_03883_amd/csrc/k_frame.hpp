@@ -558,14 +558,15 @@ __global__ void __launch_bounds__(K3x4<N>::BLOCK) k3_range_power_x4(K3Args a) {
 //   forward  DFT_N of u (N_cp <= N/4 taps): the first radix-4 Stockham stage
 //            of a zero-padded input only copies, y[i] = u[i >> 2], so the
 //            transform starts at span 4 straight from the taps.
-//   phases   b = 2, 3, 1: IFFT_N(w_k X_k e^{+2 pi i k b/(4N)});
+//   phases   b = 1, 2, 3: IFFT_N(w_k X_k e^{+2 pi i k b/(4N)});
 //            b = 0: the 3-tap filter N (a0 u[r1] - a1/2 (u[r1-1] + u[r1+1])).
-//   output   the four |G|^2 values of each r1 leave as two float2 pairs
-//            (holding all four phases in registers would spill).
+//   output   the four |G|^2 values of each r1 leave in one 16-byte store
+//            where two phases can be held in registers (FP32, N >= 512),
+//            else as two 8-byte pairs.
 // Every twiddle a row needs is the same for all rows, so each work-group
-// copies the stage blocks of its two FFT plans, the phase twiddles
-// W_{4N}^{k b} (b = 1..3) and the window cosines into LDS once, and its waves
-// then loop over rows independently: twiddle reads are LDS reads, not
+// copies the stage blocks of its two FFT plans and the phase twiddles
+// W_{4N}^{k b} (b = 1..3, each times the window w_k) into LDS once, and its
+// waves then loop over rows independently: twiddle reads are LDS reads, not
 // vector-memory instructions.
 // ------------------------------------------------------------------------
 template <int N>
@@ -576,9 +577,8 @@ struct K3p {
   static constexpr int BLOCK = 64 * WAVES;
   static constexpr int FWD = 0;                         // forward plan (from span 4)
   static constexpr int INV = PlanTable<N, 16, 4>::size();  // inverse plan (from span 1)
-  static constexpr int PH = INV + PlanTable<N, 16, 1>::size();  // W_{4N}^{k b}, b = 1..3
-  static constexpr int WIN = PH + 3 * N;                // N window cosines (as floats)
-  static constexpr int TAB = WIN + N / 2;
+  static constexpr int PH = INV + PlanTable<N, 16, 1>::size();  // w_k W_{4N}^{k b}, b = 1..3
+  static constexpr int TAB = PH + 3 * N;
   static constexpr int EXCH = LdsSize<N>::value;
   static constexpr int UBUF = N / 4 + 3;
   using Fwd = PlanLayout<N, FWD, 4>;
@@ -606,30 +606,38 @@ __global__ void __launch_bounds__(K3p<N>::BLOCK) k3_range_power_x4p(K3Args a, in
   df.init();
   constexpr int T = C::T;
   constexpr int Q = N / 4;
-  __shared__ float2 tab[C::TAB];
-  __shared__ float2 xch[C::WAVES][C::ROWS][C::EXCH];
-  __shared__ float2 ubuf[C::WAVES][C::ROWS][C::UBUF];
+  static_assert(T % 4 == 0, "the forward load indexes u[(t + T e) / 4] as t/4 + (T/4) e");
+  // one pool with the twiddle table first: its offsets stay below 64 KiB, so
+  // every table read encodes its constant part as the instruction's offset
+  static_assert(C::TAB * 8 < 65536, "twiddle table beyond the LDS offset range");
+  __shared__ float2 pool[C::TAB + C::WAVES * C::ROWS * (C::EXCH + C::UBUF)];
+  float2* const tab = pool;
+  auto xch = reinterpret_cast<float2 (*)[C::ROWS][C::EXCH]>(pool + C::TAB);
+  auto ubuf = reinterpret_cast<float2 (*)[C::ROWS][C::UBUF]>(pool + C::TAB + C::WAVES * C::ROWS * C::EXCH);
 
   copy_plan_twiddles<N, 16, 4>(tab + C::FWD, threadIdx.x, C::BLOCK);
   copy_plan_twiddles<N, 16, 1>(tab + C::INV, threadIdx.x, C::BLOCK);
+  const float2 wc = window_coeffs(a.window);
   {
+    // the window w_k = a0 - a1 cos(2 pi k/N) folded into each phase twiddle
     constexpr int poff = phase_offset(ilog2c(N), 2);
-    for (int i = threadIdx.x; i < 3 * N; i += C::BLOCK) tab[C::PH + i] = g_radar_tw[(unsigned)(poff + N + i)];
-    float* cw = reinterpret_cast<float*>(tab + C::WIN);
-    for (int i = threadIdx.x; i < N; i += C::BLOCK) cw[i] = g_radar_tw[(unsigned)(N + i)].x;
+    for (int i = threadIdx.x; i < 3 * N; i += C::BLOCK) {
+      const float w = wc.x - wc.y * g_radar_tw[(unsigned)(N + (i & (N - 1)))].x;
+      tab[C::PH + i] = cscale(g_radar_tw[(unsigned)(poff + N + i)], w);
+    }
   }
   __syncthreads();
 
   const TwLds<typename C::Fwd> tw_fwd{tab};
   const TwLds<typename C::Inv> tw_inv{tab};
-  const float* cwin = reinterpret_cast<const float*>(tab + C::WIN);
-  const int wave = threadIdx.x >> 6;
+  // wave-uniform, and said so: row indices and P row pointers then live in
+  // scalar registers and each store addresses P as scalar base + lane offset
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int g = lane / T;
   const int t0 = lane - g * T;
   float2* lds = xch[wave][g];
   float2* ub = ubuf[wave][g] + 1;                        // ub[i] = u[i], i in [-1, N/4+1]
-  const float2 wc = window_coeffs(a.window);
   const float c0 = (float)N * wc.x, c1 = -0.5f * (float)N * wc.y;
 
   for (int grp = blockIdx.x * C::WAVES + wave; grp < total_groups; grp += gridDim.x * C::WAVES) {
@@ -664,13 +672,12 @@ __global__ void __launch_bounds__(K3p<N>::BLOCK) k3_range_power_x4p(K3Args a, in
     if (t < 3) ub[t == 0 ? -1 : Q + t - 1] = make_float2(0.0f, 0.0f);
     team_sync<64>();
 
-    // forward DFT_N from span 4 (the zero-padded first radix-4 stage only copies)
+    // forward DFT_N from span 4 (the zero-padded first radix-4 stage only
+    // copies): element t + T e takes u[(t + T e) / 4] = u[t/4 + (T/4) e]
     float2 X[16];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) X[e] = ub[(t + T * e) >> 2];
+    for (int e = 0; e < 16; ++e) X[e] = ub[(t >> 2) + (T / 4) * e];
     fft_stages<N, 16, 4, false>(X, lds, t, true, tw_fwd, df);
-#pragma unroll
-    for (int e = 0; e < 16; ++e) X[e] = cscale(X[e], wc.x - wc.y * cwin[t + T * e]);
 
     RADAR_GLOBAL float* dst = gptr(a.refs ? a.refs[f].P : a.P + (int64_t)f * a.p_stride) + (int64_t)row * (4 * N);
     if constexpr (kOneStore) {
@@ -697,7 +704,7 @@ __global__ void __launch_bounds__(K3p<N>::BLOCK) k3_range_power_x4p(K3Args a, in
           for (int e = 0; e < 16; ++e) {
             const float p0 = cabs2(phase0_filter<N>(ub, t + T * e, c0, c1)) * a.scale;
             gstore4(dst + 4 * (t + T * e), p0, p1[e], p2[e], gv[e].x);
-            mx = fmaxf(mx, fmaxf(fmaxf(p0, p1[e]), fmaxf(p2[e], gv[e].x)));
+            mx = fmaxf(fmaxf(fmaxf(fmaxf(mx, p0), p1[e]), p2[e]), gv[e].x);
           }
 #pragma unroll
           for (int m = T / 2; m > 0; m >>= 1) mx = fmaxf(mx, __shfl_xor(mx, m));
