@@ -271,8 +271,15 @@ struct K2Tile {
   using Plan = PlanLayout<M, 0, 1>;
 };
 
+// K2 runs persistent in the FP32 form; the matrix-core forms hold their DFT
+// fragments in registers throughout and launch one work-group per item.
+template <Prec PR>
+struct K2Persistent {
+  static constexpr bool value = PR == Prec::FP32;
+};
+
 template <int M, int TW, Prec PR = Prec::FP32>
-__global__ void __launch_bounds__((K2Tile<M, TW>::BLOCK)) k2_doppler_tiled(K2Args a) {
+__global__ void __launch_bounds__((K2Tile<M, TW>::BLOCK)) k2_doppler_tiled(K2Args a, int n_tiles, int total) {
   using C = K2Tile<M, TW>;
   typename DftFor<PR>::type df;
   df.init();
@@ -281,73 +288,95 @@ __global__ void __launch_bounds__((K2Tile<M, TW>::BLOCK)) k2_doppler_tiled(K2Arg
   __shared__ float2 twtab[C::TWN];
   if constexpr (C::kLdsTw) copy_plan_twiddles<M, 16, 1>(twtab, threadIdx.x, BLOCK);  // ordered by the tile's barrier
   const int team = threadIdx.x / T;
-  const int t = threadIdx.x - team * T;
-  const int b = blockIdx.y;
-  const int f = blockIdx.z;
-  const int n0 = blockIdx.x * TW;
-  const int ntap = min(TW, a.n_cp - n0);
-
-  // tile of taps [l][n0 .. n0+TW).  Up to M = 1024 each thread issues its
-  // loads eight at a time before the LDS stores: a load per loop iteration
-  // with a wait before each store serialises the memory latency.  The ragged
-  // last tile clamps its column and stores zeros there, so every load is
-  // unconditional and in bounds.  The longest transforms keep the plain loop
-  // (their FFT leaves no registers for the batch).
-  static_assert(M * TW == 16 * BLOCK, "16 tile elements per thread");
-  constexpr bool kBatched = M <= 1024;
-  const float2* in = a.taps + (int64_t)f * M * a.n_cp + n0;
-  if constexpr (kBatched) {
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      float2 tv[8];
-#pragma unroll
-      for (int it = 0; it < 8; ++it) {
-        const int i = threadIdx.x + (8 * h + it) * BLOCK;
-        const int l = i / TW, c = i - l * TW;
-        tv[it] = in[(int64_t)l * a.n_cp + (c < ntap ? c : ntap - 1)];
-      }
-#pragma unroll
-      for (int it = 0; it < 8; ++it) {
-        const int i = threadIdx.x + (8 * h + it) * BLOCK;
-        const int l = i / TW, c = i - l * TW;
-        sh[l * LD + c] = c < ntap ? tv[it] : make_float2(0.0f, 0.0f);
-      }
-    }
-  } else {
-    for (int i = threadIdx.x; i < M * TW; i += BLOCK) {
-      const int l = i / TW, c = i - l * TW;
-      sh[l * LD + c] = c < ntap ? in[(int64_t)l * a.n_cp + c] : make_float2(0.0f, 0.0f);
-    }
-  }
-  __syncthreads();
-  float2 v[16];
-#pragma unroll
-  for (int e = 0; e < 16; ++e) v[e] = sh[(t + T * e) * LD + team];
-  if (b != 0) {
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int l = t + T * e;
-      const float2 w = a.ph_off >= 0 ? g_radar_tw[(unsigned)(a.ph_off + b * M + l)] : twiddle(a.m_pad, l * b);
-      v[e] = cmul(v[e], w);
-    }
-  }
-  __syncthreads();  // the tile is reused as exchange space
-  if constexpr (C::kLdsTw)
-    fft_stages<M, 16, 1, false>(v, sh + team * C::EXCH, t, true, TwLds<typename C::Plan>{twtab}, df);
-  else
-    team_fft<M, 16, false>(v, sh + team * C::EXCH, t, true, df);
-  __syncthreads();  // every team is done with its exchange region
-#pragma unroll
-  for (int e = 0; e < 16; ++e) sh[(t + T * e) * LD + team] = v[e];
-  __syncthreads();
-  float2* out = a.U + (int64_t)f * a.m_pad * a.n_cp + n0;
+  const int t0 = threadIdx.x - team * T;
   const int half = a.m_pad >> 1;
-  for (int i = threadIdx.x; i < M * TW; i += BLOCK) {
-    const int s1 = i / TW, c = i - s1 * TW;
-    if (c < ntap) {
-      const int row = (a.fm * s1 + b + half) & (a.m_pad - 1);
-      out[(int64_t)row * a.n_cp + c] = sh[s1 * LD + c];
+
+  // one (tile, b, frame) item, tile fastest
+  auto run = [&](int item) {
+    // the team lane, opaque to the optimiser (an empty asm statement emits
+    // no instruction) and masked back to its range: the per-element LDS
+    // addresses are formed again per item instead of held in registers
+    int t = t0;
+    asm volatile("" : "+v"(t));
+    t &= T - 1;
+    const int tile = item % n_tiles;
+    const int rest = item / n_tiles;
+    const int b = rest % a.fm;
+    const int f = rest / a.fm;
+    const int n0 = tile * TW;
+    const int ntap = min(TW, a.n_cp - n0);
+
+    // tile of taps [l][n0 .. n0+TW).  Up to M = 1024 each thread issues its
+    // loads eight at a time before the LDS stores: a load per loop iteration
+    // with a wait before each store serialises the memory latency.  The
+    // ragged last tile clamps its column and stores zeros there, so every
+    // load is unconditional and in bounds.  The longest transforms keep the
+    // plain loop (their FFT leaves no registers for the batch).
+    static_assert(M * TW == 16 * BLOCK, "16 tile elements per thread");
+    constexpr bool kBatched = M <= 1024;
+    const float2* in = a.taps + (int64_t)f * M * a.n_cp + n0;
+    if constexpr (kBatched) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        float2 tv[8];
+#pragma unroll
+        for (int it = 0; it < 8; ++it) {
+          const int i = threadIdx.x + (8 * h + it) * BLOCK;
+          const int l = i / TW, c = i - l * TW;
+          tv[it] = in[(int64_t)l * a.n_cp + (c < ntap ? c : ntap - 1)];
+        }
+        // the previous item's reads of the tile are done before it is refilled
+        if (h == 0) __syncthreads();
+#pragma unroll
+        for (int it = 0; it < 8; ++it) {
+          const int i = threadIdx.x + (8 * h + it) * BLOCK;
+          const int l = i / TW, c = i - l * TW;
+          sh[l * LD + c] = c < ntap ? tv[it] : make_float2(0.0f, 0.0f);
+        }
+      }
+    } else {
+      __syncthreads();
+      for (int i = threadIdx.x; i < M * TW; i += BLOCK) {
+        const int l = i / TW, c = i - l * TW;
+        sh[l * LD + c] = c < ntap ? in[(int64_t)l * a.n_cp + c] : make_float2(0.0f, 0.0f);
+      }
     }
+    __syncthreads();
+    float2 v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) v[e] = sh[(t + T * e) * LD + team];
+    if (b != 0) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int l = t + T * e;
+        const float2 w = a.ph_off >= 0 ? g_radar_tw[(unsigned)(a.ph_off + b * M + l)] : twiddle(a.m_pad, l * b);
+        v[e] = cmul(v[e], w);
+      }
+    }
+    __syncthreads();  // the tile is reused as exchange space
+    if constexpr (C::kLdsTw)
+      fft_stages<M, 16, 1, false>(v, sh + team * C::EXCH, t, true, TwLds<typename C::Plan>{twtab}, df);
+    else
+      team_fft<M, 16, false>(v, sh + team * C::EXCH, t, true, df);
+    __syncthreads();  // every team is done with its exchange region
+#pragma unroll
+    for (int e = 0; e < 16; ++e) sh[(t + T * e) * LD + team] = v[e];
+    __syncthreads();
+    float2* out = a.U + (int64_t)f * a.m_pad * a.n_cp + n0;
+    for (int i = threadIdx.x; i < M * TW; i += BLOCK) {
+      const int s1 = i / TW, c = i - s1 * TW;
+      if (c < ntap) {
+        const int row = (a.fm * s1 + b + half) & (a.m_pad - 1);
+        out[(int64_t)row * a.n_cp + c] = sh[s1 * LD + c];
+      }
+    }
+  };
+  if constexpr (K2Persistent<PR>::value) {
+    // persistent over the items: a work-group's stores of one item drain
+    // while it loads the next
+    for (int item = blockIdx.x; item < total; item += gridDim.x) run(item);
+  } else {
+    run(blockIdx.x);  // one work-group per item (the loop-carried state would spill)
   }
 }
 

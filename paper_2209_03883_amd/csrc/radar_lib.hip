@@ -141,6 +141,7 @@ struct Tuning {
   bool k3_generic = false; // use the one-team-per-row range kernel instead of the four-phase one
 };
 thread_local Tuning g_tune;
+int g_num_cus = 0;  // compute units of the device, set by radar_init
 
 // Records the opening event of a timed stage launch; returns the slot or -1.
 int timer_open(int stage, hipStream_t s) {
@@ -177,8 +178,22 @@ void launch_k2_m(const radar::K2Args& a, int n_cp, int F, hipStream_t s) {
   constexpr int T = M / 16;
   constexpr int TW0 = 1024 / T < 64 ? 1024 / T : 64;
   constexpr int TW = M * (TW0 + 1) <= 17408 ? TW0 : 17408 / M - 1;
-  dim3 grid((n_cp + TW - 1) / TW, a.fm, F);
-  hipLaunchKernelGGL((radar::k2_doppler_tiled<M, TW, PR>), grid, dim3(radar::K2Tile<M, TW>::BLOCK), 0, s, a);
+  // persistent: as many work-groups as fit on the device at once (a static
+  // initialised once, thread-safely, on the first call for this shape)
+  static const int per_cu = [] {
+    int v = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, radar::k2_doppler_tiled<M, TW, PR>,
+                                                     radar::K2Tile<M, TW>::BLOCK, 0) != hipSuccess ||
+        v < 1)
+      v = 1;
+    return v;
+  }();
+  const int n_tiles = (n_cp + TW - 1) / TW;
+  const int total = n_tiles * a.fm * F;
+  int grid = (g_num_cus > 0 ? g_num_cus : 256) * per_cu;
+  if (grid > total || !radar::K2Persistent<PR>::value) grid = total;
+  hipLaunchKernelGGL((radar::k2_doppler_tiled<M, TW, PR>), dim3(grid), dim3(radar::K2Tile<M, TW>::BLOCK), 0, s, a,
+                     n_tiles, total);
 }
 template <int N, int F2>
 void launch_k3_nf(const radar::K3Args& a, int m_pad, int F, hipStream_t s) {
@@ -192,7 +207,6 @@ void launch_k3x4_n(const radar::K3Args& a, int m_pad, int F, hipStream_t s) {
   dim3 grid(m_pad / C::ROWS, F);
   hipLaunchKernelGGL((radar::k3_range_power_x4<N, PR>), grid, dim3(C::BLOCK), 0, s, a);
 }
-int g_num_cus = 0;
 template <int N>
 void launch_k1p_n(const radar::K1Args& a, int M, int F, hipStream_t s) {
   using C = radar::K1p<N>;
