@@ -647,11 +647,16 @@ __global__ void __launch_bounds__(K3p<N>::BLOCK) k3_range_power_x4p(K3Args a, in
   copy_plan_twiddles<N, 16, 4>(tab + C::FWD, threadIdx.x, C::BLOCK);
   copy_plan_twiddles<N, 16, 1>(tab + C::INV, threadIdx.x, C::BLOCK);
   const float2 wc = window_coeffs(a.window);
+  // sqrt of the 1/(N M) normalisation: applied to the transform inputs (the
+  // transform is linear), so |G|^2 comes out normalised with no multiply per
+  // cell
+  const float rs = sqrtf(a.scale);
   {
-    // the window w_k = a0 - a1 cos(2 pi k/N) folded into each phase twiddle
+    // the window w_k = a0 - a1 cos(2 pi k/N) and rs folded into each phase
+    // twiddle
     constexpr int poff = phase_offset(ilog2c(N), 2);
     for (int i = threadIdx.x; i < 3 * N; i += C::BLOCK) {
-      const float w = wc.x - wc.y * g_radar_tw[(unsigned)(N + (i & (N - 1)))].x;
+      const float w = (wc.x - wc.y * g_radar_tw[(unsigned)(N + (i & (N - 1)))].x) * rs;
       tab[C::PH + i] = cscale(g_radar_tw[(unsigned)(poff + N + i)], w);
     }
   }
@@ -667,7 +672,7 @@ __global__ void __launch_bounds__(K3p<N>::BLOCK) k3_range_power_x4p(K3Args a, in
   const int t0 = lane - g * T;
   float2* lds = xch[wave][g];
   float2* ub = ubuf[wave][g] + 1;                        // ub[i] = u[i], i in [-1, N/4+1]
-  const float c0 = (float)N * wc.x, c1 = -0.5f * (float)N * wc.y;
+  const float c0 = (float)N * wc.x * rs, c1 = -0.5f * (float)N * wc.y * rs;
 
   for (int grp = blockIdx.x * C::WAVES + wave; grp < total_groups; grp += gridDim.x * C::WAVES) {
     const int grow = grp * C::ROWS + g;                   // row over all frames
@@ -722,7 +727,7 @@ __global__ void __launch_bounds__(K3p<N>::BLOCK) k3_range_power_x4p(K3Args a, in
         fft_stages<N, 16, 1, true>(gv, lds, t, true, tw_inv, df);
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-          const float pv = cabs2(gv[e]) * a.scale;
+          const float pv = cabs2(gv[e]);
           if (phase == 1) p1[e] = pv;
           else if (phase == 2) p2[e] = pv;
           else gv[e].x = pv;  // p3
@@ -731,7 +736,7 @@ __global__ void __launch_bounds__(K3p<N>::BLOCK) k3_range_power_x4p(K3Args a, in
           float mx = 0.0f;
 #pragma unroll
           for (int e = 0; e < 16; ++e) {
-            const float p0 = cabs2(phase0_filter<N>(ub, t + T * e, c0, c1)) * a.scale;
+            const float p0 = cabs2(phase0_filter<N>(ub, t + T * e, c0, c1));
             gstore4(dst + 4 * (t + T * e), p0, p1[e], p2[e], gv[e].x);
             mx = fmaxf(fmaxf(fmaxf(fmaxf(mx, p0), p1[e]), p2[e]), gv[e].x);
           }
@@ -754,18 +759,18 @@ __global__ void __launch_bounds__(K3p<N>::BLOCK) k3_range_power_x4p(K3Args a, in
         if (phase == 3) {
 #pragma unroll
           for (int e = 0; e < 16; ++e) {
-            const float p3 = cabs2(gv[e]) * a.scale;
+            const float p3 = cabs2(gv[e]);
             gstore2(dst + 2 * (2 * (t + T * e) + 1), p_first[e], p3);
             mx = fmaxf(mx, fmaxf(p_first[e], p3));
           }
         } else {
 #pragma unroll
-          for (int e = 0; e < 16; ++e) p_first[e] = cabs2(gv[e]) * a.scale;
+          for (int e = 0; e < 16; ++e) p_first[e] = cabs2(gv[e]);
         }
       }
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
-        const float p0 = cabs2(phase0_filter<N>(ub, t + T * e, c0, c1)) * a.scale;
+        const float p0 = cabs2(phase0_filter<N>(ub, t + T * e, c0, c1));
         gstore2(dst + 4 * (t + T * e), p0, p_first[e]);
         mx = fmaxf(mx, fmaxf(p0, p_first[e]));
       }
