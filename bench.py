@@ -131,7 +131,8 @@ def cpu_baseline(frames, budget_s):
 
 def time_extras(radar, torch, Yd, Ad, cfg, ws, peaks, n_peaks, status, stream, B, steps, warmup):
     """Figures beside the headline: the same step with sub-cell refinement of
-    the k peaks, with threshold detection (Eq. 18), with dense ZC precoding
+    the k peaks, with threshold detection (Eq. 18), with the periodogram not
+    materialised (peaks only), with dense ZC precoding
     (on frames precoded that way), the time-domain frame simulation, in the
     BF16x3 and FP16x3 matrix-core forms, the CNN refiner, and FPS-SFT (eight
     directions, K = 8) on the same frames."""
@@ -174,6 +175,23 @@ def time_extras(radar, torch, Yd, Ad, cfg, ws, peaks, n_peaks, status, stream, B
     out["threshold_stage_us_per_frame"] = {k: st[k][0] / max(st[k][1], 1) * 1e3 / B for k in ("taps", "peaks")}
     out["threshold_mean_detections"] = float(n_peaks.float().mean())
     del P, wst
+
+    # peaks only (P = NULL): the range stage keeps its row maxima and the
+    # peak search recomputes the rows it scans; no periodogram is written
+    for _ in range(warmup):
+        radar.frame_process(Yd, Ad, cfg, K, workspace=ws, peaks=peaks, n_peaks=n_peaks, status=status,
+                            stream=stream, materialise=False)
+    radar.timing_start(steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        radar.frame_process(Yd, Ad, cfg, K, workspace=ws, peaks=peaks, n_peaks=n_peaks, status=status,
+                            stream=stream, materialise=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = radar.timing_stop()
+    out["peaks_only_frames_per_s"] = B * steps / dt
+    out["peaks_only_stage_us_per_frame"] = {k: st[k][0] / max(st[k][1], 1) * 1e3 / B for k in ("range", "peaks")}
 
     # dense ZC precoding (Eq. 24 read literally): frames whose transmitter
     # applied the dense precoding; the FP64 precoding-and-division kernel runs

@@ -160,8 +160,18 @@ int radar_init(void);
  *   of 1/|a|^2 over the frame is taken from A by the taps stage).  n_peaks
  *   counts only those detections.
  * Y, A:     input frames, frame f at Y + f*frame_stride (elements).
- * P:        output, frame f at P + f*p_frame_stride (floats); must not be NULL;
+ * P:        output, frame f at P + f*p_frame_stride (floats);
  *           p_frame_stride >= M'*N' and a multiple of 4; P 16-byte aligned.
+ *           NULL: peaks only, P is not materialised (p_frame_stride ignored).
+ *           The range stage then keeps only its row maxima, and the peak
+ *           search recomputes each row it scans (and that row's two
+ *           neighbours) with the range stage's own row code, compiled into
+ *           a second kernel: a recomputed cell may differ from the written
+ *           one by a few FP32 ulps (the compiler may order a multiply-add
+ *           differently), so the peaks match those found with P written
+ *           except at near-ties.  Supported for N in {256, 512, 1024},
+ *           N' = 4N and 4 N_cp <= N, in every precision form
+ *           (RADAR_E_UNSUPPORTED otherwise).
  * peaks:    output, k entries per frame at peaks + f*k; n_peaks[f] = number
  *           written (< k only if P has fewer than k local maxima).
  * status:   output, one word per frame (RADAR_ST_* bits; 0 = clean).

@@ -625,17 +625,165 @@ __device__ __forceinline__ float2 phase0_filter(const float2* ub, int r1, float 
   return make_float2(0.0f, 0.0f);
 }
 
-template <int N, Prec PR = Prec::FP32>
-__global__ void __launch_bounds__(K3p<N>::BLOCK) k3_range_power_x4p(K3Args a, int total_groups) {
+// Where one range row of P goes: cell i (in r = 4 r1 + b order) and the
+// next one, two or four cells.
+struct RowToGlobal {
+  RADAR_GLOBAL float* dst;
+  __device__ __forceinline__ void store4(int i, float a, float b, float c, float d) const { gstore4(dst + i, a, b, c, d); }
+  __device__ __forceinline__ void store2(int i, float a, float b) const { gstore2(dst + i, a, b); }
+};
+// Nowhere: only the row maximum is kept (P not materialised).
+struct RowToNowhere {
+  __device__ __forceinline__ void store4(int, float, float, float, float) const {}
+  __device__ __forceinline__ void store2(int, float, float) const {}
+};
+// An LDS row (16-byte aligned), or nowhere when null.
+struct RowToLds {
+  float* row;
+  __device__ __forceinline__ void store4(int i, float a, float b, float c, float d) const {
+    if (row) *reinterpret_cast<float4*>(row + i) = make_float4(a, b, c, d);
+  }
+  __device__ __forceinline__ void store2(int i, float a, float b) const {
+    if (row) *reinterpret_cast<float2*>(row + i) = make_float2(a, b);
+  }
+};
+
+// one 16-byte store per four-phase group where holding two phases fits in
+// registers (no scratch): measured for the FP32 form at N >= 512
+template <int N, Prec PR>
+struct K3pOrder {
+  static constexpr bool kOneStore = PR == Prec::FP32 && N >= 512;
+};
+
+// The range kernel's LDS tables: the stage blocks of its two FFT plans, then
+// the phase twiddles W_{4N}^{k b} (b = 1..3) times the window w_k = a0 - a1
+// cos(2 pi k/N) times rs = sqrt(1/(N M)): the normalisation applied to the
+// transform inputs (the transform is linear), so |G|^2 comes out normalised
+// with no multiply per cell.  Returns the phase-0 filter's coefficients
+// (c0, c1), which carry rs too.
+template <int N>
+__device__ __forceinline__ float2 k3p_tables(float2* tab, int window, float scale, int tid, int nthreads) {
   using C = K3p<N>;
-  // one 16-byte store per four-phase group where holding two phases fits in
-  // registers (no scratch): measured for the FP32 form at N >= 512
-  constexpr bool kOneStore = PR == Prec::FP32 && N >= 512;
-  typename DftFor<PR>::type df;
-  df.init();
+  copy_plan_twiddles<N, 16, 4>(tab + C::FWD, tid, nthreads);
+  copy_plan_twiddles<N, 16, 1>(tab + C::INV, tid, nthreads);
+  const float2 wc = window_coeffs(window);
+  const float rs = sqrtf(scale);
+  constexpr int poff = phase_offset(ilog2c(N), 2);
+  for (int i = tid; i < 3 * N; i += nthreads) {
+    const float w = (wc.x - wc.y * g_radar_tw[(unsigned)(N + (i & (N - 1)))].x) * rs;
+    tab[C::PH + i] = cscale(g_radar_tw[(unsigned)(poff + N + i)], w);
+  }
+  return make_float2((float)N * wc.x * rs, -0.5f * (float)N * wc.y * rs);
+}
+
+// One Doppler row of the range stage by one team of T = N/16 lanes (lane t):
+// the taps u (N_cp <= N/4 of them, row pointer `in`) through `ub` (LDS,
+// ub[-1 .. N/4+1]), the forward DFT_N, the three phase IFFTs and the phase-0
+// filter, every |G|^2 cell to `sink`.  Returns the row maximum (in every lane
+// of the team).  The team's LDS exchange region is `lds`.
+template <int N, Prec PR, class DF, class Sink>
+__device__ __forceinline__ float k3p_row(const float2* in, int n_cp, float2* lds, float2* ub, int t,
+                                         const float2* tab, float c0, float c1, const DF& df, const Sink& sink) {
+  using C = K3p<N>;
   constexpr int T = C::T;
   constexpr int Q = N / 4;
   static_assert(T % 4 == 0, "the forward load indexes u[(t + T e) / 4] as t/4 + (T/4) e");
+  const TwLds<typename C::Fwd> tw_fwd{tab};
+  const TwLds<typename C::Inv> tw_inv{tab};
+  {
+    float2 uv[Q / T];
+#pragma unroll
+    for (int e = 0; e < Q / T; ++e) {
+      const int n = t + T * e;
+      uv[e] = in[n < n_cp ? n : 0];
+    }
+#pragma unroll
+    for (int e = 0; e < Q / T; ++e) {
+      const int n = t + T * e;
+      ub[n] = n < n_cp ? uv[e] : make_float2(0.0f, 0.0f);
+    }
+  }
+  if (t < 3) ub[t == 0 ? -1 : Q + t - 1] = make_float2(0.0f, 0.0f);
+  team_sync<64>();
+
+  // forward DFT_N from span 4 (the zero-padded first radix-4 stage only
+  // copies): element t + T e takes u[(t + T e) / 4] = u[t/4 + (T/4) e]
+  float2 X[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) X[e] = ub[(t >> 2) + (T / 4) * e];
+  fft_stages<N, 16, 4, false>(X, lds, t, true, tw_fwd, df);
+
+  float mx = 0.0f;
+  if constexpr (K3pOrder<N, PR>::kOneStore) {
+    // phases 1, 2, 3 in turn; X dies after the last twiddle product, so
+    // holding p1 and p2 through the last transform costs no more registers
+    // than X did, and each four-phase group of P leaves in one 16-byte store
+    float p1[16], p2[16];
+#pragma unroll
+    for (int phase = 1; phase <= 3; ++phase) {
+      float2 gv[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) gv[e] = cmulc(X[e], tab[C::PH + (phase - 1) * N + t + T * e]);
+      fft_stages<N, 16, 1, true>(gv, lds, t, true, tw_inv, df);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const float pv = cabs2(gv[e]);
+        if (phase == 1) p1[e] = pv;
+        else if (phase == 2) p2[e] = pv;
+        else gv[e].x = pv;  // p3
+      }
+      if (phase == 3) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const float p0 = cabs2(phase0_filter<N>(ub, t + T * e, c0, c1));
+          sink.store4(4 * (t + T * e), p0, p1[e], p2[e], gv[e].x);
+          mx = fmaxf(fmaxf(fmaxf(fmaxf(mx, p0), p1[e]), p2[e]), gv[e].x);
+        }
+      }
+    }
+  } else {
+    // phases 2 and 3 leave as one 8-byte store, then phase 1 and phase 0
+    float p_first[16];
+#pragma unroll
+    for (int b = 2; b <= 4; ++b) {
+      const int phase = b == 4 ? 1 : b;
+      float2 gv[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) gv[e] = cmulc(X[e], tab[C::PH + (phase - 1) * N + t + T * e]);
+      fft_stages<N, 16, 1, true>(gv, lds, t, true, tw_inv, df);
+      if (phase == 3) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const float p3 = cabs2(gv[e]);
+          sink.store2(2 * (2 * (t + T * e) + 1), p_first[e], p3);
+          mx = fmaxf(mx, fmaxf(p_first[e], p3));
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) p_first[e] = cabs2(gv[e]);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const float p0 = cabs2(phase0_filter<N>(ub, t + T * e, c0, c1));
+      sink.store2(4 * (t + T * e), p0, p_first[e]);
+      mx = fmaxf(mx, fmaxf(p0, p_first[e]));
+    }
+  }
+#pragma unroll
+  for (int m = T / 2; m > 0; m >>= 1) mx = fmaxf(mx, __shfl_xor(mx, m));
+  return mx;
+}
+
+// kStore = false: the row maxima only, P not written (the peak search then
+// recomputes the few rows it needs).
+template <int N, Prec PR = Prec::FP32, bool kStore = true>
+__global__ void __launch_bounds__(K3p<N>::BLOCK) k3_range_power_x4p(K3Args a, int total_groups) {
+  using C = K3p<N>;
+  constexpr bool kOneStore = K3pOrder<N, PR>::kOneStore;
+  typename DftFor<PR>::type df;
+  df.init();
+  constexpr int T = C::T;
   // one pool with the twiddle table first: its offsets stay below 64 KiB, so
   // every table read encodes its constant part as the instruction's offset
   static_assert(C::TAB * 8 < 65536, "twiddle table beyond the LDS offset range");
@@ -643,27 +791,9 @@ __global__ void __launch_bounds__(K3p<N>::BLOCK) k3_range_power_x4p(K3Args a, in
   float2* const tab = pool;
   auto xch = reinterpret_cast<float2 (*)[C::ROWS][C::EXCH]>(pool + C::TAB);
   auto ubuf = reinterpret_cast<float2 (*)[C::ROWS][C::UBUF]>(pool + C::TAB + C::WAVES * C::ROWS * C::EXCH);
-
-  copy_plan_twiddles<N, 16, 4>(tab + C::FWD, threadIdx.x, C::BLOCK);
-  copy_plan_twiddles<N, 16, 1>(tab + C::INV, threadIdx.x, C::BLOCK);
-  const float2 wc = window_coeffs(a.window);
-  // sqrt of the 1/(N M) normalisation: applied to the transform inputs (the
-  // transform is linear), so |G|^2 comes out normalised with no multiply per
-  // cell
-  const float rs = sqrtf(a.scale);
-  {
-    // the window w_k = a0 - a1 cos(2 pi k/N) and rs folded into each phase
-    // twiddle
-    constexpr int poff = phase_offset(ilog2c(N), 2);
-    for (int i = threadIdx.x; i < 3 * N; i += C::BLOCK) {
-      const float w = (wc.x - wc.y * g_radar_tw[(unsigned)(N + (i & (N - 1)))].x) * rs;
-      tab[C::PH + i] = cscale(g_radar_tw[(unsigned)(poff + N + i)], w);
-    }
-  }
+  const float2 cf = k3p_tables<N>(tab, a.window, a.scale, threadIdx.x, C::BLOCK);
   __syncthreads();
 
-  const TwLds<typename C::Fwd> tw_fwd{tab};
-  const TwLds<typename C::Inv> tw_inv{tab};
   // wave-uniform, and said so: row indices and P row pointers then live in
   // scalar registers and each store addresses P as scalar base + lane offset
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -672,7 +802,6 @@ __global__ void __launch_bounds__(K3p<N>::BLOCK) k3_range_power_x4p(K3Args a, in
   const int t0 = lane - g * T;
   float2* lds = xch[wave][g];
   float2* ub = ubuf[wave][g] + 1;                        // ub[i] = u[i], i in [-1, N/4+1]
-  const float c0 = (float)N * wc.x * rs, c1 = -0.5f * (float)N * wc.y * rs;
 
   for (int grp = blockIdx.x * C::WAVES + wave; grp < total_groups; grp += gridDim.x * C::WAVES) {
     const int grow = grp * C::ROWS + g;                   // row over all frames
@@ -690,94 +819,14 @@ __global__ void __launch_bounds__(K3p<N>::BLOCK) k3_range_power_x4p(K3Args a, in
       asm volatile("" : "+v"(t));
       t &= T - 1;
     }
-    {
-      float2 uv[Q / T];
-#pragma unroll
-      for (int e = 0; e < Q / T; ++e) {
-        const int n = t + T * e;
-        uv[e] = in[n < a.n_cp ? n : 0];
-      }
-#pragma unroll
-      for (int e = 0; e < Q / T; ++e) {
-        const int n = t + T * e;
-        ub[n] = n < a.n_cp ? uv[e] : make_float2(0.0f, 0.0f);
-      }
-    }
-    if (t < 3) ub[t == 0 ? -1 : Q + t - 1] = make_float2(0.0f, 0.0f);
-    team_sync<64>();
-
-    // forward DFT_N from span 4 (the zero-padded first radix-4 stage only
-    // copies): element t + T e takes u[(t + T e) / 4] = u[t/4 + (T/4) e]
-    float2 X[16];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) X[e] = ub[(t >> 2) + (T / 4) * e];
-    fft_stages<N, 16, 4, false>(X, lds, t, true, tw_fwd, df);
-
-    RADAR_GLOBAL float* dst = gptr(a.refs ? a.refs[f].P : a.P + (int64_t)f * a.p_stride) + (int64_t)row * (4 * N);
-    if constexpr (kOneStore) {
-      // phases 1, 2, 3 in turn; X dies after the last twiddle product, so
-      // holding p1 and p2 through the last transform costs no more registers
-      // than X did, and each four-phase group of P leaves in one 16-byte store
-      float p1[16], p2[16];
-#pragma unroll
-      for (int phase = 1; phase <= 3; ++phase) {
-        float2 gv[16];
-#pragma unroll
-        for (int e = 0; e < 16; ++e) gv[e] = cmulc(X[e], tab[C::PH + (phase - 1) * N + t + T * e]);
-        fft_stages<N, 16, 1, true>(gv, lds, t, true, tw_inv, df);
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          const float pv = cabs2(gv[e]);
-          if (phase == 1) p1[e] = pv;
-          else if (phase == 2) p2[e] = pv;
-          else gv[e].x = pv;  // p3
-        }
-        if (phase == 3) {
-          float mx = 0.0f;
-#pragma unroll
-          for (int e = 0; e < 16; ++e) {
-            const float p0 = cabs2(phase0_filter<N>(ub, t + T * e, c0, c1));
-            gstore4(dst + 4 * (t + T * e), p0, p1[e], p2[e], gv[e].x);
-            mx = fmaxf(fmaxf(fmaxf(fmaxf(mx, p0), p1[e]), p2[e]), gv[e].x);
-          }
-#pragma unroll
-          for (int m = T / 2; m > 0; m >>= 1) mx = fmaxf(mx, __shfl_xor(mx, m));
-          if (t == 0) a.rowmax[grow] = mx;
-        }
-      }
+    float mx;
+    if constexpr (kStore) {
+      const RowToGlobal sink{gptr(a.refs ? a.refs[f].P : a.P + (int64_t)f * a.p_stride) + (int64_t)row * (4 * N)};
+      mx = k3p_row<N, PR>(in, a.n_cp, lds, ub, t, tab, cf.x, cf.y, df, sink);
     } else {
-      // phases 2 and 3 leave as one 8-byte store, then phase 1 and phase 0
-      float mx = 0.0f;
-      float p_first[16];
-#pragma unroll
-      for (int b = 2; b <= 4; ++b) {
-        const int phase = b == 4 ? 1 : b;
-        float2 gv[16];
-#pragma unroll
-        for (int e = 0; e < 16; ++e) gv[e] = cmulc(X[e], tab[C::PH + (phase - 1) * N + t + T * e]);
-        fft_stages<N, 16, 1, true>(gv, lds, t, true, tw_inv, df);
-        if (phase == 3) {
-#pragma unroll
-          for (int e = 0; e < 16; ++e) {
-            const float p3 = cabs2(gv[e]);
-            gstore2(dst + 2 * (2 * (t + T * e) + 1), p_first[e], p3);
-            mx = fmaxf(mx, fmaxf(p_first[e], p3));
-          }
-        } else {
-#pragma unroll
-          for (int e = 0; e < 16; ++e) p_first[e] = cabs2(gv[e]);
-        }
-      }
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const float p0 = cabs2(phase0_filter<N>(ub, t + T * e, c0, c1));
-        gstore2(dst + 4 * (t + T * e), p0, p_first[e]);
-        mx = fmaxf(mx, fmaxf(p0, p_first[e]));
-      }
-#pragma unroll
-      for (int m = T / 2; m > 0; m >>= 1) mx = fmaxf(mx, __shfl_xor(mx, m));
-      if (t == 0) a.rowmax[grow] = mx;
+      mx = k3p_row<N, PR>(in, a.n_cp, lds, ub, t, tab, cf.x, cf.y, df, RowToNowhere{});
     }
+    if (t == 0) a.rowmax[grow] = mx;
     // the next row's tap writes must follow this row's reads of ub
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   }

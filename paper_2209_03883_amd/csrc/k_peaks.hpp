@@ -164,6 +164,96 @@ __global__ void __launch_bounds__(256) k_peak_threshold(const float* rowmax, int
   }
 }
 
+// Step 3 for one listed row: its exact local maxima >= th among the rows
+// above (rm), at (r0) and below (rp), k best of them to out[0..k) (key 0
+// pads).  Called by every thread of the work-group (256 threads; it contains
+// barriers); s_ord holds n_pad words of scratch.  Row pointers may be global
+// or LDS.
+template <class RowPtr>
+__device__ __forceinline__ void row_candidates(RowPtr rm, RowPtr r0, RowPtr rp, int n_pad, int k, float th,
+                                               uint32_t flat0, uint32_t* s_ord, uint64_t* red, int* s_cnt,
+                                               uint64_t* out) {
+  // eight columns per thread at a time, all nine values of each 3 x 3
+  // neighbourhood loaded before any test (unconditional loads, columns
+  // clamped in bounds; the rows are L2-resident), so the loads overlap
+  // instead of waiting one by one
+  for (int base = threadIdx.x; base < n_pad; base += 8 * (int)blockDim.x) {
+    float nb[8][9];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int r = base + u * (int)blockDim.x;
+      const int rc = r < n_pad ? r : 0;
+      const int rl = (rc - 1) & (n_pad - 1);
+      const int rr = (rc + 1) & (n_pad - 1);
+      nb[u][0] = r0[rc];
+      nb[u][1] = r0[rl];
+      nb[u][2] = r0[rr];
+      nb[u][3] = rm[rl];
+      nb[u][4] = rm[rc];
+      nb[u][5] = rm[rr];
+      nb[u][6] = rp[rl];
+      nb[u][7] = rp[rc];
+      nb[u][8] = rp[rr];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int r = base + u * (int)blockDim.x;
+      if (r < n_pad) {
+        const float v = nb[u][0];
+        bool pk = v >= th;
+#pragma unroll
+        for (int q = 1; q < 9; ++q) pk = pk && v >= nb[u][q];
+        s_ord[r] = pk ? ord_bits(v) : 0u;
+      }
+    }
+  }
+  // how many candidates does the row hold?
+  int mine = 0;
+  for (int r = threadIdx.x; r < n_pad; r += blockDim.x) mine += s_ord[r] ? 1 : 0;
+  __syncthreads();
+  int incl = mine;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int up = __shfl_up(incl, off);
+    if ((threadIdx.x & 63) >= off) incl += up;
+  }
+  if ((threadIdx.x & 63) == 63) s_cnt[threadIdx.x >> 6] = incl;
+  __syncthreads();
+  int total = 0, before = 0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+    if (w < (int)(threadIdx.x >> 6)) before += s_cnt[w];
+    total += s_cnt[w];
+  }
+  int i = 0;
+  if (total <= k) {
+    // few candidates: write them all (the merge ranks them), pad with 0
+    int pos = before + incl - mine;
+    for (int r = threadIdx.x; r < n_pad; r += blockDim.x)
+      if (s_ord[r]) out[pos++] = make_key(s_ord[r], flat0 + (uint32_t)r);
+    for (int q = total + (int)threadIdx.x; q < k; q += blockDim.x) out[q] = 0;
+    i = k;  // nothing left to pad below
+  } else {
+    uint64_t last = ~0ull;
+    for (; i < k; ++i) {
+      uint64_t best = 0;
+      for (int r = threadIdx.x; r < n_pad; r += blockDim.x) {
+        const uint32_t o = s_ord[r];
+        if (o) {
+          const uint64_t key = make_key(o, flat0 + (uint32_t)r);
+          if (key < last && key > best) best = key;
+        }
+      }
+      best = block_max_u64(best, red);
+      if (threadIdx.x == 0) out[i] = best;
+      if (best == 0) break;
+      last = best;
+    }
+  }
+  if (threadIdx.x == 0)
+    for (int q = i + 1; q < k; ++q) out[q] = 0;
+  __syncthreads();  // s_ord is rewritten for the next row
+}
+
 // Step 3: exact local maxima >= tau of the listed rows, k best per row.
 // Grid (G, F), 256 threads, dynamic LDS n_pad words.  Output
 // cand[f][j][0..k) for list entry j (key 0 pads).
@@ -183,87 +273,8 @@ __global__ void __launch_bounds__(256) k_peak_rows_listed(const float* P, int64_
     const RADAR_GLOBAL float* rm = base + (int64_t)((row - 1) & (m_pad - 1)) * n_pad;
     const RADAR_GLOBAL float* r0 = base + (int64_t)row * n_pad;
     const RADAR_GLOBAL float* rp = base + (int64_t)((row + 1) & (m_pad - 1)) * n_pad;
-    // eight columns per thread at a time, all nine values of each 3 x 3
-    // neighbourhood loaded before any test (unconditional loads, columns
-    // clamped in bounds; the rows are L2-resident), so the loads overlap
-    // instead of waiting one by one
-    for (int base = threadIdx.x; base < n_pad; base += 8 * (int)blockDim.x) {
-      float nb[8][9];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int r = base + u * (int)blockDim.x;
-        const int rc = r < n_pad ? r : 0;
-        const int rl = (rc - 1) & (n_pad - 1);
-        const int rr = (rc + 1) & (n_pad - 1);
-        nb[u][0] = r0[rc];
-        nb[u][1] = r0[rl];
-        nb[u][2] = r0[rr];
-        nb[u][3] = rm[rl];
-        nb[u][4] = rm[rc];
-        nb[u][5] = rm[rr];
-        nb[u][6] = rp[rl];
-        nb[u][7] = rp[rc];
-        nb[u][8] = rp[rr];
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int r = base + u * (int)blockDim.x;
-        if (r < n_pad) {
-          const float v = nb[u][0];
-          bool pk = v >= th;
-#pragma unroll
-          for (int q = 1; q < 9; ++q) pk = pk && v >= nb[u][q];
-          s_ord[r] = pk ? ord_bits(v) : 0u;
-        }
-      }
-    }
-    uint64_t* out = cand + ((int64_t)f * m_pad + j) * k;
-    const uint32_t flat0 = (uint32_t)row * (uint32_t)n_pad;
-    // how many candidates does the row hold?
-    int mine = 0;
-    for (int r = threadIdx.x; r < n_pad; r += blockDim.x) mine += s_ord[r] ? 1 : 0;
-    __syncthreads();
-    int incl = mine;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int up = __shfl_up(incl, off);
-      if ((threadIdx.x & 63) >= off) incl += up;
-    }
-    if ((threadIdx.x & 63) == 63) s_cnt[threadIdx.x >> 6] = incl;
-    __syncthreads();
-    int total = 0, before = 0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-      if (w < (int)(threadIdx.x >> 6)) before += s_cnt[w];
-      total += s_cnt[w];
-    }
-    int i = 0;
-    if (total <= k) {
-      // few candidates: write them all (the merge ranks them), pad with 0
-      int pos = before + incl - mine;
-      for (int r = threadIdx.x; r < n_pad; r += blockDim.x)
-        if (s_ord[r]) out[pos++] = make_key(s_ord[r], flat0 + (uint32_t)r);
-      for (int q = total + (int)threadIdx.x; q < k; q += blockDim.x) out[q] = 0;
-      i = k;  // nothing left to pad below
-    } else {
-      uint64_t last = ~0ull;
-      for (; i < k; ++i) {
-        uint64_t best = 0;
-        for (int r = threadIdx.x; r < n_pad; r += blockDim.x) {
-          const uint32_t o = s_ord[r];
-          if (o) {
-            const uint64_t key = make_key(o, flat0 + (uint32_t)r);
-            if (key < last && key > best) best = key;
-          }
-        }
-        best = block_max_u64(best, red);
-        if (threadIdx.x == 0) out[i] = best;
-        if (best == 0) break;
-        last = best;
-      }
-    }
-    if (threadIdx.x == 0)
-      for (int q = i + 1; q < k; ++q) out[q] = 0;
-    __syncthreads();  // s_ord is rewritten for the next row
+    row_candidates(rm, r0, rp, n_pad, k, th, (uint32_t)row * (uint32_t)n_pad, s_ord, red, s_cnt,
+                   cand + ((int64_t)f * m_pad + j) * k);
   }
 }
 

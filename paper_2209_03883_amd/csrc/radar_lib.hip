@@ -18,6 +18,7 @@ __device__ float2 g_radar_tw[RADAR_TW_ENTRIES];
 
 #include "k_frame.hpp"
 #include "k_peaks.hpp"
+#include "k_peaks_only.hpp"
 #include "k_refine.hpp"
 #include "k_sft.hpp"
 #include "k_cnn.hpp"
@@ -231,14 +232,14 @@ void launch_dense_n(const radar::DenseArgs& a, hipStream_t s) {
   if (grid > a.total) grid = a.total;
   hipLaunchKernelGGL(radar::k_dense_ls<N>, dim3(grid), dim3(radar::kDenseThreads), 0, s, a);
 }
-template <int N, radar::Prec PR>
+template <int N, radar::Prec PR, bool kStore = true>
 void launch_k3x4p_n(const radar::K3Args& a, int m_pad, int F, hipStream_t s) {
   using C = radar::K3p<N>;
   const int total = (int)((int64_t)F * m_pad / C::ROWS);
   const int per_wg = C::WAVES;
   int grid = (g_num_cus > 0 ? g_num_cus : 256) * g_tune.k3_mult;
   if (grid * per_wg > total) grid = (total + per_wg - 1) / per_wg;
-  hipLaunchKernelGGL((radar::k3_range_power_x4p<N, PR>), dim3(grid), dim3(C::BLOCK), 0, s, a, total);
+  hipLaunchKernelGGL((radar::k3_range_power_x4p<N, PR, kStore>), dim3(grid), dim3(C::BLOCK), 0, s, a, total);
 }
 template <int N>
 void launch_k3_n(const radar::K3Args& a, int f2, int m_pad, int F, hipStream_t s) {
@@ -274,10 +275,65 @@ void launch_k3x4_any(const radar::K3Args& a, int N, int m_pad, int F, hipStream_
   }
 }
 
+// P not materialised: the row maxima only (the x4p shapes; the caller checked
+// peaks_only_supported)
+template <radar::Prec PR>
+void launch_k3x4p_rowmax(const radar::K3Args& a, int N, int m_pad, int F, hipStream_t s) {
+  switch (N) {
+    case 256: launch_k3x4p_n<256, PR, false>(a, m_pad, F, s); break;
+    case 512: launch_k3x4p_n<512, PR, false>(a, m_pad, F, s); break;
+    default: launch_k3x4p_n<1024, PR, false>(a, m_pad, F, s); break;
+  }
+}
+template <radar::Prec PR>
+void launch_rows_recompute(const radar::K3Args& a, int N, int F, int k, const float* tau, const int32_t* list,
+                           const int32_t* cnt, uint64_t* cand, hipStream_t s) {
+  const int groups = a.m_pad < 64 ? a.m_pad : 64;
+  switch (N) {
+    case 256:
+      hipLaunchKernelGGL((radar::k_peak_rows_recompute<256, PR>), dim3(groups, F), dim3(256), 0, s, a, k, tau, list,
+                         cnt, cand);
+      break;
+    case 512:
+      hipLaunchKernelGGL((radar::k_peak_rows_recompute<512, PR>), dim3(groups, F), dim3(256), 0, s, a, k, tau, list,
+                         cnt, cand);
+      break;
+    default:
+      hipLaunchKernelGGL((radar::k_peak_rows_recompute<1024, PR>), dim3(groups, F), dim3(256), 0, s, a, k, tau,
+                         list, cnt, cand);
+      break;
+  }
+}
+
+// Shapes whose periodogram need not be materialised: the range kernel of the
+// 4x padding with N_cp <= N/4 and N <= 1024 keeps row maxima without writing
+// P, and the peak search recomputes the rows it scans.
+bool peaks_only_supported(const radar_frame_desc* d) {
+  const int N = d->n_sub;
+  return (N == 256 || N == 512 || N == 1024) && d->n_pad == 4 * N && d->n_cp * 4 <= N;
+}
+
 radar::Prec prec_of(const radar_frame_desc* d) {
   if (d->flags & RADAR_FLAG_BF16X3) return radar::Prec::BF16X3;
   if (d->flags & RADAR_FLAG_FP16X3) return radar::Prec::FP16X3;
   return radar::Prec::FP32;
+}
+
+// Arguments of the range stage (and of the peaks-only row recomputation).
+radar::K3Args range_args(const radar_frame_desc* d, const float2* U, float* P, int64_t p_stride, float* rowmax,
+                         const radar::FrameRef* refs) {
+  radar::K3Args a3{};
+  a3.U = U;
+  a3.P = P;
+  a3.p_stride = p_stride;
+  a3.m_pad = d->m_pad;
+  a3.n_pad = d->n_pad;
+  a3.n_cp = d->n_cp;
+  a3.window = d->window;
+  a3.scale = (float)(1.0 / ((double)d->n_sub * (double)d->n_sym));
+  a3.rowmax = rowmax;
+  a3.refs = refs;
+  return a3;
 }
 
 // K1 -> K2 -> K3 for one batch of frames with a common descriptor.
@@ -372,21 +428,19 @@ int enqueue_transforms(const radar_frame_desc* d, int F, const float2* in, const
   timer_close(RADAR_STAGE_DOPPLER, slot, s);
   RADAR_HIP_CHECK(hipGetLastError());
 
-  radar::K3Args a3{};
-  a3.U = U;
-  a3.P = P;
-  a3.p_stride = p_stride;
-  a3.m_pad = d->m_pad;
-  a3.n_pad = d->n_pad;
-  a3.n_cp = d->n_cp;
-  a3.window = d->window;
-  a3.scale = (float)(1.0 / ((double)N * (double)M));
-  a3.rowmax = reinterpret_cast<float*>(ws + w.pk.rowmax);
-  a3.refs = refs;
+  const radar::K3Args a3 = range_args(d, U, P, p_stride, reinterpret_cast<float*>(ws + w.pk.rowmax), refs);
   const int f2 = d->n_pad / N;
   const bool x4 = f2 == 4 && d->n_cp * 4 <= N && N >= 256 && !(g_tune.k3_generic && prec == radar::Prec::FP32);
   slot = timer_open(RADAR_STAGE_RANGE, s);
-  if (x4) {
+  if (!P && !refs) {
+    // peaks only: row maxima, no P (peaks_only_supported was checked)
+    if (prec == radar::Prec::BF16X3)
+      launch_k3x4p_rowmax<radar::Prec::BF16X3>(a3, N, d->m_pad, F, s);
+    else if (prec == radar::Prec::FP16X3)
+      launch_k3x4p_rowmax<radar::Prec::FP16X3>(a3, N, d->m_pad, F, s);
+    else
+      launch_k3x4p_rowmax<radar::Prec::FP32>(a3, N, d->m_pad, F, s);
+  } else if (x4) {
     if (prec == radar::Prec::BF16X3)
       launch_k3x4_any<radar::Prec::BF16X3>(a3, N, d->m_pad, F, s);
     else if (prec == radar::Prec::FP16X3)
@@ -400,7 +454,7 @@ int enqueue_transforms(const radar_frame_desc* d, int F, const float2* in, const
   }
   timer_close(RADAR_STAGE_RANGE, slot, s);
   RADAR_HIP_CHECK(hipGetLastError());
-  if (!x4) {
+  if (!x4 && (P || refs)) {
     hipLaunchKernelGGL(radar::k_row_max, dim3(d->m_pad, F), dim3(256), 0, s, P, p_stride, d->m_pad, d->n_pad,
                        a3.rowmax, refs);
     RADAR_HIP_CHECK(hipGetLastError());
@@ -432,9 +486,12 @@ int enqueue_refine(const radar_frame_desc* d, int F, int k, const float2* taps, 
 
 // Peak search from P and its row maxima (already in the workspace).
 // With inv_sum (threshold detection) the merge keeps only peaks at or above eta.
+// With P null (peaks only, frame_process) the listed rows are recomputed from
+// the Doppler-tap rows U by the range kernel's row code (`d` and `U` given).
 int enqueue_peaks(const float* P, int64_t p_stride, int m_pad, int n_pad, int F, int k, const PeakWs& w, char* ws,
                   radar_peak* peaks, int32_t* n_peaks, hipStream_t s, const radar::FrameRef* refs = nullptr,
-                  const float* inv_sum = nullptr, int M = 0, float eta_factor = 0.0f) {
+                  const float* inv_sum = nullptr, int M = 0, float eta_factor = 0.0f,
+                  const radar_frame_desc* d = nullptr, const float2* U = nullptr) {
   float* rowmax = reinterpret_cast<float*>(ws + w.rowmax);
   float* tau = reinterpret_cast<float*>(ws + w.tau);
   int32_t* cnt = reinterpret_cast<int32_t*>(ws + w.cnt);
@@ -444,9 +501,21 @@ int enqueue_peaks(const float* P, int64_t p_stride, int m_pad, int n_pad, int F,
   hipLaunchKernelGGL(radar::k_peak_threshold, dim3(F), dim3(256), 2 * m_pad * sizeof(uint32_t), s, rowmax, m_pad, k, tau,
                      list, cnt);
   RADAR_HIP_CHECK(hipGetLastError());
-  const int groups = m_pad < 32 ? m_pad : 32;
-  hipLaunchKernelGGL(radar::k_peak_rows_listed, dim3(groups, F), dim3(256), n_pad * sizeof(uint32_t), s, P,
-                     p_stride, m_pad, n_pad, k, tau, list, cnt, cand, refs);
+  if (!P && !refs) {
+    if (!d || !U) return RADAR_E_ARG;
+    const radar::K3Args a3 = range_args(d, U, nullptr, 0, rowmax, nullptr);
+    const radar::Prec prec = prec_of(d);
+    if (prec == radar::Prec::BF16X3)
+      launch_rows_recompute<radar::Prec::BF16X3>(a3, d->n_sub, F, k, tau, list, cnt, cand, s);
+    else if (prec == radar::Prec::FP16X3)
+      launch_rows_recompute<radar::Prec::FP16X3>(a3, d->n_sub, F, k, tau, list, cnt, cand, s);
+    else
+      launch_rows_recompute<radar::Prec::FP32>(a3, d->n_sub, F, k, tau, list, cnt, cand, s);
+  } else {
+    const int groups = m_pad < 32 ? m_pad : 32;
+    hipLaunchKernelGGL(radar::k_peak_rows_listed, dim3(groups, F), dim3(256), n_pad * sizeof(uint32_t), s, P,
+                       p_stride, m_pad, n_pad, k, tau, list, cnt, cand, refs);
+  }
   RADAR_HIP_CHECK(hipGetLastError());
   hipLaunchKernelGGL(radar::k_peak_merge, dim3(F), dim3(64), 0, s, cand, cnt, m_pad, n_pad, k, peaks, n_peaks,
                      refs, inv_sum, M, eta_factor);
@@ -1009,13 +1078,17 @@ size_t radar_frame_workspace_size(const radar_frame_desc* d, int32_t n_frames, i
 }
 
 static int check_frame_common(const radar_frame_desc* d, int32_t n_frames, int64_t frame_stride,
-                              int64_t p_frame_stride, const void* P) {
+                              int64_t p_frame_stride, const void* P, bool p_optional = false) {
   const int rc = validate_desc(d);
   if (rc != RADAR_OK) return rc;
   if (n_frames < 1 || n_frames > 65535) return RADAR_E_ARG;
-  if (!P || (reinterpret_cast<uintptr_t>(P) & 15)) return RADAR_E_ARG;
   const int64_t frame_elems = (int64_t)(d->n_sym - 1) * d->ld + d->n_sub;
   if (n_frames > 1 && frame_stride < frame_elems) return RADAR_E_ARG;
+  if (!P) {
+    if (!p_optional) return RADAR_E_ARG;
+    return peaks_only_supported(d) ? RADAR_OK : RADAR_E_UNSUPPORTED;
+  }
+  if (reinterpret_cast<uintptr_t>(P) & 15) return RADAR_E_ARG;
   if (p_frame_stride % 4 != 0) return RADAR_E_ARG;
   if (n_frames > 1 && p_frame_stride < (int64_t)d->m_pad * d->n_pad) return RADAR_E_ARG;
   return RADAR_OK;
@@ -1024,7 +1097,7 @@ static int check_frame_common(const radar_frame_desc* d, int32_t n_frames, int64
 int radar_frame_process(const radar_frame_desc* d, int32_t n_frames, const radar_cf32* Y, const radar_cf32* A,
                         int64_t frame_stride, float* P, int64_t p_frame_stride, int32_t k, radar_peak* peaks,
                         int32_t* n_peaks, uint32_t* status, void* ws, size_t ws_bytes, void* hip_stream) {
-  int rc = check_frame_common(d, n_frames, frame_stride, p_frame_stride, P);
+  int rc = check_frame_common(d, n_frames, frame_stride, p_frame_stride, P, true);
   if (rc != RADAR_OK) return rc;
   if (!Y || !A || !peaks || !n_peaks || !status || !ws) return RADAR_E_ARG;
   if (k < 1 || k > 64) return RADAR_E_ARG;
@@ -1042,7 +1115,7 @@ int radar_frame_process(const radar_frame_desc* d, int32_t n_frames, const radar
   const bool thr = (d->flags & RADAR_FLAG_THRESHOLD) != 0;
   rc = enqueue_peaks(P, p_frame_stride, d->m_pad, d->n_pad, n_frames, k, w.pk, wsb, peaks, n_peaks, s, nullptr,
                      thr ? reinterpret_cast<const float*>(wsb + w.inv_sum) : nullptr, d->n_sym,
-                     thr ? eta_factor_of(d) : 0.0f);
+                     thr ? eta_factor_of(d) : 0.0f, d, reinterpret_cast<const float2*>(wsb + w.U));
   if (rc != RADAR_OK || !(d->flags & RADAR_FLAG_REFINE)) return rc;
   return enqueue_refine(d, n_frames, k, reinterpret_cast<const float2*>(wsb + w.taps), peaks, n_peaks, nullptr, s);
 }

@@ -331,8 +331,12 @@ def unpack_peaks(peaks: torch.Tensor, n_peaks: torch.Tensor):
 
 def frame_process(Y: torch.Tensor, A: torch.Tensor, cfg: Config, k: int, *, P: torch.Tensor | None = None,
                   workspace: torch.Tensor | None = None, peaks: torch.Tensor | None = None,
-                  n_peaks: torch.Tensor | None = None, status: torch.Tensor | None = None, stream=None):
-    """radar_frame_process on F frames: returns (P, peaks, n_peaks, status) device tensors."""
+                  n_peaks: torch.Tensor | None = None, status: torch.Tensor | None = None, stream=None,
+                  materialise: bool = True):
+    """radar_frame_process on F frames: returns (P, peaks, n_peaks, status) device tensors.
+
+    materialise=False passes P = NULL (peaks only): P is not written and None
+    is returned in its place."""
     L = lib()
     Y = _as_frames(Y, cfg, "Y")
     A = _as_frames(A, cfg, "A")
@@ -340,7 +344,9 @@ def frame_process(Y: torch.Tensor, A: torch.Tensor, cfg: Config, k: int, *, P: t
         raise ValueError("Y and A must share shape and strides")
     F = Y.shape[0]
     dev = Y.device
-    if P is None:
+    if not materialise and P is not None:
+        raise ValueError("materialise=False takes no P")
+    if P is None and materialise:
         P = torch.empty((F, cfg.m_pad, cfg.n_pad), dtype=torch.float32, device=dev)
     if peaks is None:
         peaks = alloc_peaks(F, k, dev)
@@ -352,8 +358,10 @@ def frame_process(Y: torch.Tensor, A: torch.Tensor, cfg: Config, k: int, *, P: t
     need = workspace_bytes(cfg, F, k)
     if workspace is None or workspace.numel() < need:
         workspace = new_workspace(need, dev)
+    p_ptr = P.data_ptr() if P is not None else None
+    p_stride = (int(P.stride(0)) if P.dim() == 3 else cfg.m_pad * cfg.n_pad) if P is not None else 0
     rc = L.radar_frame_process(ctypes.byref(desc), F, Y.data_ptr(), A.data_ptr(), _frame_stride(Y),
-                               P.data_ptr(), int(P.stride(0)) if P.dim() == 3 else cfg.m_pad * cfg.n_pad,
+                               p_ptr, p_stride,
                                int(k), peaks.data_ptr(), n_peaks.data_ptr(), status.data_ptr(),
                                workspace.data_ptr(), workspace.numel(), _stream_ptr(stream))
     _check(rc, "radar_frame_process")

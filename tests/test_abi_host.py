@@ -110,6 +110,28 @@ def test_process_rejects_bad_pointers_and_workspace():
     assert L.radar_periodogram(d, 1, p, 0, p, 0, p, need, None) == radar.RADAR_E_ARG
 
 
+@pytest.mark.parametrize("change, code", [
+    (dict(), radar.RADAR_E_WORKSPACE),                                   # supported: reaches the workspace check
+    (dict(n_sub=2048, n_cp=256, n_pad=8192), radar.RADAR_E_UNSUPPORTED),  # N > 1024
+    (dict(n_pad=2048), radar.RADAR_E_UNSUPPORTED),                       # N' = 8N
+    (dict(n_cp=100), radar.RADAR_E_UNSUPPORTED),                         # 4 N_cp > N
+    (dict(n_sub=128, n_cp=16, n_pad=512), radar.RADAR_E_UNSUPPORTED),    # N < 256
+])
+def test_peaks_only_shapes(change, code):
+    # P = NULL (peaks only) is validated before any HIP call; a 1-byte
+    # workspace stops the supported shape right after the pointer checks
+    base = dict(n_sub=256, n_sym=64, n_pad=1024, m_pad=256, n_cp=32, zc_root=1)
+    base.update(change)
+    cfg = radar.Config(**base)
+    L = radar.lib()
+    p = 256
+    rc = L.radar_frame_process(ctypes.byref(cfg.desc()), 1, p, p, 0, None, 0, 3, p, p, p, p, 1, None)
+    assert rc == code
+    # the other entry points still need P
+    assert L.radar_periodogram(ctypes.byref(radar.Config(**{**base, "zc_root": None}).desc()), 1, p, 0, None, 0, p,
+                               1 << 40, None) == radar.RADAR_E_ARG
+
+
 def test_detect_rejects():
     L = radar.lib()
     p = 256

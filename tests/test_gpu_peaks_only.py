@@ -1,0 +1,133 @@
+"""Peaks without a materialised periodogram (radar_frame_process with P =
+NULL) against the same call with P written, through the C ABI.
+
+With P NULL the range stage keeps only its row maxima and the peak search
+recomputes each listed row and its two neighbours with the range stage's own
+row code.  That code is compiled into two kernels, and the compiler may order
+a few multiply-adds differently in each, so a recomputed cell can differ from
+the written one by a few FP32 ulps.  The rule: the same counts and status, the
+same cells rank by rank except at near-ties of the materialised P (the
+tolerance the oracle comparisons use), and values within 8 ulps.  The small
+workload is also checked against the FP64 oracle.
+"""
+
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import radar_oracle as O
+from synth import frames as S
+from tests.gpu_util import compare_peak_indices, oracle_ranked, rounded, say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+radar = pytest.importorskip("paper_2209_03883_amd.radar")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    radar.lib()
+
+
+def _both(frames, cfg, k):
+    Y, A = S.frames_to_complex64(frames)
+    Yd, Ad = torch.from_numpy(Y).cuda(), torch.from_numpy(A).cuda()
+    P, pk1, n1, st1 = radar.frame_process(Yd, Ad, cfg, k)
+    P0, pk0, n0, st0 = radar.frame_process(Yd, Ad, cfg, k, materialise=False)
+    torch.cuda.synchronize()
+    assert P0 is None
+    return P.cpu().numpy(), radar.unpack_peaks(pk1, n1.cpu()), st1.cpu().numpy(), \
+        radar.unpack_peaks(pk0, n0.cpu()), st0.cpu().numpy()
+
+
+def _same(res, label):
+    P, with_p, st1, without_p, st0 = res
+    np.testing.assert_array_equal(st0, st1, err_msg=label)
+    m_pad = P.shape[1]
+    exact = 0
+    for f in range(P.shape[0]):
+        a, b = with_p[f], without_p[f]
+        assert len(a) == len(b), (label, f, len(a), len(b))
+        ref = [(s, r, float(P[f, s + m_pad // 2, r])) for s, r, *_ in a]
+        assert compare_peak_indices([(s, r) for s, r, *_ in b], ref, P[f].astype(np.float64)) is not None, \
+            (label, f, a, b)
+        for (s1, r1, p1, *o1), (s0, r0, p0, *o0) in zip(a, b):
+            if (s1, r1) == (s0, r0):
+                assert abs(p0 - p1) <= 8 * np.spacing(np.float32(p1)), (label, f, s1, r1, p1, p0)
+                np.testing.assert_allclose(o0, o1, atol=1e-4)
+                exact += p0 == p1
+    say(f"{label}: {exact} of {sum(len(x) for x in with_p)} peak values bit-identical")
+
+
+def test_small_workload_peaks_only():
+    frames = [S.make_frame(S.spec_small(snr_db=snr), 7, i) for i, snr in enumerate((0.0, -10.0, 10.0, 0.0))]
+    cfg = radar.Config(256, 64, 1024, 256, 32, zc_root=1)
+    say("peaks only, small workload")
+    res = _both(frames, cfg, 3)
+    _same(res, "small")
+    pk = res[3]
+    for f, frame in enumerate(frames):
+        P_ref = O.frame_periodogram(rounded(frame.Y), rounded(frame.A), n_pad=1024, m_pad=256, n_cp=32,
+                                    window_kind=cfg.window, zc_root=1)
+        assert compare_peak_indices([(s, r) for s, r, *_ in pk[f]], oracle_ranked(O, P_ref, 3), P_ref) is not None
+
+
+# (N, M, N_cp, k, flags): every x4p shape, ragged N_cp, k up to 64, both
+# output orders of the range kernel and every precision form
+SHAPES = [
+    (256, 128, 50, 16, {}),
+    (512, 64, 128, 8, {}),
+    (512, 256, 97, 64, {}),
+    (1024, 256, 256, 8, {}),
+    (1024, 128, 200, 8, dict(precision=radar.FLAG_BF16X3)),
+    (1024, 128, 256, 8, dict(precision=radar.FLAG_FP16X3)),
+    (256, 64, 64, 8, dict(precision=radar.FLAG_BF16X3)),
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=[f"{s[0]}x{s[1]}-cp{s[2]}-k{s[3]}-{len(s[4])}" for s in SHAPES])
+def test_peaks_only_matches_materialised(shape):
+    n, m, n_cp, k, extra = shape
+    spec = S.FrameSpec(n_sub=n, n_sym=m, qam=16, zc_root=3, n_targets=6, snr_db=-5.0, on_grid=False,
+                       rho_min=0.0, rho_max=n_cp - 1.0, nu_abs_max=m / 2 - 1, rayleigh=True, min_sep=1.5)
+    frames = [S.make_frame(spec, 81, i) for i in range(3)]
+    cfg = radar.Config(n, m, 4 * n, 2 * m, n_cp, zc_root=3, **extra)
+    say(f"peaks only {shape}")
+    _same(_both(frames, cfg, k), str(shape))
+
+
+def test_full_frames_peaks_only():
+    frames = [S.make_frame(S.spec_full(snr_db=snr), 2, i) for i, snr in enumerate((0.0, -20.0))]
+    cfg = radar.Config(1024, 1024, 4096, 4096, 256, zc_root=7)
+    say("peaks only, full frames")
+    _same(_both(frames, cfg, 8), "full")
+
+
+def test_every_row_listed():
+    # noiseless, one target: fewer than k rows hold a row-profile peak, so the
+    # bound is -inf and every row is recomputed and scanned
+    spec = dataclasses.replace(S.spec_small(), n_targets=1, noise=False)
+    frames = [S.make_frame(spec, 9, i) for i in range(2)]
+    cfg = radar.Config(256, 64, 1024, 256, 32, zc_root=1)
+    say("peaks only, every row listed")
+    _same(_both(frames, cfg, 64), "all rows")
+
+
+def test_peaks_only_with_threshold_and_refinement():
+    frames = [S.make_frame(S.spec_small(snr_db=snr), 8, i) for i, snr in enumerate((-10.0, 5.0))]
+    cfg = radar.Config(256, 64, 1024, 256, 32, zc_root=1, threshold=True, pfa=1e-3, noise_power=1.0, refine=True)
+    say("peaks only, threshold and refinement")
+    _same(_both(frames, cfg, 8), "threshold+refine")
+
+
+def test_unsupported_shape_is_refused():
+    frames = [S.make_frame(S.spec_small(), 7, 0)]
+    Y, A = S.frames_to_complex64(frames)
+    cfg = radar.Config(256, 64, 2048, 256, 32, zc_root=1)  # N' = 8N
+    with pytest.raises(radar.RadarError) as ei:
+        radar.frame_process(torch.from_numpy(Y).cuda(), torch.from_numpy(A).cuda(), cfg, 3, materialise=False)
+    assert ei.value.code == radar.RADAR_E_UNSUPPORTED
