@@ -70,9 +70,12 @@ __global__ void __launch_bounds__(256) k_peak_rows_recompute(K3Args a, int k, co
     const int row = list[(int64_t)f * a.m_pad + j];
     if (computes) {
       const int rr = (row + (g < 3 ? g - 1 : 0)) & mask;
-      const float2* in = a.U + ((int64_t)f * a.m_pad + rr) * a.n_cp;
+      float2 uv[4];
+      k3p_load_taps<N>(uv, a.U + ((int64_t)f * a.m_pad + rr) * a.n_cp, a.n_cp, t);
+      k3p_put_taps<N>(ub, uv, a.n_cp, t);
+      k3p_zero_pads<N>(ub, t);
       const RowToLds sink{g < 3 ? rows + g * NP : nullptr};
-      (void)k3p_row<N, PR>(in, a.n_cp, lds, ub, t, tab, cf.x, cf.y, df, sink);
+      (void)k3p_row<N, PR>(lds, ub, t, tab, cf.x, cf.y, df, sink, [] {});
     }
     __syncthreads();  // the rows are complete; the exchange regions are free for the marks
     row_candidates(static_cast<const float*>(rows), static_cast<const float*>(rows + NP),

@@ -239,7 +239,13 @@ void launch_k3x4p_n(const radar::K3Args& a, int m_pad, int F, hipStream_t s) {
   const int per_wg = C::WAVES;
   int grid = (g_num_cus > 0 ? g_num_cus : 256) * g_tune.k3_mult;
   if (grid * per_wg > total) grid = (total + per_wg - 1) / per_wg;
-  hipLaunchKernelGGL((radar::k3_range_power_x4p<N, PR, kStore>), dim3(grid), dim3(C::BLOCK), 0, s, a, total);
+  if constexpr (kStore) {
+    if (a.refs) {
+      hipLaunchKernelGGL((radar::k3_range_power_x4p<N, PR, true, true>), dim3(grid), dim3(C::BLOCK), 0, s, a, total);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((radar::k3_range_power_x4p<N, PR, kStore, false>), dim3(grid), dim3(C::BLOCK), 0, s, a, total);
 }
 template <int N>
 void launch_k3_n(const radar::K3Args& a, int f2, int m_pad, int F, hipStream_t s) {
