@@ -627,17 +627,18 @@ __device__ __forceinline__ float2 phase0_filter(const float2* ub, int r1, float 
 
 // Where one range row of P goes: cell i (in r = 4 r1 + b order) and the
 // next one, two or four cells.  P is written once and read back only in the
-// few rows the peak search scans, so its stores are non-temporal: they do
-// not displace the taps and Doppler rows from the caches (measured: the
-// range stage 1.5 % faster, the taps and peak stages a few per cent).
+// few rows the peak search scans, so the whole 16-byte groups are stored
+// non-temporally: they do not displace the taps and Doppler rows from the
+// caches (measured: the range stage 1.5 % faster, the taps and peak stages a
+// few per cent).  The 8-byte halves of the two-store order stay ordinary
+// stores, which the caches combine into whole lines: streamed past them, the
+// halves written at different times made the BF16x3 range stage 1.8x slower.
 struct RowToGlobal {
   RADAR_GLOBAL float* dst;
   __device__ __forceinline__ void store4(int i, float a, float b, float c, float d) const {
     __builtin_nontemporal_store(radar_v4{a, b, c, d}, (RADAR_GLOBAL radar_v4*)(dst + i));
   }
-  __device__ __forceinline__ void store2(int i, float a, float b) const {
-    __builtin_nontemporal_store(radar_v2{a, b}, (RADAR_GLOBAL radar_v2*)(dst + i));
-  }
+  __device__ __forceinline__ void store2(int i, float a, float b) const { gstore2(dst + i, a, b); }
 };
 // Nowhere: only the row maximum is kept (P not materialised).
 struct RowToNowhere {
