@@ -294,7 +294,13 @@ void launch_k3x4p_rowmax(const radar::K3Args& a, int N, int m_pad, int F, hipStr
 template <radar::Prec PR>
 void launch_rows_recompute(const radar::K3Args& a, int N, int F, int k, const float* tau, const int32_t* list,
                            const int32_t* cnt, uint64_t* cand, hipStream_t s) {
-  const int groups = a.m_pad < 64 ? a.m_pad : 64;
+  // one work-group per CU in all (each holds a CU's LDS), each looping over
+  // list entries of its frame, so its twiddle tables are built once per many
+  // rows rather than once per row
+  const int cus = g_num_cus > 0 ? g_num_cus : 256;
+  int groups = (cus + F - 1) / F;
+  if (groups > 64) groups = 64;
+  if (groups > a.m_pad) groups = a.m_pad;
   switch (N) {
     case 256:
       hipLaunchKernelGGL((radar::k_peak_rows_recompute<256, PR>), dim3(groups, F), dim3(256), 0, s, a, k, tau, list,
