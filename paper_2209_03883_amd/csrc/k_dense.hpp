@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(kDenseThreads) k_dense_ls(DenseArgs a) {
 #pragma unroll
     for (int it = 0; it < NT; ++it) {
       const int j = tid + it * T;
-      if (j >= N) break;
+      if (j >= N) continue;  // only when N < the work-group size
       float2 av;
       if constexpr (kPre) av = xa[it];
       else av = x[j];
@@ -176,7 +176,7 @@ __global__ void __launch_bounds__(kDenseThreads) k_dense_ls(DenseArgs a) {
 #pragma unroll
     for (int it = 0; it < NT; ++it) {
       const int i = tid + it * T;
-      if (i >= N) break;
+      if (i >= N) continue;
       const uint32_t ui = (uint32_t)i;
       const double2 xv = s_d[(a.zc_root * ui) & (uint32_t)(N - 1)];
       // D1(i) = exp(+i pi r i^2) exp(+2 pi i rqi/N) = (-1)^i W^{rqi} for odd r

@@ -148,11 +148,11 @@ int g_num_cus = 0;  // compute units of the device, set by radar_init
 int timer_open(int stage, hipStream_t s) {
   if (g_capturing || !g_timer.on || g_timer.used[stage] >= g_timer.cap) return -1;
   const int slot = g_timer.used[stage]++;
-  hipEventRecord(g_timer.ev[stage][2 * slot], s);
+  (void)hipEventRecord(g_timer.ev[stage][2 * slot], s);
   return slot;
 }
 void timer_close(int stage, int slot, hipStream_t s) {
-  if (slot >= 0) hipEventRecord(g_timer.ev[stage][2 * slot + 1], s);
+  if (slot >= 0) (void)hipEventRecord(g_timer.ev[stage][2 * slot + 1], s);
 }
 
 #define RADAR_HIP_CHECK(expr)                  \
@@ -871,19 +871,19 @@ int tune_group(radar_batch& b, BatchGroup& g, hipStream_t s) {
       g.tune = t;
       int rc = enqueue_group(b, g, s);  // warm-up
       if (rc != RADAR_OK) return rc;
-      hipEventRecord(e0, s);
+      (void)hipEventRecord(e0, s);
       for (int r = 0; r < 3 && rc == RADAR_OK; ++r) rc = enqueue_group(b, g, s);
-      hipEventRecord(e1, s);
+      (void)hipEventRecord(e1, s);
       if (rc != RADAR_OK || hipEventSynchronize(e1) != hipSuccess) return RADAR_E_HIP;
       float ms = 0.0f;
-      hipEventElapsedTime(&ms, e0, e1);
+      (void)hipEventElapsedTime(&ms, e0, e1);
       if (ms < best) {
         best = ms;
         pick = t;
       }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     g.tune = pick;
   }
   std::lock_guard<std::mutex> lock(g_tune_mu);
@@ -1347,10 +1347,10 @@ int radar_batch_create(const radar_frame_job* jobs, int32_t n_jobs, int32_t flag
       if (rc == RADAR_OK && hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0) != hipSuccess)
         rc = RADAR_E_HIP;
       for (auto e : ev)
-        if (e) hipEventDestroy(e);
+        if (e) (void)hipEventDestroy(e);
       for (auto st : br)
-        if (st) hipStreamDestroy(st);
-      hipStreamDestroy(cs);
+        if (st) (void)hipStreamDestroy(st);
+      (void)hipStreamDestroy(cs);
     }
   }
   if (rc != RADAR_OK) {
@@ -1387,8 +1387,8 @@ int radar_batch_info(const radar_batch* b, int32_t g, int32_t* n_groups, int32_t
 
 void radar_batch_destroy(radar_batch* b) {
   if (!b) return;
-  if (b->exec) hipGraphExecDestroy(b->exec);
-  if (b->graph) hipGraphDestroy(b->graph);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
   delete b;
 }
 
@@ -1489,7 +1489,7 @@ int radar_timing_stop(double* ms_total, int64_t* launches) {
     if (ms_total) ms_total[st] = tot;
     if (launches) launches[st] = g_timer.used[st];
     for (auto& e : g_timer.ev[st])
-      if (e) hipEventDestroy(e);
+      if (e) (void)hipEventDestroy(e);
     g_timer.ev[st].clear();
     g_timer.used[st] = 0;
   }
