@@ -866,7 +866,11 @@ __global__ void __launch_bounds__(K3p<N>::BLOCK) k3_range_power_x4p(K3Args a, in
     };
     float mx;
     if constexpr (kStore) {
-      const RowToGlobal sink{gptr(kRefs ? a.refs[f].P : a.P + (int64_t)f * a.p_stride) + (int64_t)row * (4 * N)};
+      // the job table is read-only for the whole launch: read through the
+      // constant address space, a wave-uniform entry comes by a scalar load,
+      // which the vector-memory waits do not count
+      const auto* crefs = (const __attribute__((address_space(4))) FrameRef*)a.refs;
+      const RowToGlobal sink{gptr(kRefs ? crefs[f].P : a.P + (int64_t)f * a.p_stride) + (int64_t)row * (4 * N)};
       mx = k3p_row<N, PR>(lds, ub, t, tab, cf.x, cf.y, df, sink, next);
     } else {
       mx = k3p_row<N, PR>(lds, ub, t, tab, cf.x, cf.y, df, RowToNowhere{}, next);
