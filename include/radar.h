@@ -315,8 +315,11 @@ int radar_fps_sft(const radar_frame_desc *d, const radar_sft_desc *s, int32_t n_
  *     plus every group's own scratch: the captured graph runs groups on up
  *     to four concurrent branches, heaviest groups first onto the least
  *     loaded branch).
+ * Every job writes its periodogram: P must not be NULL here (the peaks-only
+ * mode is radar_frame_process's).
  * Errors: as radar_frame_process per job (validation before any HIP call),
- * RADAR_E_ARG for n_jobs < 1, unknown batch flags or a NULL plan pointer,
+ * RADAR_E_ARG for n_jobs < 1, a NULL P, unknown batch flags or a NULL plan
+ * pointer,
  * RADAR_E_HIP if a HIP call (upload, capture, instantiation) fails.
  * ------------------------------------------------------------------------ */
 typedef struct {
