@@ -37,7 +37,7 @@ EXPORTED = (
     "radar_batch_destroy",
     "radar_cnn_param_count", "radar_cnn_workspace_size", "radar_cnn_patches", "radar_cnn_forward",
     "radar_cnn_gradient", "radar_cnn_adam", "radar_cnn_train_step", "radar_tap_wiener_weights",
-    "radar_simulate_frames", "radar_papr", "radar_hpa",
+    "radar_simulate_frames", "radar_papr", "radar_hpa"
 )
 BATCH_GRAPH, BATCH_TUNE = 1, 2
 STAGES = ("taps", "doppler", "range", "peaks", "refine", "sft_slices", "sft_decode")
@@ -329,6 +329,52 @@ def unpack_peaks(peaks: torch.Tensor, n_peaks: torch.Tensor):
     return out
 
 
+def _check_device_buffer(x: torch.Tensor, name: str, dtype, min_elems: int, device):
+    if not isinstance(x, torch.Tensor) or not x.is_cuda or x.device != device:
+        raise TypeError(f"{name} must be a CUDA tensor on {device}")
+    if x.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if x.numel() < min_elems:
+        raise ValueError(f"{name} holds {x.numel()} elements, needs at least {min_elems}")
+
+
+def _check_P(P: torch.Tensor, cfg: Config, F: int, device) -> int:
+    """P's frame stride in floats, after checking dtype, device, shape and row layout."""
+    if not isinstance(P, torch.Tensor) or not P.is_cuda or P.device != device or P.dtype != torch.float32:
+        raise TypeError(f"P must be a float32 CUDA tensor on {device}")
+    shape = tuple(P.shape)
+    if shape == (F, cfg.m_pad, cfg.n_pad):
+        if P.stride(2) != 1 or P.stride(1) != cfg.n_pad:
+            raise ValueError("P must have contiguous rows of N' floats")
+        return int(P.stride(0))
+    if F == 1 and shape == (cfg.m_pad, cfg.n_pad):
+        if not P.is_contiguous():
+            raise ValueError("P must be contiguous")
+        return cfg.m_pad * cfg.n_pad
+    raise ValueError(f"P must have shape ({F}, {cfg.m_pad}, {cfg.n_pad})")
+
+
+def _frame_outputs(F: int, k: int, cfg: Config, dev, P, peaks, n_peaks, status, materialise: bool):
+    """Allocates the outputs not given and checks those given; returns them and P's frame stride."""
+    if not materialise and P is not None:
+        raise ValueError("materialise=False takes no P")
+    if P is None and materialise:
+        P = torch.empty((F, cfg.m_pad, cfg.n_pad), dtype=torch.float32, device=dev)
+    p_stride = _check_P(P, cfg, F, dev) if P is not None else 0
+    if peaks is None:
+        peaks = alloc_peaks(F, k, dev)
+    _check_device_buffer(peaks, "peaks", torch.int32, F * k * PEAK_WORDS, dev)
+    if n_peaks is None:
+        n_peaks = torch.zeros(F, dtype=torch.int32, device=dev)
+    _check_device_buffer(n_peaks, "n_peaks", torch.int32, F, dev)
+    if status is None:
+        status = torch.zeros(F, dtype=torch.int32, device=dev)
+    _check_device_buffer(status, "status", torch.int32, F, dev)
+    return P, p_stride, peaks, n_peaks, status
+
+
 def frame_process(Y: torch.Tensor, A: torch.Tensor, cfg: Config, k: int, *, P: torch.Tensor | None = None,
                   workspace: torch.Tensor | None = None, peaks: torch.Tensor | None = None,
                   n_peaks: torch.Tensor | None = None, status: torch.Tensor | None = None, stream=None,
@@ -344,22 +390,15 @@ def frame_process(Y: torch.Tensor, A: torch.Tensor, cfg: Config, k: int, *, P: t
         raise ValueError("Y and A must share shape and strides")
     F = Y.shape[0]
     dev = Y.device
-    if not materialise and P is not None:
-        raise ValueError("materialise=False takes no P")
-    if P is None and materialise:
-        P = torch.empty((F, cfg.m_pad, cfg.n_pad), dtype=torch.float32, device=dev)
-    if peaks is None:
-        peaks = alloc_peaks(F, k, dev)
-    if n_peaks is None:
-        n_peaks = torch.zeros(F, dtype=torch.int32, device=dev)
-    if status is None:
-        status = torch.zeros(F, dtype=torch.int32, device=dev)
+    if Y.device != A.device:
+        raise ValueError("Y and A must be on one device")
+    P, p_stride, peaks, n_peaks, status = _frame_outputs(F, k, cfg, dev, P, peaks, n_peaks, status, materialise)
     desc = cfg.desc(ld=Y.stride(1))
     need = workspace_bytes(cfg, F, k)
     if workspace is None or workspace.numel() < need:
         workspace = new_workspace(need, dev)
+    _check_device_buffer(workspace, "workspace", torch.uint8, need, dev)
     p_ptr = P.data_ptr() if P is not None else None
-    p_stride = (int(P.stride(0)) if P.dim() == 3 else cfg.m_pad * cfg.n_pad) if P is not None else 0
     rc = L.radar_frame_process(ctypes.byref(desc), F, Y.data_ptr(), A.data_ptr(), _frame_stride(Y),
                                p_ptr, p_stride,
                                int(k), peaks.data_ptr(), n_peaks.data_ptr(), status.data_ptr(),
