@@ -185,6 +185,34 @@ int radar_frame_process(const radar_frame_desc *d, int32_t n_frames,
                         void *ws, size_t ws_bytes, void *hip_stream);
 
 /* ------------------------------------------------------------------------
+ * radar_frame_process_noalloc -- radar_frame_process for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the same path, the same arguments and
+ * results, minus the caller's workspace.
+ *
+ * The workspace is instead a library-owned device array of
+ * RADAR_NOALLOC_WS_BYTES bytes, one per device, allocated when the library's
+ * code is loaded on that device and held until the process ends; its address
+ * is looked up once per device by radar_init.  Nothing is allocated or freed
+ * by the call (no hipMalloc, no hipFree, no allocating library routine).
+ * Limit: radar_frame_workspace_size(d, n_frames, k) must not exceed
+ * RADAR_NOALLOC_WS_BYTES (one 1024 x 1024 frame with k = 8 needs about
+ * 10.3 MiB, so up to three such frames per call); larger requests return
+ * RADAR_E_WORKSPACE and enqueue nothing.
+ * Every call on one device uses that device's one array, which keeps the
+ * last call's contents: calls that overlap in time on one device (other
+ * streams, other threads) race and give undefined results.  Successive calls
+ * on one stream are fine; nothing in the array needs to start cleared.
+ * Call radar_init once outside capture before capturing this call.
+ * ------------------------------------------------------------------------ */
+#define RADAR_NOALLOC_WS_BYTES (32u << 20)
+int radar_frame_process_noalloc(const radar_frame_desc *d, int32_t n_frames,
+                                const radar_cf32 *Y, const radar_cf32 *A, int64_t frame_stride,
+                                float *P, int64_t p_frame_stride,
+                                int32_t k, radar_peak *peaks, int32_t *n_peaks, uint32_t *status,
+                                void *hip_stream);
+
+/* ------------------------------------------------------------------------
  * radar_tap_wiener_weights -- per-tap LMMSE weights of the LMMSE-based DFT-CE
  * (Sec. III-A, Fig. 5), host only, no GPU call.
  *

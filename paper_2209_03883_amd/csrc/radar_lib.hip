@@ -28,11 +28,19 @@ __device__ float2 g_radar_tw[RADAR_TW_ENTRIES];
 __device__ double2 g_root64_hi[1 << (RADAR_ROOT64_LOG2 - 12)];
 __device__ double2 g_root64_lo[1 << 12];
 
+// The workspace of radar_frame_process_noalloc: one array per device, held
+// until the process ends.  Host code never uses this name as an address (in
+// host code it is a stand-in for the symbol, not device memory): radar_init
+// looks up each device's copy with hipGetSymbolAddress and keeps it in
+// g_scratch_dev.
+static __device__ __align__(256) unsigned char scratch[RADAR_NOALLOC_WS_BYTES];
+
 namespace {
 
 constexpr int kMaxDevices = 64;
 std::mutex g_init_mu;
 bool g_init_done[kMaxDevices];
+void* g_scratch_dev[kMaxDevices];  // device address of `scratch` on each device, set by radar_init
 
 bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 int ilog2(int64_t x) {
@@ -977,6 +985,10 @@ int radar_init(void) {
       hipMemcpyToSymbol(HIP_SYMBOL(g_root64_lo), r_lo.data(), r_lo.size() * sizeof(double2), 0,
                         hipMemcpyHostToDevice) != hipSuccess)
     return RADAR_E_HIP;
+  // this device's copy of the allocation-free entry point's workspace
+  void* sp = nullptr;
+  if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) != hipSuccess || sp == nullptr) return RADAR_E_HIP;
+  g_scratch_dev[dev] = sp;
   // the peak threshold kernel holds two words per row of the largest M' in LDS
   if (hipFuncSetAttribute(reinterpret_cast<const void*>(radar::k_peak_threshold),
                           hipFuncAttributeMaxDynamicSharedMemorySize, 2 * 16384 * (int)sizeof(uint32_t)) !=
@@ -1130,6 +1142,25 @@ int radar_frame_process(const radar_frame_desc* d, int32_t n_frames, const radar
                      thr ? eta_factor_of(d) : 0.0f, d, reinterpret_cast<const float2*>(wsb + w.U));
   if (rc != RADAR_OK || !(d->flags & RADAR_FLAG_REFINE)) return rc;
   return enqueue_refine(d, n_frames, k, reinterpret_cast<const float2*>(wsb + w.taps), peaks, n_peaks, nullptr, s);
+}
+
+int radar_frame_process_noalloc(const radar_frame_desc* d, int32_t n_frames, const radar_cf32* Y,
+                                const radar_cf32* A, int64_t frame_stride, float* P, int64_t p_frame_stride,
+                                int32_t k, radar_peak* peaks, int32_t* n_peaks, uint32_t* status,
+                                void* hip_stream) {
+  int rc = check_frame_common(d, n_frames, frame_stride, p_frame_stride, P, true);
+  if (rc != RADAR_OK) return rc;
+  if (k < 1 || k > 64) return RADAR_E_ARG;
+  const size_t need = frame_ws_layout(d, n_frames, k).total;
+  if (need > (size_t)RADAR_NOALLOC_WS_BYTES) return RADAR_E_WORKSPACE;
+  if ((rc = ensure_init()) != RADAR_OK) return rc;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return RADAR_E_HIP;
+  // ensure_init has run on this device, so its scratch address is known; the
+  // path clears what it needs itself (status and peak counts by a fill
+  // kernel, every workspace word is written before it is read)
+  return radar_frame_process(d, n_frames, Y, A, frame_stride, P, p_frame_stride, k, peaks, n_peaks, status,
+                             g_scratch_dev[dev], need, hip_stream);
 }
 
 int radar_periodogram(const radar_frame_desc* d, int32_t n_frames, const radar_cf32* H, int64_t frame_stride,

@@ -37,7 +37,7 @@ EXPORTED = (
     "radar_batch_destroy",
     "radar_cnn_param_count", "radar_cnn_workspace_size", "radar_cnn_patches", "radar_cnn_forward",
     "radar_cnn_gradient", "radar_cnn_adam", "radar_cnn_train_step", "radar_tap_wiener_weights",
-    "radar_simulate_frames", "radar_papr", "radar_hpa"
+    "radar_simulate_frames", "radar_papr", "radar_hpa", "radar_frame_process_noalloc",
 )
 BATCH_GRAPH, BATCH_TUNE = 1, 2
 STAGES = ("taps", "doppler", "range", "peaks", "refine", "sft_slices", "sft_decode")
@@ -108,6 +108,8 @@ def lib() -> ctypes.CDLL:
     L.radar_frame_workspace_size.argtypes = [dp, i32, i32]
     L.radar_frame_process.restype = ctypes.c_int
     L.radar_frame_process.argtypes = [dp, i32, vp, vp, i64, vp, i64, i32, vp, vp, vp, vp, sz, vp]
+    L.radar_frame_process_noalloc.restype = ctypes.c_int
+    L.radar_frame_process_noalloc.argtypes = [dp, i32, vp, vp, i64, vp, i64, i32, vp, vp, vp, vp]
     L.radar_periodogram.restype = ctypes.c_int
     L.radar_periodogram.argtypes = [dp, i32, vp, i64, vp, i64, vp, sz, vp]
     L.radar_detect_workspace_size.restype = sz
@@ -404,6 +406,30 @@ def frame_process(Y: torch.Tensor, A: torch.Tensor, cfg: Config, k: int, *, P: t
                                int(k), peaks.data_ptr(), n_peaks.data_ptr(), status.data_ptr(),
                                workspace.data_ptr(), workspace.numel(), _stream_ptr(stream))
     _check(rc, "radar_frame_process")
+    return P, peaks, n_peaks, status
+
+
+def frame_process_noalloc(Y: torch.Tensor, A: torch.Tensor, cfg: Config, k: int, *, P: torch.Tensor,
+                          peaks: torch.Tensor, n_peaks: torch.Tensor, status: torch.Tensor, stream=None):
+    """radar_frame_process_noalloc: radar_frame_process with the library's own
+    per-device workspace (no caller workspace; nothing allocated, here or in
+    the library).  Every output is the caller's; P=None means peaks only."""
+    L = lib()
+    Y = _as_frames(Y, cfg, "Y")
+    A = _as_frames(A, cfg, "A")
+    if Y.stride() != A.stride() or Y.shape != A.shape or Y.device != A.device:
+        raise ValueError("Y and A must share shape, strides and device")
+    F = Y.shape[0]
+    for name, x in (("peaks", peaks), ("n_peaks", n_peaks), ("status", status)):
+        if x is None:
+            raise ValueError(f"{name} must be given")
+    P, p_stride, peaks, n_peaks, status = _frame_outputs(F, k, cfg, Y.device, P, peaks, n_peaks, status,
+                                                         P is not None)
+    desc = cfg.desc(ld=Y.stride(1))
+    rc = L.radar_frame_process_noalloc(ctypes.byref(desc), F, Y.data_ptr(), A.data_ptr(), _frame_stride(Y),
+                                       P.data_ptr() if P is not None else None, p_stride, int(k),
+                                       peaks.data_ptr(), n_peaks.data_ptr(), status.data_ptr(), _stream_ptr(stream))
+    _check(rc, "radar_frame_process_noalloc")
     return P, peaks, n_peaks, status
 
 

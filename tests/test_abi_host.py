@@ -110,6 +110,20 @@ def test_process_rejects_bad_pointers_and_workspace():
     assert L.radar_periodogram(d, 1, p, 0, p, 0, p, need, None) == radar.RADAR_E_ARG
 
 
+def test_noalloc_rejects_before_any_hip_call():
+    L = radar.lib()
+    cfg = radar.Config(1024, 1024, 4096, 4096, 256, zc_root=7)
+    d = ctypes.byref(cfg.desc())
+    p = 256
+    fs, ps = 1024 * 1024, 4096 * 4096
+    # four full frames need more than the library's own workspace
+    assert L.radar_frame_workspace_size(d, 4, 8) > (32 << 20) >= L.radar_frame_workspace_size(d, 3, 8)
+    assert L.radar_frame_process_noalloc(d, 4, p, p, fs, p, ps, 8, p, p, p, None) == radar.RADAR_E_WORKSPACE
+    assert L.radar_frame_process_noalloc(d, 1, p, p, 0, p, 0, 0, p, p, p, None) == radar.RADAR_E_ARG   # k = 0
+    assert L.radar_frame_process_noalloc(d, 1, p, p, 0, p + 4, 0, 8, p, p, p, None) == radar.RADAR_E_ARG  # P misaligned
+    assert L.radar_frame_process_noalloc(d, 0, p, p, 0, p, 0, 8, p, p, p, None) == radar.RADAR_E_ARG   # no frames
+
+
 @pytest.mark.parametrize("change, code", [
     (dict(), radar.RADAR_E_WORKSPACE),                                   # supported: reaches the workspace check
     (dict(n_sub=2048, n_cp=256, n_pad=8192), radar.RADAR_E_UNSUPPORTED),  # N > 1024
