@@ -99,3 +99,48 @@ def test_patch_input_definition():
     # cyclic: a corner cell wraps round both axes
     x0 = C.patch_input(P, 0, 0)
     assert x0[0, 0] == pytest.approx(np.log(max(P[-16, -16], 1e-12 * P[0, 0])) - np.log(P[0, 0]))
+
+
+def test_forward_composition_hand_worked():
+    """The network's composition (the layer order, the stride-2 sampling, the
+    NHWC flatten index (y * 8 + x) * 32 + c, ReLU after fc1 but not after fc2,
+    the biases) on hand-set weights that route single pixels through single
+    channels, against an output worked out by hand:
+
+      x[8][12] = 1.5, x[20][4] = -5, x[0][0] = 100 (routed nowhere)
+      conv1  ch0 = relu(x), ch1 = relu(-x)          (centre taps)
+      conv2  ch0 <- ch0, ch5 <- ch1                  (stride 2: reads row 2y, col 2x)
+      conv3  ch0 <- ch0, ch5 <- ch5, ch9 = bias 0.75 everywhere
+      conv4  ch0 <- ch0, ch7 <- ch5 (stride 2), ch9 = relu(2 * 0.75 - 0.5) = 1
+      so x[8][12] lands at conv4 (2, 3, ch0) = 1.5 and x[20][4] at (5, 1, ch7) = 5
+      flat   (2*8+3)*32+0 = 608,  (5*8+1)*32+7 = 1319,  (7*8+7)*32+9 = 2025
+      fc1    a0 = relu(2*1.5 + 0.5) = 3.5, a1 = relu(5 - 3) = 2, a2 = relu(-1) = 0,
+             a3 = relu(-1.5) = 0, a4 = relu(1) = 1
+      fc2    out0 = 3.5 + 3*2 + 10*0 + 7*0 + 0.125*1 + 0.25 = 9.875
+             out1 = -3.5 + 0.5*2 - 2 = -4.5  (no ReLU: stays negative)"""
+    p = {name: np.zeros(shape) for name, shape in C.param_shapes()}
+    p["conv1.w"][0, 1, 1, 0] = 1.0
+    p["conv1.w"][1, 1, 1, 0] = -1.0
+    p["conv2.w"][0, 1, 1, 0] = 1.0
+    p["conv2.w"][5, 1, 1, 1] = 1.0
+    p["conv3.w"][0, 1, 1, 0] = 1.0
+    p["conv3.w"][5, 1, 1, 5] = 1.0
+    p["conv3.b"][9] = 0.75
+    p["conv4.w"][0, 1, 1, 0] = 1.0
+    p["conv4.w"][7, 1, 1, 5] = 1.0
+    p["conv4.w"][9, 1, 1, 9] = 2.0
+    p["conv4.b"][9] = -0.5
+    p["fc1.w"][0, 608], p["fc1.b"][0] = 2.0, 0.5
+    p["fc1.w"][1, 1319], p["fc1.b"][1] = 1.0, -3.0
+    p["fc1.b"][2] = -1.0
+    p["fc1.w"][3, 608] = -1.0
+    p["fc1.w"][4, 2025] = 1.0
+    p["fc2.w"][0, :5] = [1.0, 3.0, 10.0, 7.0, 0.125]
+    p["fc2.b"][0] = 0.25
+    p["fc2.w"][1, :2] = [-1.0, 0.5]
+    p["fc2.b"][1] = -2.0
+    x = np.zeros((1, 32, 32))
+    x[0, 8, 12], x[0, 20, 4], x[0, 0, 0] = 1.5, -5.0, 100.0
+    out, cache = C.forward(p, x)
+    np.testing.assert_allclose(cache["fc1"][1][0, :5], [3.5, 2.0, 0.0, 0.0, 1.0], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(out[0], [9.875, -4.5], rtol=0, atol=1e-12)
