@@ -32,6 +32,11 @@ HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 256 * 2.4e9 * 128 * 2 / 1e12
 FP32_UNPACKED_PEAK_TFLOPS = FP32_VECTOR_PEAK_TFLOPS / 2
 N, M, PAD, NCP, ROOT_ZC, K = 1024, 1024, 4, 256, 7, 8
+# Table I: subcarrier spacing and carrier (Eq. 13-15, 19 units); the
+# workload's own N, M and prefix N_cp / N set the bin sizes
+DF_HZ, FC_HZ, C_MPS = 240e3, 77e9, 3e8
+RANGE_BIN_M = C_MPS / (2 * N * DF_HZ)
+VELOCITY_BIN_MPS = C_MPS / (2 * FC_HZ * M * (1 + NCP / N) / DF_HZ)
 
 
 def parse():
@@ -47,6 +52,8 @@ def parse():
                          "uneven batch)")
     ap.add_argument("--batch-frames", type=int, default=512,
                     help="frames of the uneven Monte-Carlo batch reported beside the headline (0 skips it)")
+    ap.add_argument("--rmse-frames", type=int, default=24,
+                    help="frames per SNR point of the equal-RMSE comparison of the forms (0 skips it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 3 plain device copies of MIB MiB (calibrates HBM byte counters) and exit")
     return ap.parse_args()
@@ -125,8 +132,15 @@ def cpu_baseline(frames, budget_s):
             break
     dt = time.perf_counter() - t0
     del np
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": done / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} whole {N}x{M} frames (FP64 numpy, single thread), {dt:.1f} s"}
+            "sample": f"{done} whole {N}x{M} frames (FP64 numpy, single thread), {dt:.1f} s",
+            "cpu_model": model, "host_cpu_count": os.cpu_count()}
 
 
 def time_extras(radar, torch, Yd, Ad, cfg, ws, peaks, n_peaks, status, stream, B, steps, warmup):
@@ -245,8 +259,8 @@ def time_extras(radar, torch, Yd, Ad, cfg, ws, peaks, n_peaks, status, stream, B
     out["simulate_frames_per_s_8_targets"] = B * steps / (time.perf_counter() - t0)
     del Ysim, tg, nt
 
-    # the matrix-core precision forms of the Doppler and range FFTs, same step
-    for name, flag in (("bf16x3", radar.FLAG_BF16X3), ("fp16x3", radar.FLAG_FP16X3)):
+    # the matrix-core precision forms of the range stage, same step
+    for name, flag in (("bf16x3", radar.FLAG_BF16X3), ("fp16x3", radar.FLAG_FP16X3), ("fp16", radar.FLAG_FP16)):
         cfg_p = dataclasses.replace(cfg, precision=flag)
         P = torch.empty((B, cfg.m_pad, cfg.n_pad), dtype=torch.float32, device=Yd.device)
         for _ in range(warmup):
@@ -305,7 +319,25 @@ def time_extras(radar, torch, Yd, Ad, cfg, ws, peaks, n_peaks, status, stream, B
         radar.cnn_train_step(theta, mom, vel, warmup + t + 1, 1e-3, xb, lab, loss, workspace=tws)
     torch.cuda.synchronize()
     out["cnn_train_step_ms_batch256"] = (time.perf_counter() - t0) / steps * 1e3
-    del np
+    # the whole FP32 path followed by the CNN on every frame's k peaks (patches cut from P, inference)
+    P = torch.empty((B, cfg.m_pad, cfg.n_pad), dtype=torch.float32, device=Yd.device)
+    cws_f = radar.CnnWorkspace(B * K, False, Yd.device)
+
+    def cnn_step():
+        radar.frame_process(Yd, Ad, cfg, K, P=P, workspace=ws, peaks=peaks, n_peaks=n_peaks, status=status,
+                            stream=stream)
+        pt, _ = radar.cnn_patches(P, peaks, n_peaks, stream=stream)
+        radar.cnn_forward(theta, pt, workspace=cws_f, stream=stream)
+
+    for _ in range(warmup):
+        cnn_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        cnn_step()
+    torch.cuda.synchronize()
+    out["with_cnn_frames_per_s"] = B * steps / (time.perf_counter() - t0)
+    del P, np
 
     sft = radar.sft_desc(K)
     ws_sft = radar.new_workspace(radar.sft_workspace_bytes(cfg, sft, B), Yd.device)
@@ -338,6 +370,108 @@ def _match_errors(truth_rho, truth_nu, det, n, m):
     dv = (dv + m / 2) % m - m / 2
     rows, cols = linear_sum_assignment(np.hypot(dr, dv))
     return [(dr[i, j], dv[i, j]) for i, j in zip(rows, cols)]
+
+
+def rmse_comparison(radar, torch, dev, fps, per_snr=24, train_frames=768, train_steps=1500):
+    """Range and velocity RMSE of every form on the same frames: the full-frame
+    workload's generator at SNR -20, -15, ..., 10 dB (per_snr frames each,
+    eight off-grid Rayleigh targets), top-8 peaks, each truth matched to a
+    detection by the assignment of least wrapped distance; a hit has both
+    errors within one native bin, RMSE over hits (Eq. 19 units and native
+    bins), hit rate beside it.  The forms: the FP32 grid peak, FP32 with the
+    interpolation refinement, the grid peaks of the three matrix-core range
+    forms, and FP32 with the CNN refiner (trained here, by the library's own
+    kernels, on train_frames frames of the same workload drawn from other
+    seeds).  fps: each form's frames/s on the benchmark batch."""
+    import dataclasses
+
+    import numpy as np
+
+    from paper_2209_03883_amd import cnn_train
+    from synth import cnn_init
+    from synth import frames as S
+    from synth import frames_torch as G
+
+    data = cnn_train.make_patches(train_frames, 12, n=N, m=M, k=K, chunk=32, device=dev)
+    theta, _ = cnn_train.train(cnn_init.init_params(0), data, train_steps, device=dev)
+    del data
+    base = radar.Config(N, M, PAD * N, PAD * M, NCP, zc_root=ROOT_ZC, window=radar.WIN_HANN)
+    forms = {
+        "fp32_grid": dict(),
+        "fp32_refined": dict(refine=True),
+        "bf16x3_grid": dict(precision=radar.FLAG_BF16X3),
+        "fp16x3_grid": dict(precision=radar.FLAG_FP16X3),
+        "fp16_grid": dict(precision=radar.FLAG_FP16),
+        "fp32_cnn": dict(),
+    }
+    snrs = [-20.0, -15.0, -10.0, -5.0, 0.0, 5.0, 10.0]
+    acc = {f: {s: [[], [], 0] for s in snrs} for f in forms}
+    same_cells = {f: [0, 0] for f in forms}
+    for si, snr in enumerate(snrs):
+        drawn = [G.make_frame(S.spec_full(snr_db=snr), 21, si * 1000 + i, device=dev) for i in range(per_snr)]
+        Y = torch.stack([d[0] for d in drawn])
+        A = torch.stack([d[1] for d in drawn])
+        truth = [d[2] for d in drawn]
+        del drawn
+        grid32 = {}
+        for name, kw in forms.items():
+            P, peaks, n_peaks, st = radar.frame_process(Y, A, dataclasses.replace(base, **kw), K)
+            off = None
+            if name == "fp32_cnn":
+                pt, _ = radar.cnn_patches(P, peaks, n_peaks)
+                off = cnn_train.predict(theta, pt).cpu().numpy().reshape(per_snr, K, 2)
+            pk = radar.unpack_peaks(peaks, n_peaks.cpu())
+            del P
+            for f in range(per_snr):
+                cells = [(s, r) for s, r, *_ in pk[f]]
+                if name == "fp32_grid":
+                    grid32[f] = cells
+                else:
+                    same_cells[name][0] += int(cells == grid32[f])
+                    same_cells[name][1] += 1
+                det = []
+                for i, (s, r, _, so, ro) in enumerate(pk[f]):
+                    if name == "fp32_refined":
+                        det.append(((r + ro) / PAD, (s + so) / PAD))
+                    elif name == "fp32_cnn":
+                        det.append(((r + off[f, i, 0]) / PAD, (s + off[f, i, 1]) / PAD))
+                    else:
+                        det.append((r / PAD, s / PAD))
+                e = acc[name][snr]
+                for er, ev in _match_errors(truth[f][0], truth[f][1], det, N, M):
+                    if abs(er) <= 1.0 and abs(ev) <= 1.0:
+                        e[0].append(er)
+                        e[1].append(ev)
+                e[2] += len(truth[f][0])
+        del Y, A
+
+    def rm(v):
+        return float(np.sqrt(np.mean(np.square(v)))) if v else None
+
+    out = {"snr_db": snrs, "frames_per_snr": per_snr, "range_bin_m": RANGE_BIN_M,
+           "velocity_bin_mps": VELOCITY_BIN_MPS, "cnn_training": {"frames": train_frames, "steps": train_steps},
+           "forms": {}}
+    for name in forms:
+        er = [x for s in snrs for x in acc[name][s][0]]
+        ev = [x for s in snrs for x in acc[name][s][1]]
+        tot = sum(acc[name][s][2] for s in snrs)
+        out["forms"][name] = {
+            "frames_per_s": fps.get(name),
+            "rmse_range_m": rm(er) * RANGE_BIN_M if er else None,
+            "rmse_velocity_mps": rm(ev) * VELOCITY_BIN_MPS if ev else None,
+            "rmse_range_bins": rm(er), "rmse_doppler_bins": rm(ev), "hit_rate": len(er) / max(tot, 1),
+            "per_snr": {f"{s:+.0f} dB": {"hit_rate": len(acc[name][s][0]) / max(acc[name][s][2], 1),
+                                         "rmse_range_bins": rm(acc[name][s][0]),
+                                         "rmse_doppler_bins": rm(acc[name][s][1])} for s in snrs},
+        }
+        if name != "fp32_grid":
+            out["forms"][name]["frames_with_fp32_grid_cells"] = same_cells[name][0] / max(same_cells[name][1], 1)
+    g = out["forms"]["fp32_grid"]
+    for name, v in out["forms"].items():
+        if v["rmse_range_bins"] and g["rmse_range_bins"]:
+            v["rmse_ratio_to_fp32_grid"] = [v["rmse_range_bins"] / g["rmse_range_bins"],
+                                            v["rmse_doppler_bins"] / g["rmse_doppler_bins"]]
+    return out
 
 
 def device_copy_gbs(torch, dev, mib=2048, reps=5):
@@ -496,9 +630,16 @@ def main():
         print(f"[bench] batch {({k: v for k, v in extras.items() if k.startswith('batch_') and 'rmse' not in k})}",
               file=sys.stderr, flush=True)
 
-    copy_gbs = device_copy_gbs(torch, dev)
     frames_done = B * args.steps
     fps = frames_done / dt
+    if not args.no_extras and args.rmse_frames > 0:
+        print("[bench] equal-RMSE comparison of the forms", file=sys.stderr, flush=True)
+        fps_forms = {"fp32_grid": fps, "fp32_refined": extras.get("with_refinement_frames_per_s"),
+                     "bf16x3_grid": extras.get("bf16x3_frames_per_s"),
+                     "fp16x3_grid": extras.get("fp16x3_frames_per_s"),
+                     "fp16_grid": extras.get("fp16_frames_per_s"), "fp32_cnn": extras.get("with_cnn_frames_per_s")}
+        extras["equal_rmse"] = rmse_comparison(radar, torch, dev, fps_forms, per_snr=args.rmse_frames)
+    copy_gbs = device_copy_gbs(torch, dev)
     rng_ms, rng_n = stages["range"]
     k3_ms = rng_ms / max(rng_n, 1)
     # algorithmic bytes of one range-kernel launch: read the Doppler-tap rows
@@ -529,6 +670,7 @@ def main():
             "frames_per_step": B,
             "periodogram_materialised": True,
             "hbm_roofline_frames_per_s": HBM_PEAK_GBS * 1e9 / (16 * N * M + 4 * PAD * N * PAD * M),
+            "hbm_frac": fps / (HBM_PEAK_GBS * 1e9 / (16 * N * M + 4 * PAD * N * PAD * M)),
             "device_copy_gbs": copy_gbs,
             "k3_frac_of_device_copy": achieved / copy_gbs,
             "k3_hbm": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -74,8 +74,9 @@ enum { RADAR_ST_ZERO_SYMBOL = 1u, RADAR_ST_NONFINITE = 2u,
 enum {
   RADAR_FLAG_REFINE = 1,   /* sub-cell refinement of the peaks (radar_frame_process) */
   RADAR_FLAG_BF16X3 = 2,   /* Doppler and range FFTs' radix-16 stages on BF16 matrix cores, split operands */
-  RADAR_FLAG_FP16X3 = 4,   /* the same with FP16 operands and per-column power-of-two scaling */
-  RADAR_FLAG_THRESHOLD = 8 /* keep only peaks at or above the detection threshold of Eq. 18 */
+  RADAR_FLAG_FP16X3 = 4,   /* the same with FP16 operands and power-of-two scaling */
+  RADAR_FLAG_THRESHOLD = 8,/* keep only peaks at or above the detection threshold of Eq. 18 */
+  RADAR_FLAG_FP16 = 16     /* range stage on FP16 matrix cores, operands rounded once (N = 1024 only) */
 };
 
 /* One frame shape.  Names follow the paper: N subcarriers, M OFDM symbols,
@@ -145,13 +146,23 @@ int radar_init(void);
  *   neighbourhood is solved in FP64 (separable parabolas when that quadratic
  *   has no maximum within one cell); offsets are clamped to half a fine cell
  *   about the best fine cell.  Needs M'/M <= 16, N'/N <= 16 and M <= 1024.
- *   With RADAR_FLAG_BF16X3 or RADAR_FLAG_FP16X3 (at most one) the radix-16
- *   stages of the Doppler FFT and of the range IFFTs run as 16-point DFTs by
- *   matrix product on the matrix cores: data and DFT matrix are each split
- *   into two half-precision parts (v = hi + lo, hi = rn(v), lo = rn(v - hi)),
- *   the products hi*hi, hi*lo and lo*hi accumulate in FP32; twiddles, windows,
- *   the taps stage and |.|^2 stay FP32.  These forms exist for N' = 4N,
+ *   With RADAR_FLAG_BF16X3 or RADAR_FLAG_FP16X3 the FFT butterflies run as
+ *   DFTs by matrix product on the matrix cores: data and DFT matrix are each
+ *   split into two half-precision parts (v = hi + lo, hi = rn(v),
+ *   lo = rn(v - hi)), the products hi*hi, hi*lo and lo*hi accumulate in FP32;
+ *   twiddles, windows, the taps stage and |.|^2 stay FP32.  At N = 1024 with
+ *   P written, the whole range stage (DFT back, window, padded range IDFT) is
+ *   two passes of 32-point DFTs per transform, each row scaled by a power of
+ *   two into the half-precision range, and the Doppler stage stays FP32; at
+ *   other N (and with P = NULL) the radix-16 stages of the Doppler FFT and of
+ *   the range IFFTs run as 16-point DFTs.  These forms exist for N' = 4N,
  *   4 N_cp <= N, N >= 256 (RADAR_E_UNSUPPORTED otherwise).
+ *   With RADAR_FLAG_FP16 the range stage is the N = 1024 matrix-core form
+ *   above with each operand rounded once to FP16 (one product per pass, a
+ *   third of the matrix-core work): the periodogram's normwise error is of
+ *   the order of 1e-4 instead of 1e-7.  Only for N = 1024, N' = 4N,
+ *   4 N_cp <= N, with P written (RADAR_E_UNSUPPORTED otherwise).
+ *   At most one of RADAR_FLAG_BF16X3, RADAR_FLAG_FP16X3, RADAR_FLAG_FP16.
  *   With RADAR_FLAG_THRESHOLD the peaks are the paper's detections (Eq. 18):
  *   local maxima with P >= eta = -ln(pfa) sigma_P^2, at most k, where
  *   sigma_P^2 = noise_power * mean(1/|a|^2) * sum_l w_l^2 * sum_k w_k^2 / (N M)

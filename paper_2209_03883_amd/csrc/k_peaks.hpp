@@ -93,8 +93,16 @@ __global__ void __launch_bounds__(256) k_row_max(const float* P, int64_t p_strid
 // in flight at a time; profile peaks are marked in LDS with strided row
 // ownership; the k-th largest comes from k rounds of work-group maxima; the
 // row list is written in ascending order from contiguous row chunks.
+//
+// slack > 0 (peaks only, P not materialised): the row maxima come from the
+// range kernel while the scan reads rows recomputed by another kernel, which
+// may differ by a few FP32 ulps.  The bound is then lowered to
+// tau (1 - slack), for the listing and for the scan alike, so that a local
+// maximum sitting at tau whose recomputed value lands just below it is still
+// found; the merge keeps only the k best, so the extra candidates cost only
+// scanning.
 __global__ void __launch_bounds__(256) k_peak_threshold(const float* rowmax, int m_pad, int k, float* tau_out,
-                                                        int32_t* list, int32_t* cnt_out) {
+                                                        int32_t* list, int32_t* cnt_out, float slack) {
   extern __shared__ uint32_t s_prof[];  // ord bits of profile peaks, 0 elsewhere; then the row maxima
   __shared__ uint64_t red[4];
   __shared__ int s_cnt[4];
@@ -134,7 +142,8 @@ __global__ void __launch_bounds__(256) k_peak_threshold(const float* rowmax, int
     if (best == 0) break;
     last = best;
   }
-  const float tau = found == k ? ord_value((uint32_t)(last >> 32)) : -__builtin_huge_valf();
+  float tau = found == k ? ord_value((uint32_t)(last >> 32)) : -__builtin_huge_valf();
+  if (found == k) tau -= fabsf(tau) * slack;
 
   const int chunk = (m_pad + 255) / 256;
   const int lo = tid * chunk < m_pad ? tid * chunk : m_pad;

@@ -32,7 +32,9 @@ typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
-enum class Prec { FP32 = 0, BF16X3 = 1, FP16X3 = 2 };
+// FP16: FP16 operands rounded once (no split), one product per pass; only
+// the matrix-core range stage implements it.
+enum class Prec { FP32 = 0, BF16X3 = 1, FP16X3 = 2, FP16 = 3 };
 
 template <Prec P>
 struct PrecTraits;
@@ -44,6 +46,16 @@ struct PrecTraits<Prec::BF16X3> {
   static constexpr bool kScale = false;
   static __device__ __forceinline__ f32x16_t mfma(vec8 a, vec8 b, f32x16_t c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <>
+struct PrecTraits<Prec::FP16> {
+  using half_t = _Float16;
+  using vec8 = f16x8_t;
+  static constexpr bool kScale = true;
+  static __device__ __forceinline__ f32x16_t mfma(vec8 a, vec8 b, f32x16_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
   }
 };
 

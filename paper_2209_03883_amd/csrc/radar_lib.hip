@@ -17,6 +17,7 @@
 __device__ float2 g_radar_tw[RADAR_TW_ENTRIES];
 
 #include "k_frame.hpp"
+#include "k_range_mx.hpp"
 #include "k_peaks.hpp"
 #include "k_peaks_only.hpp"
 #include "k_refine.hpp"
@@ -59,12 +60,16 @@ int validate_desc(const radar_frame_desc* d) {
   if (d->window < RADAR_WIN_RECT || d->window > RADAR_WIN_HAMMING) return RADAR_E_ARG;
   if (d->zc_mode != RADAR_ZC_NONE && d->zc_mode != RADAR_ZC_DIAG && d->zc_mode != RADAR_ZC_DENSE)
     return RADAR_E_ARG;
-  if ((d->flags & ~(RADAR_FLAG_REFINE | RADAR_FLAG_BF16X3 | RADAR_FLAG_FP16X3 | RADAR_FLAG_THRESHOLD)) != 0)
+  if ((d->flags & ~(RADAR_FLAG_REFINE | RADAR_FLAG_BF16X3 | RADAR_FLAG_FP16X3 | RADAR_FLAG_THRESHOLD |
+                    RADAR_FLAG_FP16)) != 0)
     return RADAR_E_ARG;
   if ((d->flags & RADAR_FLAG_THRESHOLD) &&
       !(d->pfa > 0.0f && d->pfa < 1.0f && d->noise_power > 0.0f && d->noise_power <= FLT_MAX))
     return RADAR_E_ARG;
-  if ((d->flags & RADAR_FLAG_BF16X3) && (d->flags & RADAR_FLAG_FP16X3)) return RADAR_E_ARG;
+  {
+    const int pf = d->flags & (RADAR_FLAG_BF16X3 | RADAR_FLAG_FP16X3 | RADAR_FLAG_FP16);
+    if (pf & (pf - 1)) return RADAR_E_ARG;  // at most one precision form
+  }
   if (d->ld < N) return RADAR_E_ARG;
   if (reinterpret_cast<uintptr_t>(d->tap_weights) & 3) return RADAR_E_ARG;
   if (!is_pow2(N) || !is_pow2(M) || N < 16 || N > 4096 || M < 16 || M > 4096) return RADAR_E_UNSUPPORTED;
@@ -75,6 +80,9 @@ int validate_desc(const radar_frame_desc* d) {
     return RADAR_E_UNSUPPORTED;
   // the matrix-core forms exist for the 4x range-padding kernels
   if ((d->flags & (RADAR_FLAG_BF16X3 | RADAR_FLAG_FP16X3)) && !(d->n_pad == 4 * N && 4 * d->n_cp <= N && N >= 256))
+    return RADAR_E_UNSUPPORTED;
+  // the single-rounding FP16 form exists for the N = 1024 matrix-core range stage
+  if ((d->flags & RADAR_FLAG_FP16) && !(N == 1024 && d->n_pad == 4 * N && 4 * d->n_cp <= N))
     return RADAR_E_UNSUPPORTED;
   return RADAR_OK;
 }
@@ -255,6 +263,23 @@ void launch_k3x4p_n(const radar::K3Args& a, int m_pad, int F, hipStream_t s) {
   }
   hipLaunchKernelGGL((radar::k3_range_power_x4p<N, PR, kStore, false>), dim3(grid), dim3(C::BLOCK), 0, s, a, total);
 }
+// the matrix-core range kernel (N = 1024): one persistent work-group per CU
+template <radar::Prec PR, bool kStore = true>
+void launch_k3mx(const radar::K3Args& a, int m_pad, int F, hipStream_t s) {
+  using C = radar::K3Mx<1024>;
+  const int total = (int)((int64_t)F * m_pad);
+  int grid = (g_num_cus > 0 ? g_num_cus : 256) * g_tune.k3_mult;
+  if (grid * C::WAVES > total) grid = (total + C::WAVES - 1) / C::WAVES;
+  if constexpr (kStore) {
+    if (a.refs) {
+      hipLaunchKernelGGL((radar::k3_range_power_mx<1024, PR, true, true>), dim3(grid), dim3(C::BLOCK), 0, s, a,
+                         total);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((radar::k3_range_power_mx<1024, PR, kStore, false>), dim3(grid), dim3(C::BLOCK), 0, s, a,
+                     total);
+}
 template <int N>
 void launch_k3_n(const radar::K3Args& a, int f2, int m_pad, int F, hipStream_t s) {
   switch (f2) {
@@ -330,12 +355,22 @@ void launch_rows_recompute(const radar::K3Args& a, int N, int F, int k, const fl
 // P, and the peak search recomputes the rows it scans.
 bool peaks_only_supported(const radar_frame_desc* d) {
   const int N = d->n_sub;
-  return (N == 256 || N == 512 || N == 1024) && d->n_pad == 4 * N && d->n_cp * 4 <= N;
+  return (N == 256 || N == 512 || N == 1024) && d->n_pad == 4 * N && d->n_cp * 4 <= N &&
+         !(d->flags & RADAR_FLAG_FP16);
+}
+
+// The matrix-core range kernel runs the range stage: N = 1024, N' = 4N,
+// 4 N_cp <= N, a matrix-core form, P written (or batch jobs).
+bool range_on_mx(const radar_frame_desc* d, bool p_written) {
+  const int N = d->n_sub;
+  return p_written && N == 1024 && d->n_pad == 4 * N && 4 * d->n_cp <= N &&
+         (d->flags & (RADAR_FLAG_BF16X3 | RADAR_FLAG_FP16X3 | RADAR_FLAG_FP16)) != 0;
 }
 
 radar::Prec prec_of(const radar_frame_desc* d) {
   if (d->flags & RADAR_FLAG_BF16X3) return radar::Prec::BF16X3;
   if (d->flags & RADAR_FLAG_FP16X3) return radar::Prec::FP16X3;
+  if (d->flags & RADAR_FLAG_FP16) return radar::Prec::FP16;
   return radar::Prec::FP32;
 }
 
@@ -432,11 +467,14 @@ int enqueue_transforms(const radar_frame_desc* d, int F, const float2* in, const
   a2.ph_off = (a2.fm == 2 || a2.fm == 4 || a2.fm == 8) ? radar::phase_offset(ilog2(M), ilog2(a2.fm)) : -1;
   slot = timer_open(RADAR_STAGE_DOPPLER, s);
   const radar::Prec prec = prec_of(d);
-  if (prec == radar::Prec::BF16X3) {
+  const bool mx = range_on_mx(d, P || refs);
+  // with the matrix-core range kernel the Doppler stage stays FP32 (it is
+  // bound by memory and latency, and its split form measured slower)
+  if (prec == radar::Prec::BF16X3 && !mx) {
 #define K2_CALL(m) launch_k2_m<m, radar::Prec::BF16X3>(a2, d->n_cp, F, s)
     RADAR_SIZE_SWITCH(M, K2_CALL)
 #undef K2_CALL
-  } else if (prec == radar::Prec::FP16X3) {
+  } else if (prec == radar::Prec::FP16X3 && !mx) {
 #define K2_CALL(m) launch_k2_m<m, radar::Prec::FP16X3>(a2, d->n_cp, F, s)
     RADAR_SIZE_SWITCH(M, K2_CALL)
 #undef K2_CALL
@@ -460,6 +498,13 @@ int enqueue_transforms(const radar_frame_desc* d, int F, const float2* in, const
       launch_k3x4p_rowmax<radar::Prec::FP16X3>(a3, N, d->m_pad, F, s);
     else
       launch_k3x4p_rowmax<radar::Prec::FP32>(a3, N, d->m_pad, F, s);
+  } else if (mx) {
+    if (prec == radar::Prec::BF16X3)
+      launch_k3mx<radar::Prec::BF16X3>(a3, d->m_pad, F, s);
+    else if (prec == radar::Prec::FP16X3)
+      launch_k3mx<radar::Prec::FP16X3>(a3, d->m_pad, F, s);
+    else
+      launch_k3mx<radar::Prec::FP16>(a3, d->m_pad, F, s);
   } else if (x4) {
     if (prec == radar::Prec::BF16X3)
       launch_k3x4_any<radar::Prec::BF16X3>(a3, N, d->m_pad, F, s);
@@ -518,8 +563,11 @@ int enqueue_peaks(const float* P, int64_t p_stride, int m_pad, int n_pad, int F,
   int32_t* list = reinterpret_cast<int32_t*>(ws + w.list);
   uint64_t* cand = reinterpret_cast<uint64_t*>(ws + w.cand);
   const int slot = timer_open(RADAR_STAGE_PEAKS, s);
-  hipLaunchKernelGGL(radar::k_peak_threshold, dim3(F), dim3(256), 2 * m_pad * sizeof(uint32_t), s, rowmax, m_pad, k, tau,
-                     list, cnt);
+  // peaks only: the rows scanned are recomputed by another kernel than the
+  // one whose row maxima set tau, and may differ from them by a few ulps
+  const float slack = (!P && !refs) ? 1.0f / 65536.0f : 0.0f;
+  hipLaunchKernelGGL(radar::k_peak_threshold, dim3(F), dim3(256), 2 * m_pad * sizeof(uint32_t), s, rowmax, m_pad, k,
+                     tau, list, cnt, slack);
   RADAR_HIP_CHECK(hipGetLastError());
   if (!P && !refs) {
     if (!d || !U) return RADAR_E_ARG;
@@ -752,7 +800,7 @@ struct BatchGroup {
   int k = 0;
   std::vector<int> jobs;
   size_t refs_off = 0;     // FrameRef table in the workspace
-  size_t scratch_off = 0;  // this group's scratch (groups may run concurrently)
+  size_t ws_off = 0;  // this group's workspace region (groups may run concurrently)
   double work = 0.0;       // algorithmic bytes, for balancing concurrent branches
   Tuning tune;
 };
@@ -772,7 +820,7 @@ int validate_job(const radar_frame_job& j) {
   return RADAR_OK;
 }
 
-// groups in order of first appearance; fills the table and scratch offsets and
+// groups in order of first appearance; fills the table and workspace offsets and
 // returns the workspace size
 size_t plan_groups(const radar_frame_job* jobs, int n, std::vector<BatchGroup>& groups) {
   groups.clear();
@@ -794,7 +842,7 @@ size_t plan_groups(const radar_frame_job* jobs, int n, std::vector<BatchGroup>& 
     off += align256(g.jobs.size() * sizeof(radar::FrameRef));
   }
   for (auto& g : groups) {
-    g.scratch_off = off;
+    g.ws_off = off;
     off += frame_ws_layout(&g.d, (int)g.jobs.size(), g.k).total;
     g.work = (double)g.jobs.size() * (16.0 * g.d.n_sub * g.d.n_sym + 4.0 * g.d.n_pad * g.d.m_pad);
   }
@@ -818,21 +866,21 @@ namespace {
 int enqueue_group(const radar_batch& b, const BatchGroup& g, hipStream_t s) {
   const int F = (int)g.jobs.size();
   const auto* refs = reinterpret_cast<const radar::FrameRef*>(b.ws + g.refs_off);
-  char* scratch = b.ws + g.scratch_off;
+  char* gws = b.ws + g.ws_off;
   const FrameWs w = frame_ws_layout(&g.d, F, g.k);
   const Tuning saved = g_tune;
   g_tune = g.tune;
   hipLaunchKernelGGL(radar::k0_clear, dim3((F + 255) / 256), dim3(256), 0, s, nullptr, nullptr, F, refs);
   int rc = hipGetLastError() == hipSuccess ? RADAR_OK : RADAR_E_HIP;
   if (rc == RADAR_OK)
-    rc = enqueue_transforms(&g.d, F, nullptr, nullptr, 0, 0, nullptr, 0, nullptr, w, scratch, s, refs);
+    rc = enqueue_transforms(&g.d, F, nullptr, nullptr, 0, 0, nullptr, 0, nullptr, w, gws, s, refs);
   const float* inv_sum =
-      (g.d.flags & RADAR_FLAG_THRESHOLD) ? reinterpret_cast<const float*>(scratch + w.inv_sum) : nullptr;
+      (g.d.flags & RADAR_FLAG_THRESHOLD) ? reinterpret_cast<const float*>(gws + w.inv_sum) : nullptr;
   if (rc == RADAR_OK)
-    rc = enqueue_peaks(nullptr, 0, g.d.m_pad, g.d.n_pad, F, g.k, w.pk, scratch, nullptr, nullptr, s, refs, inv_sum,
+    rc = enqueue_peaks(nullptr, 0, g.d.m_pad, g.d.n_pad, F, g.k, w.pk, gws, nullptr, nullptr, s, refs, inv_sum,
                        g.d.n_sym);
   if (rc == RADAR_OK && (g.d.flags & RADAR_FLAG_REFINE))
-    rc = enqueue_refine(&g.d, F, g.k, reinterpret_cast<const float2*>(scratch + w.taps), nullptr, nullptr, refs, s);
+    rc = enqueue_refine(&g.d, F, g.k, reinterpret_cast<const float2*>(gws + w.taps), nullptr, nullptr, refs, s);
   g_tune = saved;
   return rc;
 }
@@ -1341,7 +1389,7 @@ int radar_batch_create(const radar_frame_job* jobs, int32_t n_jobs, int32_t flag
       rc = RADAR_E_HIP;
     } else {
       // groups run on up to kBatchBranches concurrent branches (each has its
-      // own scratch), heaviest first onto the least loaded branch
+      // own workspace region), heaviest first onto the least loaded branch
       const int nb = std::min<int>(kBatchBranches, (int)b->groups.size());
       std::vector<hipStream_t> br(nb, nullptr);
       std::vector<hipEvent_t> ev(nb + 1, nullptr);

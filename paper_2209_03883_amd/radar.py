@@ -26,7 +26,7 @@ RADAR_E_NOT_COPRIME = -5
 WIN_RECT, WIN_HANN, WIN_HAMMING = 0, 1, 2
 ZC_NONE, ZC_DIAG, ZC_DENSE = 0, 1, 2
 ST_ZERO_SYMBOL, ST_NONFINITE, ST_ISI = 1, 2, 4
-FLAG_REFINE, FLAG_BF16X3, FLAG_FP16X3, FLAG_THRESHOLD = 1, 2, 4, 8
+FLAG_REFINE, FLAG_BF16X3, FLAG_FP16X3, FLAG_THRESHOLD, FLAG_FP16 = 1, 2, 4, 8, 16
 
 EXPORTED = (
     "radar_version", "radar_status_string", "radar_init",
@@ -188,7 +188,7 @@ class Config:
     zc_shift: int = 0
     window: int = WIN_HANN
     refine: bool = False
-    precision: int = 0          # 0 (FP32), FLAG_BF16X3 or FLAG_FP16X3
+    precision: int = 0          # 0 (FP32), FLAG_BF16X3, FLAG_FP16X3 or FLAG_FP16
     threshold: bool = False     # Eq. 18 detection (pfa, noise_power)
     pfa: float = 1e-2
     noise_power: float = 0.0

@@ -312,6 +312,11 @@ def test_sft_rejects_pointers_and_workspace():
     (dict(precision=8), radar.RADAR_E_ARG),                                        # unknown bit
     (dict(precision=radar.FLAG_BF16X3, n_pad=2048), radar.RADAR_E_UNSUPPORTED),   # needs N' = 4N
     (dict(precision=radar.FLAG_FP16X3, n_cp=300), radar.RADAR_E_UNSUPPORTED),     # needs 4 N_cp <= N
+    (dict(precision=radar.FLAG_FP16 | radar.FLAG_FP16X3), radar.RADAR_E_ARG),     # at most one form
+    (dict(precision=radar.FLAG_FP16 | radar.FLAG_BF16X3), radar.RADAR_E_ARG),
+    (dict(precision=radar.FLAG_FP16, n_sub=512, n_pad=2048, n_cp=128), radar.RADAR_E_UNSUPPORTED),  # N = 1024 only
+    (dict(precision=radar.FLAG_FP16, n_pad=8192), radar.RADAR_E_UNSUPPORTED),     # needs N' = 4N
+    (dict(precision=radar.FLAG_FP16, n_cp=257), radar.RADAR_E_UNSUPPORTED),       # needs 4 N_cp <= N
 ])
 def test_precision_flag_validation(kw, code):
     base = dict(n_sub=1024, n_sym=1024, n_pad=4096, m_pad=4096, n_cp=256, zc_root=7)
@@ -321,6 +326,17 @@ def test_precision_flag_validation(kw, code):
     assert L.radar_frame_workspace_size(ctypes.byref(cfg.desc()), 1, 8) == 0
     p = 256
     assert L.radar_frame_process(ctypes.byref(cfg.desc()), 1, p, p, 0, p, 0, 8, p, p, p, p, 1 << 40, None) == code
+
+
+def test_fp16_form_needs_the_periodogram_written():
+    L = radar.lib()
+    cfg = radar.Config(1024, 1024, 4096, 4096, 256, zc_root=7, precision=radar.FLAG_FP16)
+    d = ctypes.byref(cfg.desc())
+    need = L.radar_frame_workspace_size(d, 1, 8)
+    assert need > 0
+    p = 256
+    assert L.radar_frame_process(d, 1, p, p, 0, None, 0, 8, p, p, p, p, need, None) == radar.RADAR_E_UNSUPPORTED
+    assert L.radar_frame_process(d, 1, p, p, 0, p, 0, 8, p, p, p, p, need - 1, None) == radar.RADAR_E_WORKSPACE
 
 
 def test_precision_flags_accepted():

@@ -7,8 +7,11 @@ row code.  That code is compiled into two kernels, and the compiler may order
 a few multiply-adds differently in each, so a recomputed cell can differ from
 the written one by a few FP32 ulps.  The rule: the same counts and status, the
 same cells rank by rank except at near-ties of the materialised P (the
-tolerance the oracle comparisons use), and values within 8 ulps.  The small
-workload is also checked against the FP64 oracle.
+tolerance the oracle comparisons use), and values within 8 ulps.  At N = 1024
+the split matrix-core forms write P with the two-pass 32-point range kernel,
+whose row code peaks-only does not use; there the two runs agree to the
+forms' error instead.  The small workload is also checked against the FP64
+oracle.
 """
 
 import dataclasses
@@ -44,7 +47,12 @@ def _both(frames, cfg, k):
         radar.unpack_peaks(pk0, n0.cpu()), st0.cpu().numpy()
 
 
-def _same(res, label):
+def _same(res, label, split=False):
+    """split: the materialised run took the matrix-core range kernel (N = 1024
+    in a split form) while peaks-only recomputes rows with the radix-16 form's
+    row code, so the two differ by the forms' error (normwise about 1e-5), not
+    by ulps: cells may then swap only at near-ties of 1e-3 relative and values
+    agree within 1e-4 of the frame's largest peak."""
     P, with_p, st1, without_p, st0 = res
     np.testing.assert_array_equal(st0, st1, err_msg=label)
     m_pad = P.shape[1]
@@ -53,11 +61,15 @@ def _same(res, label):
         a, b = with_p[f], without_p[f]
         assert len(a) == len(b), (label, f, len(a), len(b))
         ref = [(s, r, float(P[f, s + m_pad // 2, r])) for s, r, *_ in a]
-        assert compare_peak_indices([(s, r) for s, r, *_ in b], ref, P[f].astype(np.float64)) is not None, \
-            (label, f, a, b)
+        assert compare_peak_indices([(s, r) for s, r, *_ in b], ref, P[f].astype(np.float64),
+                                    near_tie=1e-3 if split else 1e-5) is not None, (label, f, a, b)
+        top = max(p for _, _, p, *_ in a) if a else 0.0
         for (s1, r1, p1, *o1), (s0, r0, p0, *o0) in zip(a, b):
             if (s1, r1) == (s0, r0):
-                assert abs(p0 - p1) <= 8 * np.spacing(np.float32(p1)), (label, f, s1, r1, p1, p0)
+                if split:
+                    assert abs(p0 - p1) <= 1e-4 * top, (label, f, s1, r1, p1, p0)
+                else:
+                    assert abs(p0 - p1) <= 8 * np.spacing(np.float32(p1)), (label, f, s1, r1, p1, p0)
                 np.testing.assert_allclose(o0, o1, atol=1e-4)
                 exact += p0 == p1
     say(f"{label}: {exact} of {sum(len(x) for x in with_p)} peak values bit-identical")
@@ -97,7 +109,7 @@ def test_peaks_only_matches_materialised(shape):
     frames = [S.make_frame(spec, 81, i) for i in range(3)]
     cfg = radar.Config(n, m, 4 * n, 2 * m, n_cp, zc_root=3, **extra)
     say(f"peaks only {shape}")
-    _same(_both(frames, cfg, k), str(shape))
+    _same(_both(frames, cfg, k), str(shape), split=n == 1024 and bool(extra))
 
 
 def test_full_frames_peaks_only():
@@ -131,3 +143,21 @@ def test_unsupported_shape_is_refused():
     with pytest.raises(radar.RadarError) as ei:
         radar.frame_process(torch.from_numpy(Y).cuda(), torch.from_numpy(A).cuda(), cfg, 3, materialise=False)
     assert ei.value.code == radar.RADAR_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("n, m, ncp", [(256, 64, 32), (1024, 128, 256)])
+def test_kth_peak_at_the_bound(n, m, ncp):
+    # exactly k noiseless targets, each alone in its rows: the k-th largest
+    # row-profile peak, the bound tau, is the k-th peak itself.  The recomputed
+    # value of that cell may land a few ulps below the range kernel's; the
+    # lowered bound must still find it, so every frame reports k peaks
+    k = 6
+    spec = S.FrameSpec(n_sub=n, n_sym=m, qam=16, zc_root=3, n_targets=k, snr_db=0.0, on_grid=False,
+                       rho_min=1.0, rho_max=ncp - 2.0, nu_abs_max=m / 2 - 2, rayleigh=True, min_sep=4.0, noise=False)
+    frames = [S.make_frame(spec, 83, i) for i in range(8)]
+    cfg = radar.Config(n, m, 4 * n, 4 * m, ncp, zc_root=3)
+    say(f"peaks only, k-th peak at the bound, {n}x{m}")
+    res = _both(frames, cfg, k)
+    for f in range(len(frames)):
+        assert len(res[3][f]) == k, (f, res[3][f])
+    _same(res, f"k-th at tau {n}x{m}")
