@@ -559,6 +559,17 @@ def time_batch(radar, torch, n_frames, steps):
             "batch_rmse_vs_snr_grid": grid, "batch_rmse_vs_snr_refined": refined}
 
 
+def fp16_range_hbm(extras, copy_gbs):
+    """The FP16 matrix-core form's range stage against HBM: its algorithmic
+    bytes per frame (read U, write P) over its HIP-event time per frame."""
+    st = extras.get("fp16_stage_us_per_frame")
+    if not st or not st.get("range"):
+        return {}
+    gbs = (PAD * M * NCP * 8 + PAD * M * PAD * N * 4) / (st["range"] * 1e-6) / 1e9
+    return {"fp16_range_hbm": {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                               "frac_of_device_copy": gbs / copy_gbs}}
+
+
 def dataclasses_replace(cfg, **kw):
     import dataclasses
 
@@ -676,6 +687,7 @@ def main():
             "k3_hbm": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": achieved / HBM_PEAK_GBS},
             "k3_frac_of_unpacked_fp32": k3_tflops / FP32_UNPACKED_PEAK_TFLOPS,
+            **fp16_range_hbm(extras, copy_gbs),
             "stage_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in stages.items() if v[1]},
             **extras,
         },

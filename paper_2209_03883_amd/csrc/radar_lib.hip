@@ -887,12 +887,16 @@ int enqueue_group(const radar_batch& b, const BatchGroup& g, hipStream_t s) {
 
 // Autotuner: candidate launch plans of one group, timed on the jobs' data.
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int, int, int, int, int>, Tuning> g_tune_cache;
+std::map<std::tuple<int, int, int, int, int, int, int, int, int, bool, int>, Tuning> g_tune_cache;
 
 int tune_group(radar_batch& b, BatchGroup& g, hipStream_t s) {
   const radar_frame_desc& d = g.d;
   const int F = (int)g.jobs.size();
-  const auto key = std::make_tuple(d.n_sub, d.n_sym, d.n_pad, d.m_pad, d.n_cp, d.flags, g.k, F);
+  // everything that changes the work: the shape, the flags (precision form,
+  // refinement, threshold), the precoding (the dense reading adds an FP64
+  // stage), tap weights and the window
+  const auto key = std::make_tuple(d.n_sub, d.n_sym, d.n_pad, d.m_pad, d.n_cp, d.flags, g.k, F, d.zc_mode,
+                                   d.tap_weights != nullptr, d.window);
   {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     auto it = g_tune_cache.find(key);
@@ -905,7 +909,7 @@ int tune_group(radar_batch& b, BatchGroup& g, hipStream_t s) {
   const bool persistent_k1 = N >= 256 && N <= 1024;
   const bool x4 = d.n_pad == 4 * N && 4 * d.n_cp <= N && N >= 256;
   const bool x4p = x4 && N <= 1024;
-  const bool fp32 = !(d.flags & (RADAR_FLAG_BF16X3 | RADAR_FLAG_FP16X3));
+  const bool fp32 = !(d.flags & (RADAR_FLAG_BF16X3 | RADAR_FLAG_FP16X3 | RADAR_FLAG_FP16));
   std::vector<Tuning> cands(1);
   if (persistent_k1 || x4p) {
     Tuning t;

@@ -164,6 +164,8 @@ def test_full_frame_parity(snr_db):
     assert st[0] == 0
     excl = _check_frame(P[0], pk[0], f, cfg, 8, f"full snr={snr_db}")
     say(f"near-tie exclusions: {excl}")
+    # at SNR >= 0 dB at most one rank of eight may be an FP32 near-tie
+    assert excl <= 1, excl
 
 
 # ------------------------------------------------------- the other entry points
@@ -278,5 +280,7 @@ def test_bench_launch_configuration_sampled():
         say(f"frame {f}: normwise P error {err:.3e}")
         assert err <= P_TOL_FP32
         assert check_topk_property(Pf, pk_all[f], 8) is None
-        assert compare_peak_indices([(s, r) for s, r, *_ in pk_all[f]], oracle_ranked(O, P_ref, 8), P_ref) is not None
+        excl = compare_peak_indices([(s, r) for s, r, *_ in pk_all[f]], oracle_ranked(O, P_ref, 8), P_ref)
+        say(f"frame {f}: near-tie exclusions {excl}")
+        assert excl is not None and excl <= 1, excl
     del P, Yd, Ad

@@ -38,18 +38,22 @@ def _supported(name, cfg):
 
 
 def _same_or_tie(got, want, P_ref, name, m_pad):
-    """Peak cells equal rank by rank, except where the oracle's values of the two cells tie at the form's error."""
+    """Peak cells equal rank by rank, except where the oracle's values of the
+    two cells tie at the form's error: the number of such ranks, or None on a
+    real mismatch."""
     pmax = float(P_ref.max())
+    ties = 0
     for (gs, gr), (ws, wr) in zip(got, want):
         if (gs, gr) == (ws, wr):
             continue
         va, vb = P_ref[gs + m_pad // 2, gr], P_ref[ws + m_pad // 2, wr]
         if name == "fp16":
             if abs(va - vb) > 2 * P_TOL_FP16 * pmax:
-                return False
+                return None
         elif abs(va - vb) > NEAR_TIE_SPLIT * max(va, vb):
-            return False
-    return True
+            return None
+        ties += 1
+    return ties
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -89,13 +93,15 @@ def _check(frames, cfg, k, label):
                 (label, name, err)
             # peak cells: the oracle's, up to near-ties at this form's error level
             if name == "fp16":
-                assert len(pk[i]) == len(ref) and _same_or_tie([(s, r) for s, r, *_ in pk[i]],
-                                                               [(s, r) for s, r, _ in ref], P_ref, name,
-                                                               cfg.m_pad), (label, name, pk[i][:4], ref[:4])
+                assert len(pk[i]) == len(ref)
+                excl = _same_or_tie([(s, r) for s, r, *_ in pk[i]], [(s, r) for s, r, _ in ref], P_ref, name,
+                                    cfg.m_pad)
             else:
                 excl = compare_peak_indices([(s, r) for s, r, *_ in pk[i]], ref, P_ref,
                                             near_tie=1e-5 if name == "fp32" else NEAR_TIE_SPLIT)
-                assert excl is not None, (label, name, pk[i][:4], ref[:4])
+            # at most one rank per frame may be a near-tie
+            assert excl is not None and excl <= 1, (label, name, excl, pk[i][:4], ref[:4])
+            line.append(f"ties {excl}")
         say(f"{label}/{i}: " + "; ".join(line))
         # and the FP32 path's cells
         fp32 = [(s, r) for s, r, *_ in out["fp32"][1][i]]
@@ -103,7 +109,8 @@ def _check(frames, cfg, k, label):
             if name == "fp32":
                 continue
             got = [(s, r) for s, r, *_ in out[name][1][i]]
-            assert _same_or_tie(got, fp32, P_ref, name, cfg.m_pad), (label, name, got, fp32)
+            ties = _same_or_tie(got, fp32, P_ref, name, cfg.m_pad)
+            assert ties is not None and ties <= 1, (label, name, got, fp32)
     return out
 
 
