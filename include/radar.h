@@ -274,7 +274,15 @@ int radar_detect_topk(const float *P, int32_t m_pad, int32_t n_pad, int32_t n_fr
  * Works on the LS estimate h[k, l] = y conj(z_k) / a of Eq. 16 at native
  * resolution (no DFT-CE, no window, no padding).  Of the descriptor only
  * n_sub (N), n_sym (M), zc_mode, zc_root, zc_shift and ld are used (N, M
- * powers of two in [16, 4096]); flags must be 0.  Q = lcm(N, M) = max(N, M).
+ * in [16, 4096]; flags must be 0).  Q = lcm(N, M).  For N, M powers of two
+ * Q = max(N, M) and the slices and their recovery stay in registers and LDS.
+ * Otherwise (e.g. Table I's N = 2048, M = 560, Q = 71680) Q = P R with P the
+ * power of two in Q and R odd; the Q-point DFT then runs as P-point and
+ * R-point DFTs in the prime-factor mapping (no twiddles), and the recovery
+ * keeps the spectra in global memory.  That path needs Q <= 131072,
+ * P >= 16 and R <= 255 (RADAR_E_UNSUPPORTED otherwise), the ZC root
+ * relatively prime to N (RADAR_E_NOT_COPRIME), and takes the ZC phase of
+ * Eq. 23 for either parity of N.
  *
  * For each direction (alpha, beta) of s->dirs, in order, three slices
  * t -> h[(alpha t + tau1) mod N, (beta t + tau2) mod M], t < Q, at offsets
@@ -299,8 +307,9 @@ int radar_detect_topk(const float *P, int32_t m_pad, int32_t n_pad, int32_t n_fr
  * gathered samples only.
  * slices: optional output (NULL for none): the raw slice spectra
  *         [n_frames][n_dirs][3][Q] complex64 before any subtraction.
- * ws: device workspace of radar_fps_sft_workspace_size bytes (0 when slices
- *     is given: the spectra then live there).
+ * ws: device workspace of radar_fps_sft_workspace_size bytes.  With slices
+ *     given and Q a power of two it may be NULL (the spectra live in slices);
+ *     for other Q it is always needed (the DFT's first pass and the ZC table).
  * Errors: RADAR_E_ARG for bad pointers, n_frames outside [1, 65535], n_dirs
  * outside [1, 16], k outside [1, 64], pfa outside (0, 1), tol outside
  * (0, 1], a direction with alpha = 0 mod N and beta = 0 mod M, or flags != 0;

@@ -22,6 +22,7 @@ __device__ float2 g_radar_tw[RADAR_TW_ENTRIES];
 #include "k_peaks_only.hpp"
 #include "k_refine.hpp"
 #include "k_sft.hpp"
+#include "k_sft_general.hpp"
 #include "k_cnn.hpp"
 #include "k_dense.hpp"
 #include "k_sim.hpp"
@@ -596,7 +597,34 @@ int enqueue_peaks(const float* P, int64_t p_stride, int m_pad, int n_pad, int F,
 struct SftPlan {
   int N, M, Q, n_dirs;
   int dir_a[radar::kSftMaxDirs], dir_b[radar::kSftMaxDirs];
+  // Q not a power of two: Q = P R, P a power of two, R odd (the prime-factor path)
+  bool general = false;
+  int P = 0, R = 1, r_inv = 0, p_inv = 0, gcd_nm = 1;
 };
+
+int64_t gcd64(int64_t a, int64_t b) {
+  while (b) {
+    const int64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a < 0 ? -a : a;
+}
+// x^-1 mod m (gcd(x, m) = 1, m >= 1) by the extended Euclidean algorithm
+int64_t inv_mod(int64_t x, int64_t m) {
+  if (m == 1) return 0;
+  int64_t r0 = m, r1 = ((x % m) + m) % m, s0 = 0, s1 = 1;
+  while (r1) {
+    const int64_t q = r0 / r1;
+    int64_t t = r0 - q * r1;
+    r0 = r1;
+    r1 = t;
+    t = s0 - q * s1;
+    s0 = s1;
+    s1 = t;
+  }
+  return ((s0 % m) + m) % m;
+}
 
 int validate_sft(const radar_frame_desc* d, const radar_sft_desc* sd, SftPlan* plan) {
   if (!d || !sd) return RADAR_E_ARG;
@@ -610,11 +638,26 @@ int validate_sft(const radar_frame_desc* d, const radar_sft_desc* sd, SftPlan* p
   if (sd->n_dirs < 1 || sd->n_dirs > radar::kSftMaxDirs) return RADAR_E_ARG;
   if (sd->k < 1 || sd->k > radar::kSftMaxK) return RADAR_E_ARG;
   if (!(sd->pfa > 0.0f && sd->pfa < 1.0f) || !(sd->tol > 0.0f && sd->tol <= 1.0f)) return RADAR_E_ARG;
-  if (!is_pow2(N) || !is_pow2(M) || N < 16 || N > 4096 || M < 16 || M > 4096) return RADAR_E_UNSUPPORTED;
-  if (d->zc_mode == RADAR_ZC_DIAG && (d->zc_root % 2) == 0) return RADAR_E_NOT_COPRIME;
+  if (N < 16 || N > 4096 || M < 16 || M > 4096) return RADAR_E_UNSUPPORTED;
+  if (d->zc_mode == RADAR_ZC_DIAG && gcd64(d->zc_root, N) != 1) return RADAR_E_NOT_COPRIME;
   plan->N = N;
   plan->M = M;
-  plan->Q = N > M ? N : M;  // lcm of two powers of two
+  const int64_t g = gcd64(N, M);
+  const int64_t Q = (int64_t)N / g * M;  // lcm(N, M)
+  if (is_pow2(Q)) {
+    plan->Q = (int)Q;
+  } else {
+    // the prime-factor path: Q = P R, P = the power of two in Q, R odd
+    const int64_t P = Q & -Q, R = Q / P;
+    if (Q > radar::kSftGMaxQ || P < 16 || R > radar::kSftGMaxR) return RADAR_E_UNSUPPORTED;
+    plan->Q = (int)Q;
+    plan->general = true;
+    plan->P = (int)P;
+    plan->R = (int)R;
+    plan->r_inv = (int)inv_mod(R, P);
+    plan->p_inv = (int)inv_mod(P, R);
+    plan->gcd_nm = (int)g;
+  }
   plan->n_dirs = sd->n_dirs;
   for (int i = 0; i < sd->n_dirs; ++i) {
     // alpha enters only through alpha t mod N and alpha k1 Q/N mod Q: reduce mod N (beta mod M)
@@ -629,6 +672,59 @@ int validate_sft(const radar_frame_desc* d, const radar_sft_desc* sd, SftPlan* p
 
 size_t sft_spectra_bytes(const SftPlan& p, int n_frames) {
   return align256((size_t)n_frames * p.n_dirs * 3 * p.Q * sizeof(float2));
+}
+// the prime-factor path's workspace: the spectra (unless the caller takes
+// them), pass 1's output of the same size, conj(z_k) and W_R^x
+struct SftGeneralWs {
+  size_t S, Z, zc, wr, total;
+};
+SftGeneralWs sft_general_ws(const SftPlan& p, int n_frames) {
+  SftGeneralWs w;
+  w.S = 0;
+  w.Z = sft_spectra_bytes(p, n_frames);
+  w.zc = w.Z + sft_spectra_bytes(p, n_frames);
+  w.wr = w.zc + align256((size_t)p.N * sizeof(float2));
+  w.total = w.wr + align256((size_t)p.R * sizeof(float2));
+  return w;
+}
+
+template <int Q>
+int launch_sft_q(const radar::K5Args& a5, const radar::K6Args& a6, int F, hipStream_t s);
+
+template <int P>
+void launch_sft_pass1(const radar::K5gArgs& g, hipStream_t s) {
+  using C = radar::K5Shape<P>;
+  const int teams = g.total * g.R;
+  hipLaunchKernelGGL(radar::k5g_sft_pass1<P>, dim3((teams + C::TEAMS - 1) / C::TEAMS), dim3(C::BLOCK), 0, s, g);
+}
+
+// the prime-factor path: tables, the P-point pass, the R-point pass, the decode
+int launch_sft_general(const radar::K5gArgs& g, const radar::K6gArgs& g6, int64_t root, int64_t shift, int F,
+                       hipStream_t s) {
+  int slot = timer_open(RADAR_STAGE_SFT_SLICES, s);
+  const int nt = g.N > g.R ? g.N : g.R;
+  hipLaunchKernelGGL(radar::k_sft_tables, dim3((nt + 255) / 256), dim3(256), 0, s, g.N, root, shift, g.R,
+                     const_cast<float2*>(g.zc), const_cast<float2*>(g.wr));
+  switch (g.P) {
+    case 16: launch_sft_pass1<16>(g, s); break;
+    case 32: launch_sft_pass1<32>(g, s); break;
+    case 64: launch_sft_pass1<64>(g, s); break;
+    case 128: launch_sft_pass1<128>(g, s); break;
+    case 256: launch_sft_pass1<256>(g, s); break;
+    case 512: launch_sft_pass1<512>(g, s); break;
+    case 1024: launch_sft_pass1<1024>(g, s); break;
+    case 2048: launch_sft_pass1<2048>(g, s); break;
+    default: launch_sft_pass1<4096>(g, s); break;
+  }
+  const int64_t outs = (int64_t)g.total * g.Q;
+  hipLaunchKernelGGL(radar::k5g_sft_pass2, dim3((unsigned)((outs + 255) / 256)), dim3(256), 0, s, g);
+  timer_close(RADAR_STAGE_SFT_SLICES, slot, s);
+  RADAR_HIP_CHECK(hipGetLastError());
+  slot = timer_open(RADAR_STAGE_SFT_DECODE, s);
+  hipLaunchKernelGGL(radar::k6g_sft_decode, dim3(F), dim3(radar::kSftDecodeThreads), 0, s, g6);
+  timer_close(RADAR_STAGE_SFT_DECODE, slot, s);
+  RADAR_HIP_CHECK(hipGetLastError());
+  return RADAR_OK;
 }
 
 template <int Q>
@@ -1276,7 +1372,7 @@ void radar_sft_default(radar_sft_desc* s, int32_t k) {
 size_t radar_fps_sft_workspace_size(const radar_frame_desc* d, const radar_sft_desc* sd, int32_t n_frames) {
   SftPlan p;
   if (validate_sft(d, sd, &p) != RADAR_OK || n_frames < 1) return 0;
-  return sft_spectra_bytes(p, n_frames);
+  return p.general ? sft_general_ws(p, n_frames).total : sft_spectra_bytes(p, n_frames);
 }
 
 int radar_fps_sft(const radar_frame_desc* d, const radar_sft_desc* sd, int32_t n_frames, const radar_cf32* Y,
@@ -1290,7 +1386,12 @@ int radar_fps_sft(const radar_frame_desc* d, const radar_sft_desc* sd, int32_t n
   const int64_t frame_elems = (int64_t)(p.M - 1) * d->ld + p.N;
   if (n_frames > 1 && frame_stride < frame_elems) return RADAR_E_ARG;
   float2* spectra = reinterpret_cast<float2*>(slices);
-  if (!spectra) {
+  if (p.general) {
+    // pass 1's output and the tables need the workspace even when the caller takes the spectra
+    if (!ws) return RADAR_E_ARG;
+    if (ws_bytes < sft_general_ws(p, n_frames).total) return RADAR_E_WORKSPACE;
+    if (!spectra) spectra = static_cast<float2*>(ws);
+  } else if (!spectra) {
     if (!ws) return RADAR_E_ARG;
     if (ws_bytes < sft_spectra_bytes(p, n_frames)) return RADAR_E_WORKSPACE;
     spectra = static_cast<float2*>(ws);
@@ -1328,6 +1429,51 @@ int radar_fps_sft(const radar_frame_desc* d, const radar_sft_desc* sd, int32_t n
   for (int i = 0; i < p.n_dirs; ++i) {
     a5.dir_a[i] = a6.dir_a[i] = p.dir_a[i];
     a5.dir_b[i] = a6.dir_b[i] = p.dir_b[i];
+  }
+  if (p.general) {
+    char* wsb = static_cast<char*>(ws);
+    const SftGeneralWs w = sft_general_ws(p, n_frames);
+    radar::K5gArgs g{};
+    g.Y = a5.Y;
+    g.A = a5.A;
+    g.ld = a5.ld;
+    g.frame_stride = a5.frame_stride;
+    const bool zc_on = d->zc_mode == RADAR_ZC_DIAG;
+    g.zc = zc_on ? reinterpret_cast<float2*>(wsb + w.zc) : nullptr;
+    g.wr = reinterpret_cast<float2*>(wsb + w.wr);
+    g.Z = reinterpret_cast<float2*>(wsb + w.Z);
+    g.S = spectra;
+    g.status = status;
+    g.N = p.N;
+    g.M = p.M;
+    g.Q = p.Q;
+    g.P = p.P;
+    g.R = p.R;
+    g.n_dirs = p.n_dirs;
+    g.total = a5.total;
+    g.r_inv = p.r_inv;
+    g.p_inv = p.p_inv;
+    radar::K6gArgs g6{};
+    g6.S = spectra;
+    g6.peaks = peaks;
+    g6.n_peaks = n_peaks;
+    g6.N = p.N;
+    g6.M = p.M;
+    g6.Q = p.Q;
+    g6.n_dirs = p.n_dirs;
+    g6.k = sd->k;
+    g6.nm_over_q = (float)p.gcd_nm;
+    g6.thr_factor = a6.thr_factor;
+    g6.tol = a6.tol;
+    g6.floor_rel = a6.floor_rel;
+    for (int i = 0; i < p.n_dirs; ++i) {
+      g.dir_a[i] = g6.dir_a[i] = p.dir_a[i];
+      g.dir_b[i] = g6.dir_b[i] = p.dir_b[i];
+    }
+    const int64_t two_n = 2 * (int64_t)p.N;
+    const int64_t root = zc_on ? ((d->zc_root % two_n) + two_n) % two_n : 0;
+    const int64_t shift = zc_on ? ((d->zc_shift % two_n) + two_n) % two_n : 0;
+    return launch_sft_general(g, g6, root, shift, n_frames, s);
   }
   switch (p.Q) {
     case 16: return launch_sft_q<16>(a5, a6, n_frames, s);

@@ -8,6 +8,7 @@ here.  The binding refuses to run when the library is not built.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from dataclasses import dataclass
 
@@ -520,10 +521,11 @@ def fps_sft(Y: torch.Tensor, A: torch.Tensor, cfg: Config, sft: SftDesc, *, slic
     status = torch.zeros(F, dtype=torch.int32, device=dev)
     S = None
     ws_ptr, ws_bytes = None, 0
+    q = cfg.n_sub * cfg.n_sym // math.gcd(cfg.n_sub, cfg.n_sym)  # lcm(N, M)
     if slices:
-        q = max(cfg.n_sub, cfg.n_sym)
         S = torch.empty((F, sft.n_dirs, 3, q), dtype=torch.complex64, device=dev)
-    else:
+    if not slices or q & (q - 1):
+        # the workspace holds the spectra, and for Q not a power of two the DFT's first pass
         need = sft_workspace_bytes(cfg, sft, F)
         if workspace is None or workspace.numel() < need:
             workspace = new_workspace(need, dev)

@@ -263,6 +263,21 @@ def test_sft_workspace_size():
     assert L.radar_fps_sft_workspace_size(ctypes.byref(cfg.desc()), ctypes.byref(s2), 1) == _al(2 * 3 * 1024 * 8)
 
 
+def test_sft_workspace_size_prime_factor_path():
+    # Table I's frame: N = 2048, M = 560, Q = lcm = 71680 = 2048 * 35
+    L = radar.lib()
+    cfg = radar.Config(2048, 560, 2048, 560, 2048, zc_root=7)
+    s = radar.sft_desc(8)
+    spectra = _al(8 * 3 * 71680 * 8)
+    # the spectra, the first pass's output, conj(z_k) for k < N, W_35^x
+    assert L.radar_fps_sft_workspace_size(ctypes.byref(cfg.desc()), ctypes.byref(s), 1) == \
+        2 * spectra + _al(2048 * 8) + _al(35 * 8)
+    # other sizes of the path are accepted: odd N (the k(k+1) phase of Eq. 23), N not a power of two
+    for n, m, root in ((45, 64, 7), (96, 40, 5), (1000, 64, 3), (2048, 560, 1)):
+        c = radar.Config(n, m, n, m, n, zc_root=root)
+        assert L.radar_fps_sft_workspace_size(ctypes.byref(c.desc()), ctypes.byref(s), 1) > 0, (n, m)
+
+
 @pytest.mark.parametrize("change,code", [
     (dict(k=0), radar.RADAR_E_ARG), (dict(k=65), radar.RADAR_E_ARG),
     (dict(n_dirs=0), radar.RADAR_E_ARG), (dict(n_dirs=17), radar.RADAR_E_ARG),
@@ -270,7 +285,12 @@ def test_sft_workspace_size():
     (dict(tol=0.0), radar.RADAR_E_ARG), (dict(flags=1), radar.RADAR_E_ARG),
     (dict(dir0=(0, 0)), radar.RADAR_E_ARG), (dict(dir0=(256, -64)), radar.RADAR_E_ARG),  # both vanish mod (N, M)
     (dict(n_sub=8), radar.RADAR_E_UNSUPPORTED), (dict(n_sym=8192), radar.RADAR_E_UNSUPPORTED),
-    (dict(n_sub=96), radar.RADAR_E_UNSUPPORTED), (dict(zc_root=4), radar.RADAR_E_NOT_COPRIME),
+    (dict(zc_root=4), radar.RADAR_E_NOT_COPRIME),
+    # Q = lcm(N, M) not a power of two: the prime-factor path's limits
+    (dict(n_sub=45, n_sym=63), radar.RADAR_E_UNSUPPORTED),       # Q = 315: power of two in Q below 16
+    (dict(n_sub=272, n_sym=304), radar.RADAR_E_UNSUPPORTED),     # odd part of Q = 17 * 19 > 255
+    (dict(n_sub=4096, n_sym=4095), radar.RADAR_E_UNSUPPORTED),   # Q above 131072
+    (dict(n_sub=96, zc_root=3), radar.RADAR_E_NOT_COPRIME),      # gcd(3, 96) = 3
     (dict(refine=True), radar.RADAR_E_ARG),
 ])
 def test_sft_validation_rejects(change, code):

@@ -173,3 +173,52 @@ def test_sft_status_bit_for_zero_symbol():
     say("sft status bits")
     _, st, _ = _run([f.Y], [A], _cfg(256, 64, 1), radar.sft_desc(3))
     assert st[0] & radar.ST_ZERO_SYMBOL
+
+
+# Frames whose Q = lcm(N, M) is not a power of two: the prime-factor path
+# (Q = P R, P-point passes and R-point DFTs, the recovery from global memory).
+# (N, M, root, K): Q = 480 = 32 x 15; Q = 2880 = 64 x 45 with odd N (the
+# k(k+1) phase of Eq. 23); Q = 8000 = 64 x 125; Table I's 2048 x 560,
+# Q = 71680 = 2048 x 35.
+GENERAL = [(96, 40, 5, 3), (45, 64, 7, 4), (1000, 64, 3, 5), (2048, 560, 7, 8)]
+
+
+@pytest.mark.parametrize("n,m,root,nt", GENERAL)
+def test_sft_general_q_noiseless_exact(n, m, root, nt):
+    spec = S.FrameSpec(n_sub=n, n_sym=m, qam=16, zc_root=root, n_targets=nt, noise=False, on_grid=True,
+                       rho_min=0, rho_max=max(1, n // 4), nu_abs_max=m // 2 - 1, min_sep=1.0)
+    f = S.make_frame(spec, 94, n + m)
+    say(f"sft noiseless {n}x{m} (Q = {n * m // np.gcd(n, m)}) K={nt}")
+    pk, _ = _compare([f.Y], [f.A], n, m, root, radar.sft_desc(nt), f"general-noiseless-{n}x{m}")
+    assert sorted((s, r) for s, r, *_ in pk[0]) == sorted((int(v), int(r)) for r, v in zip(f.rho, f.nu))
+    np.testing.assert_allclose(sorted(p for _, _, p, _, _ in pk[0]), sorted(n * m * np.abs(f.b) ** 2), rtol=1e-4)
+
+
+def test_sft_general_q_batch_and_status():
+    spec = S.FrameSpec(n_sub=96, n_sym=40, qam=16, zc_root=5, n_targets=3, snr_db=15.0, on_grid=True, rho_min=1,
+                       rho_max=30, nu_abs_max=18, min_sep=3.0)
+    frames = [S.make_frame(spec, 93, i) for i in range(3)]
+    say("sft general Q, 3 frames, strided rows")
+    pk, _ = _compare([f.Y for f in frames], [f.A for f in frames], 96, 40, 5, radar.sft_desc(3), "general-batch",
+                     ld=100)
+    pk1, _, _ = _run([frames[2].Y], [frames[2].A], _cfg(96, 40, 5), radar.sft_desc(3))
+    assert pk1[0] == pk[2]
+    A = frames[0].A.copy()
+    A[0, 0] = 0.0
+    _, st, _ = _run([frames[0].Y], [A], _cfg(96, 40, 5), radar.sft_desc(3))
+    assert st[0] & radar.ST_ZERO_SYMBOL
+
+
+@pytest.mark.parametrize("snr_db", [10.0, 20.0])
+def test_sft_table1_frames(snr_db):
+    # Table I: N = 2048 subcarriers, M = 560 symbols; eight off-grid Rayleigh
+    # targets inside the prefix's range box.  (At 0 dB per element the
+    # oracle's own decisions on such frames move under the 1e-5 perturbation:
+    # with 71680 bins per slice, noise bins sit at the threshold.)
+    spec = S.FrameSpec(n_sub=2048, n_sym=560, qam=16, zc_root=7, n_targets=8, snr_db=snr_db, on_grid=False,
+                       rho_min=1.0, rho_max=511.0, nu_abs_max=279.0, rayleigh=True, min_sep=3.0)
+    frames = [S.make_frame(spec, 99, i) for i in range(3)]
+    say(f"sft Table I frames (2048 x 560, Q = 71680), snr {snr_db}")
+    _, unstable = _compare([f.Y for f in frames], [f.A for f in frames], 2048, 560, 7, radar.sft_desc(8),
+                           f"tableI-{snr_db}", require_stable=False)
+    assert unstable <= 1
