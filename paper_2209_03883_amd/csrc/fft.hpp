@@ -155,6 +155,21 @@ struct TwLds {
   }
 };
 
+// The same LDS copy, but a stage's twiddles are read after the exchange
+// rather than before it: the prefetch then holds no registers across the
+// exchange (for kernels that keep much else live through the transform).
+template <class Layout>
+struct TwLdsLate : TwLds<Layout> {};
+
+template <class TS>
+struct TwFetchLate {
+  static constexpr bool value = false;
+};
+template <class Layout>
+struct TwFetchLate<TwLdsLate<Layout>> {
+  static constexpr bool value = true;
+};
+
 // Shape of the Stockham stage that starts at span NS.
 template <int L, int E, int NS>
 struct StagePlan {
@@ -237,7 +252,7 @@ __device__ __forceinline__ void fft_stages_tw(float2 (&v)[E], float2* lds, int t
     }
     if constexpr (!P::LAST) {
       StageTw<L, E, NS * R> next;
-      load_stage_tw<L, E, NS * R>(next, t, active, ts);
+      if constexpr (!TwFetchLate<TS>::value) load_stage_tw<L, E, NS * R>(next, t, active, ts);
       team_sync<T>();
       if (active) {
         if constexpr (T % 16 == 0) {
@@ -250,6 +265,7 @@ __device__ __forceinline__ void fft_stages_tw(float2 (&v)[E], float2* lds, int t
           for (int e = 0; e < E; ++e) v[e] = lds[lds_pad(t + T * e)];
         }
       }
+      if constexpr (TwFetchLate<TS>::value) load_stage_tw<L, E, NS * R>(next, t, active, ts);
       if constexpr (T > 64) {
         __syncthreads();
       } else {

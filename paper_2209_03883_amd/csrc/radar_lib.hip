@@ -18,6 +18,7 @@ __device__ float2 g_radar_tw[RADAR_TW_ENTRIES];
 
 #include "k_frame.hpp"
 #include "k_range_mx.hpp"
+#include "k_range_wide.hpp"
 #include "k_peaks.hpp"
 #include "k_peaks_only.hpp"
 #include "k_refine.hpp"
@@ -264,6 +265,18 @@ void launch_k3x4p_n(const radar::K3Args& a, int m_pad, int F, hipStream_t s) {
   }
   hipLaunchKernelGGL((radar::k3_range_power_x4p<N, PR, kStore, false>), dim3(grid), dim3(C::BLOCK), 0, s, a, total);
 }
+// the N = 2048 range kernel (FP32): persistent, one work-group per CU (its
+// LDS holds one)
+void launch_k3x4w(const radar::K3Args& a, int m_pad, int F, hipStream_t s) {
+  using C = radar::K3w<2048>;
+  const int total = F * m_pad;
+  int grid = (g_num_cus > 0 ? g_num_cus : 256) * g_tune.k3_mult;
+  if (grid * C::PAIRS > total) grid = (total + C::PAIRS - 1) / C::PAIRS;
+  if (a.refs)
+    hipLaunchKernelGGL((radar::k3_range_power_x4w<2048, true>), dim3(grid), dim3(C::BLOCK), 0, s, a, total);
+  else
+    hipLaunchKernelGGL((radar::k3_range_power_x4w<2048, false>), dim3(grid), dim3(C::BLOCK), 0, s, a, total);
+}
 // the matrix-core range kernel (N = 1024): one persistent work-group per CU
 template <radar::Prec PR, bool kStore = true>
 void launch_k3mx(const radar::K3Args& a, int m_pad, int F, hipStream_t s) {
@@ -310,7 +323,12 @@ void launch_k3x4_any(const radar::K3Args& a, int N, int m_pad, int F, hipStream_
     case 256: launch_k3x4p_n<256, PR>(a, m_pad, F, s); break;
     case 512: launch_k3x4p_n<512, PR>(a, m_pad, F, s); break;
     case 1024: launch_k3x4p_n<1024, PR>(a, m_pad, F, s); break;
-    case 2048: launch_k3x4_n<2048, PR>(a, m_pad, F, s); break;
+    case 2048:
+      if constexpr (PR == radar::Prec::FP32)
+        launch_k3x4w(a, m_pad, F, s);
+      else
+        launch_k3x4_n<2048, PR>(a, m_pad, F, s);
+      break;
     default: launch_k3x4_n<4096, PR>(a, m_pad, F, s); break;
   }
 }
@@ -1004,8 +1022,8 @@ int tune_group(radar_batch& b, BatchGroup& g, hipStream_t s) {
   const int N = d.n_sub;
   const bool persistent_k1 = N >= 256 && N <= 1024;
   const bool x4 = d.n_pad == 4 * N && 4 * d.n_cp <= N && N >= 256;
-  const bool x4p = x4 && N <= 1024;
   const bool fp32 = !(d.flags & (RADAR_FLAG_BF16X3 | RADAR_FLAG_FP16X3 | RADAR_FLAG_FP16));
+  const bool x4p = x4 && (N <= 1024 || (N == 2048 && fp32));  // a persistent range kernel
   std::vector<Tuning> cands(1);
   if (persistent_k1 || x4p) {
     Tuning t;
