@@ -39,16 +39,12 @@ __device__ __forceinline__ uint64_t make_key(uint32_t ord, uint32_t flat) {
   return ((uint64_t)ord << 32) | (uint64_t)(0xFFFFFFFFu - flat);
 }
 
-__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
-#pragma unroll
-  for (int m = 32; m > 0; m >>= 1) {
-    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m);
-    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m);
-    const uint64_t o = ((uint64_t)hi << 32) | lo;
-    v = o > v ? o : v;
-  }
-  return v;
-}
+// The device library's wavefront reduction (cross-lane moves within rows of
+// 16 lanes, then across rows, the result read from one lane into scalar
+// registers): no LDS round trips.  Every lane of the wavefront must be active.
+extern "C" __device__ __attribute__((const)) unsigned long long __ockl_wfred_max_u64(unsigned long long);
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) { return __ockl_wfred_max_u64(v); }
 
 // Work-group maximum; every thread gets the result.  `red` holds one slot per wave.
 __device__ __forceinline__ uint64_t block_max_u64(uint64_t v, uint64_t* red) {
@@ -73,6 +69,48 @@ __device__ __forceinline__ float block_max_f32(float v, float* red) {
   for (int i = 1; i < nwaves; ++i) r = fmaxf(r, red[i]);
   __syncthreads();
   return r;
+}
+
+// The k (<= 64) largest of n distinct keys key_at(j), j < n, by a 256-thread
+// work-group: each wavefront ranks its share (j = 64 w + lane + 256 q) in k
+// rounds of "largest key below the previous one" (no barriers), then
+// wavefront 0 ranks the 4 k survivors the same way.  out[0..k) receives the
+// keys in descending order, 0-padded; s_top holds 4 x 64 keys of scratch.
+// Every thread must call it (two barriers); out is valid after it returns.
+template <class KeyAt>
+__device__ __forceinline__ void block_topk(int n, int k, const KeyAt& key_at, uint64_t (*s_top)[64],
+                                           uint64_t* out) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  uint64_t last = ~0ull;
+  int i = 0;
+  for (; i < k; ++i) {
+    uint64_t best = 0;
+    for (int j = 64 * wave + lane; j < n; j += 256) {
+      const uint64_t key = key_at(j);
+      if (key < last && key > best) best = key;
+    }
+    best = wave_max_u64(best);
+    if (lane == 0) s_top[wave][i] = best;
+    if (best == 0) break;
+    last = best;
+  }
+  for (int q = i + 1 + lane; q < k; q += 64) s_top[wave][q] = 0;
+  __syncthreads();
+  if (wave == 0) {
+    last = ~0ull;
+    for (i = 0; i < k; ++i) {
+      uint64_t best = 0;
+      for (int j = lane; j < 4 * k; j += 64) {
+        const uint64_t key = s_top[j / k][j - (j / k) * k];
+        if (key < last && key > best) best = key;
+      }
+      best = wave_max_u64(best);
+      if (lane == 0) out[i] = best;
+      last = best;
+    }
+  }
+  __syncthreads();
 }
 
 // Row maxima of arbitrary periodograms (used when the range kernel did not
@@ -103,13 +141,17 @@ __global__ void __launch_bounds__(256) k_row_max(const float* P, int64_t p_strid
 // scanning.
 __global__ void __launch_bounds__(256) k_peak_threshold(const float* rowmax, int m_pad, int k, float* tau_out,
                                                         int32_t* list, int32_t* cnt_out, float slack) {
-  extern __shared__ uint32_t s_prof[];  // ord bits of profile peaks, 0 elsewhere; then the row maxima
-  __shared__ uint64_t red[4];
+  extern __shared__ uint32_t s_dyn[];  // the row maxima, then the indices of profile peaks
+  __shared__ uint64_t s_top[4][64];
+  __shared__ uint64_t s_best[64];
   __shared__ int s_cnt[4];
+  __shared__ int s_np;
   const int f = blockIdx.x;
   const int tid = threadIdx.x;
   const int mask = m_pad - 1;
-  float* m = reinterpret_cast<float*>(s_prof + m_pad);
+  float* m = reinterpret_cast<float*>(s_dyn);
+  uint32_t* pk = s_dyn + m_pad;
+  if (tid == 0) s_np = 0;
   {
     const float* g = rowmax + (int64_t)f * m_pad;
     for (int base = tid; base < m_pad; base += 8 * 256) {
@@ -122,28 +164,18 @@ __global__ void __launch_bounds__(256) k_peak_threshold(const float* rowmax, int
     }
   }
   __syncthreads();
+  // the profile peaks (rows whose maximum is >= both neighbours'), gathered
+  // in any order: the ranking below depends only on their keys
   for (int i = tid; i < m_pad; i += 256) {
     const float v = m[i];
-    s_prof[i] = (v >= m[(i - 1) & mask] && v >= m[(i + 1) & mask]) ? ord_bits(v) : 0u;
+    if (v >= m[(i - 1) & mask] && v >= m[(i + 1) & mask]) pk[atomicAdd(&s_np, 1)] = (uint32_t)i;
   }
   __syncthreads();
-  uint64_t last = ~0ull;
-  int found = 0;
-  for (; found < k; ++found) {
-    uint64_t best = 0;
-    for (int i = tid; i < m_pad; i += 256) {
-      const uint32_t o = s_prof[i];
-      if (o) {
-        const uint64_t key = make_key(o, (uint32_t)i);
-        if (key < last && key > best) best = key;
-      }
-    }
-    best = block_max_u64(best, red);
-    if (best == 0) break;
-    last = best;
-  }
-  float tau = found == k ? ord_value((uint32_t)(last >> 32)) : -__builtin_huge_valf();
-  if (found == k) tau -= fabsf(tau) * slack;
+  const int np = s_np;
+  block_topk(np, k, [&](int j) { const uint32_t i = pk[j]; return make_key(ord_bits(m[i]), i); }, s_top, s_best);
+  const uint64_t kth = s_best[k - 1];
+  float tau = kth ? ord_value((uint32_t)(kth >> 32)) : -__builtin_huge_valf();
+  if (kth) tau -= fabsf(tau) * slack;
 
   const int chunk = (m_pad + 255) / 256;
   const int lo = tid * chunk < m_pad ? tid * chunk : m_pad;
@@ -173,6 +205,24 @@ __global__ void __launch_bounds__(256) k_peak_threshold(const float* rowmax, int
   }
 }
 
+// Columns c0-1 .. c0+8 of a row (cyclic; c0 a multiple of 8, n_pad >= 8 a
+// power of two): from global memory as two 16-byte loads and two single
+// values, from LDS value by value.
+__device__ __forceinline__ void load_cols10(const RADAR_GLOBAL float* row, int c0, int n_pad, float (&a)[10]) {
+  const radar_v4 x = *(const RADAR_GLOBAL radar_v4*)(row + c0);
+  const radar_v4 y = *(const RADAR_GLOBAL radar_v4*)(row + c0 + 4);
+  a[0] = row[(c0 - 1) & (n_pad - 1)];
+  a[9] = row[(c0 + 8) & (n_pad - 1)];
+  a[1] = x.x, a[2] = x.y, a[3] = x.z, a[4] = x.w;
+  a[5] = y.x, a[6] = y.y, a[7] = y.z, a[8] = y.w;
+}
+__device__ __forceinline__ void load_cols10(const float* row, int c0, int n_pad, float (&a)[10]) {
+  a[0] = row[(c0 - 1) & (n_pad - 1)];
+  a[9] = row[(c0 + 8) & (n_pad - 1)];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) a[u + 1] = row[c0 + u];
+}
+
 // Step 3 for one listed row: its exact local maxima >= th among the rows
 // above (rm), at (r0) and below (rp), k best of them to out[0..k) (key 0
 // pads).  Called by every thread of the work-group (256 threads; it contains
@@ -182,43 +232,28 @@ template <class RowPtr>
 __device__ __forceinline__ void row_candidates(RowPtr rm, RowPtr r0, RowPtr rp, int n_pad, int k, float th,
                                                uint32_t flat0, uint32_t* s_ord, uint64_t* red, int* s_cnt,
                                                uint64_t* out) {
-  // eight columns per thread at a time, all nine values of each 3 x 3
-  // neighbourhood loaded before any test (unconditional loads, columns
-  // clamped in bounds; the rows are L2-resident), so the loads overlap
-  // instead of waiting one by one
-  for (int base = threadIdx.x; base < n_pad; base += 8 * (int)blockDim.x) {
-    float nb[8][9];
+  // eight contiguous columns per thread at a time: the three rows' values
+  // at columns c0-1 .. c0+8 are loaded once (two 16-byte loads and two
+  // single values per row, every load issued before any test), and each
+  // cell's 3 x 3 neighbourhood is read from them
+  int mine = 0;
+  for (int c0 = 8 * (int)threadIdx.x; c0 < n_pad; c0 += 8 * (int)blockDim.x) {
+    float a[3][10];
+    load_cols10(rm, c0, n_pad, a[0]);
+    load_cols10(r0, c0, n_pad, a[1]);
+    load_cols10(rp, c0, n_pad, a[2]);
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int r = base + u * (int)blockDim.x;
-      const int rc = r < n_pad ? r : 0;
-      const int rl = (rc - 1) & (n_pad - 1);
-      const int rr = (rc + 1) & (n_pad - 1);
-      nb[u][0] = r0[rc];
-      nb[u][1] = r0[rl];
-      nb[u][2] = r0[rr];
-      nb[u][3] = rm[rl];
-      nb[u][4] = rm[rc];
-      nb[u][5] = rm[rr];
-      nb[u][6] = rp[rl];
-      nb[u][7] = rp[rc];
-      nb[u][8] = rp[rr];
-    }
+      const float v = a[1][u + 1];
+      bool pk = v >= th;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int r = base + u * (int)blockDim.x;
-      if (r < n_pad) {
-        const float v = nb[u][0];
-        bool pk = v >= th;
-#pragma unroll
-        for (int q = 1; q < 9; ++q) pk = pk && v >= nb[u][q];
-        s_ord[r] = pk ? ord_bits(v) : 0u;
-      }
+      for (int q = 0; q < 3; ++q) pk = pk && v >= a[0][u + q] && v >= a[2][u + q];
+      pk = pk && v >= a[1][u] && v >= a[1][u + 2];
+      s_ord[c0 + u] = pk ? ord_bits(v) : 0u;
+      mine += pk ? 1 : 0;
     }
   }
   // how many candidates does the row hold?
-  int mine = 0;
-  for (int r = threadIdx.x; r < n_pad; r += blockDim.x) mine += s_ord[r] ? 1 : 0;
   __syncthreads();
   int incl = mine;
 #pragma unroll
@@ -237,8 +272,10 @@ __device__ __forceinline__ void row_candidates(RowPtr rm, RowPtr r0, RowPtr rp, 
   if (total <= k) {
     // few candidates: write them all (the merge ranks them), pad with 0
     int pos = before + incl - mine;
-    for (int r = threadIdx.x; r < n_pad; r += blockDim.x)
-      if (s_ord[r]) out[pos++] = make_key(s_ord[r], flat0 + (uint32_t)r);
+    for (int c0 = 8 * (int)threadIdx.x; c0 < n_pad; c0 += 8 * (int)blockDim.x)
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (s_ord[c0 + u]) out[pos++] = make_key(s_ord[c0 + u], flat0 + (uint32_t)(c0 + u));
     for (int q = total + (int)threadIdx.x; q < k; q += blockDim.x) out[q] = 0;
     i = k;  // nothing left to pad below
   } else {
@@ -277,7 +314,14 @@ __global__ void __launch_bounds__(256) k_peak_rows_listed(const float* P, int64_
   const int count = cnt[f];
   const float th = tau[f];
   const RADAR_GLOBAL float* base = gptr(refs ? refs[f].P : P + (int64_t)f * p_stride);
-  for (int j = blockIdx.x; j < count; j += gridDim.x) {
+  // a contiguous run of the (ascending) list per work-group: listed rows
+  // come in runs of neighbours, so the rows above and below one listed row
+  // are the listed rows next to it, read moments before by the same
+  // work-group (cache hits rather than HBM reads)
+  const int per = (count + (int)gridDim.x - 1) / (int)gridDim.x;
+  const int j0 = (int)blockIdx.x * per;
+  const int j1 = j0 + per < count ? j0 + per : count;
+  for (int j = j0; j < j1; ++j) {
     const int row = list[(int64_t)f * m_pad + j];
     const RADAR_GLOBAL float* rm = base + (int64_t)((row - 1) & (m_pad - 1)) * n_pad;
     const RADAR_GLOBAL float* r0 = base + (int64_t)row * n_pad;
@@ -287,51 +331,68 @@ __global__ void __launch_bounds__(256) k_peak_rows_listed(const float* P, int64_
   }
 }
 
-// Step 4: the k best keys over the scanned rows of a frame, one wavefront per
-// frame (grid F, 64 threads).  With inv_sum (threshold detection, Eq. 18) the
-// list stops at the first peak below eta = eta_factor * sum_l inv_sum[f][l];
-// the peaks come in descending P, so what is kept is exactly the top-k local
-// maxima at or above eta.
-__global__ void __launch_bounds__(64) k_peak_merge(const uint64_t* cand, const int32_t* cnt, int m_pad, int n_pad,
-                                                   int k, radar_peak* peaks, int32_t* n_peaks,
-                                                   const FrameRef* refs, const float* inv_sum, int M,
-                                                   float eta_factor) {
+// Step 4: the k best keys over the scanned rows of a frame (grid F, 256
+// threads).  The scanned rows leave k slots each, mostly 0-padding: the
+// nonzero keys are first gathered into LDS (up to kMergeCap of them; beyond
+// that the ranking reads the slots in global memory) and ranked there.  With
+// inv_sum (threshold detection, Eq. 18) the list stops at the first peak
+// below eta = eta_factor * sum_l inv_sum[f][l]; the peaks come in descending
+// P, so what is kept is exactly the top-k local maxima at or above eta.
+constexpr int kMergeCap = 4096;
+__global__ void __launch_bounds__(256) k_peak_merge(const uint64_t* cand, const int32_t* cnt, int m_pad, int n_pad,
+                                                    int k, radar_peak* peaks, int32_t* n_peaks,
+                                                    const FrameRef* refs, const float* inv_sum, int M,
+                                                    float eta_factor) {
+  __shared__ uint64_t s_key[kMergeCap];
+  __shared__ uint64_t s_top[4][64];
+  __shared__ uint64_t s_best[64];
+  __shared__ int s_n;
   const int f = blockIdx.x;
+  const int tid = threadIdx.x;
   const int count = cnt[f] * k;
   const uint64_t* c = cand + (int64_t)f * m_pad * k;
+  if (tid == 0) s_n = 0;
+  __syncthreads();
+  for (int j = tid; j < count; j += 256) {
+    const uint64_t key = c[j];
+    if (key) {
+      const int pos = atomicAdd(&s_n, 1);
+      if (pos < kMergeCap) s_key[pos] = key;
+    }
+  }
+  __syncthreads();
+  const int n = s_n;
+  if (n <= kMergeCap)
+    block_topk(n, k, [&](int j) { return s_key[j]; }, s_top, s_best);
+  else
+    block_topk(count, k, [&](int j) { return c[j]; }, s_top, s_best);
+  if (tid >= 64) return;
   float eta = -__builtin_huge_valf();
   if (inv_sum) {
     float acc = 0.0f;  // fixed order: lane-strided partial sums, then a butterfly
-    for (int l = threadIdx.x; l < M; l += 64) acc += inv_sum[(int64_t)f * M + l];
+    for (int l = tid; l < M; l += 64) acc += inv_sum[(int64_t)f * M + l];
 #pragma unroll
     for (int m = 32; m > 0; m >>= 1) acc += __shfl_xor(acc, m);
     eta = (refs ? refs[f].eta_factor : eta_factor) * acc;
   }
-  uint64_t last = ~0ull;
-  int i = 0;
-  for (; i < k; ++i) {
-    uint64_t best = 0;
-    for (int j = threadIdx.x; j < count; j += 64) {
-      const uint64_t key = c[j];
-      if (key < last && key > best) best = key;
-    }
-    best = wave_max_u64(best);
-    if (best == 0) break;
-    const float p = ord_value((uint32_t)(best >> 32));
-    if (p < eta) break;
-    if (threadIdx.x == 0) {
-      const uint32_t flat = 0xFFFFFFFFu - (uint32_t)best;
-      radar_peak pk;
-      pk.s = (int32_t)(flat / (uint32_t)n_pad) - (m_pad >> 1);
-      pk.r = (int32_t)(flat % (uint32_t)n_pad);
-      pk.p = p;
-      pk.s_off = 0.0f;
-      pk.r_off = 0.0f;
-      (refs ? refs[f].peaks : peaks + (int64_t)f * k)[i] = pk;
-    }
-    last = best;
+  // lane i emits the i-th best; the kept peaks are a prefix (keys and values
+  // both descend)
+  const uint64_t best = tid < k ? s_best[tid] : 0;
+  const float p = ord_value((uint32_t)(best >> 32));
+  const bool keep = best != 0 && !(p < eta);
+  const uint64_t kept = __ballot(keep);
+  const int n_kept = (int)__builtin_popcountll(kept);
+  if (tid < n_kept) {
+    const uint32_t flat = 0xFFFFFFFFu - (uint32_t)best;
+    radar_peak pk;
+    pk.s = (int32_t)(flat / (uint32_t)n_pad) - (m_pad >> 1);
+    pk.r = (int32_t)(flat % (uint32_t)n_pad);
+    pk.p = p;
+    pk.s_off = 0.0f;
+    pk.r_off = 0.0f;
+    (refs ? refs[f].peaks : peaks + (int64_t)f * k)[tid] = pk;
   }
-  if (threadIdx.x == 0) *(refs ? refs[f].n_peaks : n_peaks + f) = i;
+  if (tid == 0) *(refs ? refs[f].n_peaks : n_peaks + f) = n_kept;
 }
 
 }  // namespace radar

@@ -21,13 +21,14 @@
 //           |g[r]|^2 (Sec. IV-A: padding the range IDFT by four interleaves
 //           four phase-shifted N-point IDFTs).
 // phase 0   the three-tap filter of the taps, as for N <= 1024.
-// stores    a wave holds phases 1 and 2 of its 16 cells per lane through the
-//           phase-3 transform, so each four-phase group leaves in one
-//           16-byte store.  The two waves of a row run the same instructions
-//           in step and write alternate groups of every line at nearly the
-//           same time.  (One wave doing both halves in turn left half-written
-//           lines in the caches for a third of a row's time, long enough to
-//           be evicted as partial lines: measured 1.7x slower.)
+// stores    a wave holds the four phases of its 16 cells per lane, so each
+//           four-phase group leaves in one 16-byte store.  The two waves of a
+//           row run in step and write alternate groups of every line at
+//           nearly the same time.  (One wave doing both
+//           halves in turn left half-written lines in the caches for a third
+//           of a row's time, long enough to be evicted as partial lines:
+//           measured 1.7x slower; non-temporal stores, which skip that
+//           joining, as slow.)
 // LDS       per work-group: the two length-H plans' stage blocks, W_{4N}^{k b}
 //           (b = 1..3) and W_N^k for k < H (51 KB); per wave an exchange
 //           region and the row's taps.
@@ -166,17 +167,15 @@ __device__ __forceinline__ void k3w_combine(float2 (&xl)[K3w<N>::E], float2 (&xh
   }
 }
 
-// Half Hf of one row (the cells 4 r + b, r = 2 s + Hf): phases 1 and 2 held,
-// then phase 3 and the phase-0 filter, each four-phase group in one 16-byte
-// store.  `next()` runs before the stores.  Returns the wave's maximum.
-template <int N, int Hf, class Sink, class Next>
-__device__ __forceinline__ float k3w_half(const float2 (&xl)[K3w<N>::E], const float2 (&xh)[K3w<N>::E], float2* lds,
-                                          const float2* ub, int t, const float2* tab, float c0, float c1,
-                                          const Sink& sink, const Next& next) {
+// Half Hf of one row (the cells 4 r + b, r = 2 s + Hf): |g|^2 of phases 1,
+// 2 and 3 for the lane's 16 values of s, left in p1, p2, p3.
+template <int N, int Hf>
+__device__ __forceinline__ void k3w_half(const float2 (&xl)[K3w<N>::E], const float2 (&xh)[K3w<N>::E], float2* lds,
+                                         const float2* tab, int t, float (&p1)[K3w<N>::E], float (&p2)[K3w<N>::E],
+                                         float (&p3)[K3w<N>::E]) {
   using C = K3w<N>;
   constexpr int E = C::E;
   const TwLdsLate<typename C::Inv> tw_inv{{tab}};
-  float p1[E], p2[E];
   {
     float2 gv[E];
     k3w_phase<N, Hf, 1>(gv, xl, xh, lds, tab, t, tw_inv);
@@ -189,35 +188,13 @@ __device__ __forceinline__ float k3w_half(const float2 (&xl)[K3w<N>::E], const f
 #pragma unroll
     for (int e = 0; e < E; ++e) p2[e] = cabs2(gv[e]);
   }
-  float mx = 0.0f;
   {
     float2 gv[E];
     k3w_phase<N, Hf, 3>(gv, xl, xh, lds, tab, t, tw_inv);
-    next();
-    t = k3w_lane(t);
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int r1 = 2 * (t + 64 * e) + Hf;
-      const float p0 = cabs2(phase0_filter<N>(ub, r1, c0, c1));
-      const float p3 = cabs2(gv[e]);
-      sink.store4(4 * r1, p0, p1[e], p2[e], p3);
-      mx = fmaxf(fmaxf(fmaxf(fmaxf(mx, p0), p1[e]), p2[e]), p3);
-    }
+    for (int e = 0; e < E; ++e) p3[e] = cabs2(gv[e]);
   }
-#pragma unroll
-  for (int m = 32; m > 0; m >>= 1) mx = fmaxf(mx, __shfl_xor(mx, m));
-  return mx;
 }
-
-// P rows by ordinary 16-byte stores: the two waves of a row write alternate
-// 16-byte groups of every line at nearly the same time, and the caches join
-// them before the line goes to HBM.
-struct RowToGlobalJoined {
-  RADAR_GLOBAL float* dst;
-  __device__ __forceinline__ void store4(int i, float a, float b, float c, float d) const {
-    gstore4(dst + i, a, b, c, d);
-  }
-};
 
 // kRefs: P row pointers from the batch job table.  The work-group's waves
 // run in step (every loop trip holds the same barriers for all of them; a
@@ -252,6 +229,8 @@ __global__ void __launch_bounds__(K3w<N>::BLOCK) k3_range_power_x4w(K3Args a, in
       k3w_put_taps<N>(ub, uv, a.n_cp, t0);
     }
   }
+  float mx_prev = 0.0f;  // this wave's maximum of its last row (row_prev)
+  int row_prev = -1;
   for (int base = blockIdx.x * C::PAIRS; base < total_rows; base += stride) {
     const int grow = base + pair;
     const bool active = grow < total_rows;  // wave-uniform
@@ -268,6 +247,9 @@ __global__ void __launch_bounds__(K3w<N>::BLOCK) k3_range_power_x4w(K3Args a, in
       for (int e = 0; e < E; ++e) lds[t + 64 * e] = own[e];
     }
     __syncthreads();
+    // the previous row's maximum (wave 1 wrote its half's before this barrier
+    // and writes again only after the next one)
+    if (hf == 0 && t0 == 0 && row_prev >= 0) a.rowmax[row_prev] = fmaxf(mx_prev, s_max[pair]);
     float2 xl[E], xh[E];  // E_0 and E_1, both read back from the pair's regions
     if (active) {
       t = k3w_lane(t);
@@ -278,27 +260,42 @@ __global__ void __launch_bounds__(K3w<N>::BLOCK) k3_range_power_x4w(K3Args a, in
       }
     }
     __syncthreads();  // both regions are free for the transforms
-    float mx = 0.0f;
+    float p0[E], p1[E], p2[E], p3[E];
     if (active) {
       k3w_combine<N>(xl, xh, tab, t, wr);
-      const int gnext = grow + stride < total_rows ? grow + stride : grow;
-      const auto next = [&] { k3w_load_taps<N>(uv, a.U + (int64_t)gnext * a.n_cp, a.n_cp, t); };
-      const auto* crefs = (const __attribute__((address_space(4))) FrameRef*)a.refs;
-      const RowToGlobalJoined sink{gptr(kRefs ? crefs[f].P : a.P + (int64_t)f * a.p_stride) + (int64_t)row * (4 * N)};
       if (hf == 0)
-        mx = k3w_half<N, 0>(xl, xh, lds, ub, t, tab, c0, c1, sink, next);
+        k3w_half<N, 0>(xl, xh, lds, tab, t, p1, p2, p3);
       else
-        mx = k3w_half<N, 1>(xl, xh, lds, ub, t, tab, c0, c1, sink, next);
+        k3w_half<N, 1>(xl, xh, lds, tab, t, p1, p2, p3);
+      // the next row's taps, loaded while this row is stored
+      const int gnext = grow + stride < total_rows ? grow + stride : grow;
+      k3w_load_taps<N>(uv, a.U + (int64_t)gnext * a.n_cp, a.n_cp, t);
+      t = k3w_lane(t);
+      float mx = 0.0f;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        p0[e] = cabs2(phase0_filter<N>(ub, 2 * (t + 64 * e) + hf, c0, c1));
+        mx = fmaxf(fmaxf(fmaxf(fmaxf(mx, p0[e]), p1[e]), p2[e]), p3[e]);
+      }
+#pragma unroll
+      for (int m = 32; m > 0; m >>= 1) mx = fmaxf(mx, __shfl_xor(mx, m));
+      // the row maximum: wave 1 leaves its half's in LDS, wave 0 combines
+      // it with its own after the next trip's first barrier
       if (hf == 1 && t0 == 0) s_max[pair] = mx;
-    }
-    __syncthreads();
-    if (active) {
-      if (hf == 0 && t0 == 0) a.rowmax[grow] = fmaxf(mx, s_max[pair]);
+      mx_prev = mx;
+      row_prev = grow;
+      const auto* crefs = (const __attribute__((address_space(4))) FrameRef*)a.refs;
+      RADAR_GLOBAL float* dst = gptr(kRefs ? crefs[f].P : a.P + (int64_t)f * a.p_stride) + (int64_t)row * (4 * N);
+      t = k3w_lane(t);
+#pragma unroll
+      for (int e = 0; e < E; ++e) gstore4(dst + 4 * (2 * (t + 64 * e) + hf), p0[e], p1[e], p2[e], p3[e]);
       // the next row's tap writes follow this row's reads of ub
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       k3w_put_taps<N>(ub, uv, a.n_cp, t0);
     }
   }
+  __syncthreads();
+  if (hf == 0 && t0 == 0 && row_prev >= 0) a.rowmax[row_prev] = fmaxf(mx_prev, s_max[pair]);
 }
 
 }  // namespace radar

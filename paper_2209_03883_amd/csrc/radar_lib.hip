@@ -158,6 +158,7 @@ struct Tuning {
   int k1_mult = 1;         // persistent taps kernel: work-groups per CU
   int k3_mult = 1;         // persistent range kernel: work-groups per CU
   bool k3_generic = false; // use the one-team-per-row range kernel instead of the four-phase one
+  float ms = 0.0f;         // measured time of one pass of the group with these settings (0: not measured)
 };
 thread_local Tuning g_tune;
 int g_num_cus = 0;  // compute units of the device, set by radar_init
@@ -604,7 +605,7 @@ int enqueue_peaks(const float* P, int64_t p_stride, int m_pad, int n_pad, int F,
                        p_stride, m_pad, n_pad, k, tau, list, cnt, cand, refs);
   }
   RADAR_HIP_CHECK(hipGetLastError());
-  hipLaunchKernelGGL(radar::k_peak_merge, dim3(F), dim3(64), 0, s, cand, cnt, m_pad, n_pad, k, peaks, n_peaks,
+  hipLaunchKernelGGL(radar::k_peak_merge, dim3(F), dim3(256), 0, s, cand, cnt, m_pad, n_pad, k, peaks, n_peaks,
                      refs, inv_sum, M, eta_factor);
   RADAR_HIP_CHECK(hipGetLastError());
   timer_close(RADAR_STAGE_PEAKS, slot, s);
@@ -1036,7 +1037,9 @@ int tune_group(radar_batch& b, BatchGroup& g, hipStream_t s) {
     t.k3_generic = true;
     cands.push_back(t);
   }
-  if (cands.size() > 1) {
+  {
+    // every candidate is timed (a single one too: the time balances the
+    // concurrent branches of the captured batch)
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return RADAR_E_HIP;
     float best = 1e30f;
@@ -1054,6 +1057,7 @@ int tune_group(radar_batch& b, BatchGroup& g, hipStream_t s) {
       if (ms < best) {
         best = ms;
         pick = t;
+        pick.ms = ms / 3.0f;
       }
     }
     (void)hipEventDestroy(e0);
@@ -1567,8 +1571,12 @@ int radar_batch_create(const radar_frame_job* jobs, int32_t n_jobs, int32_t flag
         if (hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess) rc = RADAR_E_HIP;
       std::vector<int> order(b->groups.size());
       for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
-      std::stable_sort(order.begin(), order.end(),
-                       [&](int x, int y) { return b->groups[x].work > b->groups[y].work; });
+      // the measured time of each group when the batch was tuned, else its
+      // algorithmic bytes
+      bool timed = true;
+      for (const auto& g : b->groups) timed = timed && g.tune.ms > 0.0f;
+      const auto cost = [&](int x) { return timed ? (double)b->groups[x].tune.ms : b->groups[x].work; };
+      std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
       g_capturing = true;
       if (rc == RADAR_OK && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
         rc = RADAR_E_HIP;
@@ -1579,7 +1587,7 @@ int radar_batch_create(const radar_frame_job* jobs, int32_t n_jobs, int32_t flag
       for (int gi : order) {
         if (rc != RADAR_OK) break;
         const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        load[j] += b->groups[gi].work;
+        load[j] += cost(gi);
         rc = enqueue_group(*b, b->groups[gi], br[j]);
       }
       for (int i = 0; i < nb && rc == RADAR_OK; ++i) {
