@@ -208,8 +208,8 @@ def time_extras(radar, torch, Yd, Ad, cfg, ws, peaks, n_peaks, status, stream, B
     out["peaks_only_stage_us_per_frame"] = {k: st[k][0] / max(st[k][1], 1) * 1e3 / B for k in ("range", "peaks")}
 
     # dense ZC precoding (Eq. 24 read literally): frames whose transmitter
-    # applied the dense precoding; the FP64 precoding-and-division kernel runs
-    # inside the taps stage
+    # applied the dense precoding; the taps kernel folds in its FP64 transform
+    # and the division
     from synth import frames as S
     from synth import frames_torch as G
 

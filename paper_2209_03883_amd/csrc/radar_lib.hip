@@ -109,7 +109,7 @@ struct FrameWs {
   size_t taps, U;
   PeakWs pk;
   size_t inv_sum;  // [F][M] floats with RADAR_FLAG_THRESHOLD (else an empty region)
-  size_t H;        // [F][M][N] LS estimate with RADAR_ZC_DENSE (else an empty region)
+  size_t H;        // [F][M][N] LS estimate with RADAR_ZC_DENSE at N outside 256 .. 1024 (else empty)
   size_t total;
 };
 
@@ -121,7 +121,10 @@ FrameWs frame_ws_layout(const radar_frame_desc* d, int n_frames, int k) {
   w.pk = peak_ws_layout(d->m_pad, n_frames, k, w.U + align256(F * d->m_pad * d->n_cp * sizeof(float2)));
   w.inv_sum = w.pk.total;
   w.H = w.inv_sum + ((d->flags & RADAR_FLAG_THRESHOLD) ? align256(F * d->n_sym * sizeof(float)) : 0);
-  w.total = w.H + (d->zc_mode == RADAR_ZC_DENSE ? align256(F * d->n_sym * (size_t)d->n_sub * sizeof(float2)) : 0);
+  // the estimate passes through HBM only where the taps kernel does not
+  // take the dense precoding itself
+  const bool h_in_hbm = d->zc_mode == RADAR_ZC_DENSE && (d->n_sub < 256 || d->n_sub > 1024);
+  w.total = w.H + (h_in_hbm ? align256(F * d->n_sym * (size_t)d->n_sub * sizeof(float2)) : 0);
   return w;
 }
 
@@ -234,6 +237,15 @@ void launch_k1p_n(const radar::K1Args& a, int M, int F, hipStream_t s) {
   int grid = (g_num_cus > 0 ? g_num_cus : 256) * g_tune.k1_mult;
   if (grid * C::WAVES > total) grid = (total + C::WAVES - 1) / C::WAVES;
   hipLaunchKernelGGL(radar::k1_taps_p<N>, dim3(grid), dim3(C::BLOCK), 0, s, a, total);
+}
+// the taps stage with the dense precoding folded in (N = 256 .. 1024)
+template <int N>
+void launch_k1d_n(const radar::K1Args& a, int M, int F, hipStream_t s) {
+  using C = radar::K1d<N>;
+  const int total = (int)((int64_t)F * M / C::ROWS);
+  int grid = (g_num_cus > 0 ? g_num_cus : 256) * g_tune.k1_mult;
+  if (grid * C::WAVES > total) grid = (total + C::WAVES - 1) / C::WAVES;
+  hipLaunchKernelGGL(radar::k1_taps_dense<N>, dim3(grid), dim3(C::BLOCK), 0, s, a, total);
 }
 template <int N>
 void launch_dense_n(const radar::DenseArgs& a, hipStream_t s) {
@@ -443,37 +455,47 @@ int enqueue_transforms(const radar_frame_desc* d, int F, const float2* in, const
   a1.inv_sum = inv_sum;
   a1.tap_w = d->tap_weights;
   int slot = timer_open(RADAR_STAGE_TAPS, s);
-  if (dense) {
-    // FP64 precoding and division first; the taps kernel then reads the estimate
-    radar::DenseArgs ad{};
-    ad.Y = in;
-    ad.A = A;
-    ad.ld = d->ld;
-    ad.frame_stride = frame_stride;
-    ad.refs = refs;
-    ad.status = status;
-    ad.H = reinterpret_cast<float2*>(ws + w.H);
-    ad.inv_sum = inv_sum;
-    ad.M = M;
-    ad.total = F * M;
-    ad.zc_root = a1.zc_root;
-    ad.zc_shift = a1.zc_shift;
+  if (dense && N >= 256 && N <= 1024) {
+    // the precoding transform inside the taps kernel: the LS estimate stays on chip
+    switch (N) {
+      case 256: launch_k1d_n<256>(a1, M, F, s); break;
+      case 512: launch_k1d_n<512>(a1, M, F, s); break;
+      default: launch_k1d_n<1024>(a1, M, F, s); break;
+    }
+  } else {
+    if (dense) {
+      // other sizes: the FP64 precoding and division first, the taps kernel
+    // then reads the estimate
+      radar::DenseArgs ad{};
+      ad.Y = in;
+      ad.A = A;
+      ad.ld = d->ld;
+      ad.frame_stride = frame_stride;
+      ad.refs = refs;
+      ad.status = status;
+      ad.H = reinterpret_cast<float2*>(ws + w.H);
+      ad.inv_sum = inv_sum;
+      ad.M = M;
+      ad.total = F * M;
+      ad.zc_root = a1.zc_root;
+      ad.zc_shift = a1.zc_shift;
 #define KD_CALL(n) launch_dense_n<n>(ad, s)
-    RADAR_SIZE_SWITCH(N, KD_CALL)
+      RADAR_SIZE_SWITCH(N, KD_CALL)
 #undef KD_CALL
-    RADAR_HIP_CHECK(hipGetLastError());
-    a1.Y = ad.H;
-    a1.A = nullptr;
-    a1.ld = N;
-    a1.frame_stride = (int64_t)M * N;
-    a1.from_h = 1;
-    a1.refs = nullptr;
-    a1.status = nullptr;
-    a1.inv_sum = nullptr;
-  }
+      RADAR_HIP_CHECK(hipGetLastError());
+      a1.Y = ad.H;
+      a1.A = nullptr;
+      a1.ld = N;
+      a1.frame_stride = (int64_t)M * N;
+      a1.from_h = 1;
+      a1.refs = nullptr;
+      a1.status = nullptr;
+      a1.inv_sum = nullptr;
+    }
 #define K1_CALL(n) launch_k1_n<n>(a1, M, F, s)
-  RADAR_SIZE_SWITCH(N, K1_CALL)
+    RADAR_SIZE_SWITCH(N, K1_CALL)
 #undef K1_CALL
+  }
   timer_close(RADAR_STAGE_TAPS, slot, s);
   RADAR_HIP_CHECK(hipGetLastError());
 

@@ -72,9 +72,10 @@ def test_small_workload_dense(snr_db):
         _check(P[f], pk[f], frame, cfg, 3, f"frame {f}")
 
 
-# (N, M, N', M', N_cp, root, shift): the generic taps kernel (N < 256, N >= 2048)
-# and the persistent one (256 <= N <= 1024); roots and shifts beyond 2N and
-# negative shifts exercise the reductions modulo 2N^2
+# (N, M, N', M', N_cp, root, shift): the FP64 precoding kernel followed by the
+# generic taps kernel (N < 256, N >= 2048), and the taps kernel that folds the
+# precoding in (256 <= N <= 1024); roots and shifts beyond 2N and negative
+# shifts exercise the reductions modulo 2N^2
 DENSE_SHAPES = [
     (16, 16, 64, 32, 16, 3, 0),
     (64, 32, 256, 64, 16, 5, -7),
