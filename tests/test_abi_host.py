@@ -195,9 +195,13 @@ def test_dense_precoding_validation():
     L = radar.lib()
     ok = radar.Config(256, 64, 1024, 256, 32, zc_root=7, zc_shift=-3, zc_dense=True)
     assert ok.desc().zc_mode == radar.ZC_DENSE
-    # plus the FP64 stage's LS estimate, [F][M][N] complex64
-    assert L.radar_frame_workspace_size(ctypes.byref(ok.desc()), 2, 3) == (
-        _ws(radar.Config(256, 64, 1024, 256, 32), 2, 3) + _al(2 * 64 * 256 * 8))
+    # 256 <= N <= 1024: the taps kernel folds the precoding in, no extra region
+    assert L.radar_frame_workspace_size(ctypes.byref(ok.desc()), 2, 3) == _ws(
+        radar.Config(256, 64, 1024, 256, 32), 2, 3)
+    # other N: plus the FP64 stage's LS estimate, [F][M][N] complex64
+    small = radar.Config(128, 64, 512, 256, 32, zc_root=7, zc_shift=-3, zc_dense=True)
+    assert L.radar_frame_workspace_size(ctypes.byref(small.desc()), 2, 3) == (
+        _ws(radar.Config(128, 64, 512, 256, 32), 2, 3) + _al(2 * 64 * 128 * 8))
     even = radar.Config(256, 64, 1024, 256, 32, zc_root=4, zc_dense=True)
     d = even.desc()
     assert L.radar_frame_workspace_size(ctypes.byref(d), 1, 3) == 0
