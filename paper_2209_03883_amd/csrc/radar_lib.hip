@@ -110,8 +110,19 @@ struct FrameWs {
   PeakWs pk;
   size_t inv_sum;  // [F][M] floats with RADAR_FLAG_THRESHOLD (else an empty region)
   size_t H;        // [F][M][N] LS estimate with RADAR_ZC_DENSE at N outside 256 .. 1024 (else empty)
+  size_t ring;     // peaks only: the recompute kernel's row rings
   size_t total;
 };
+
+bool peaks_only_supported(const radar_frame_desc* d);
+
+// Peaks only: work-groups of the recompute kernel (two per frame up to one
+// per CU of the largest part) and the bytes of their row rings (8 wavefronts,
+// each 1024/N + 2 rows of 4N floats).
+int window_blocks(int n_frames) { return std::min(256, 2 * n_frames); }
+size_t window_ring_bytes(int N, int n_frames) {
+  return (size_t)window_blocks(n_frames) * 8 * (size_t)(1024 / N + 2) * (size_t)(4 * N) * sizeof(float);
+}
 
 FrameWs frame_ws_layout(const radar_frame_desc* d, int n_frames, int k) {
   FrameWs w;
@@ -124,7 +135,17 @@ FrameWs frame_ws_layout(const radar_frame_desc* d, int n_frames, int k) {
   // the estimate passes through HBM only where the taps kernel does not
   // take the dense precoding itself
   const bool h_in_hbm = d->zc_mode == RADAR_ZC_DENSE && (d->n_sub < 256 || d->n_sub > 1024);
-  w.total = w.H + (h_in_hbm ? align256(F * d->n_sym * (size_t)d->n_sub * sizeof(float2)) : 0);
+  w.ring = w.H + (h_in_hbm ? align256(F * d->n_sym * (size_t)d->n_sub * sizeof(float2)) : 0);
+  w.total = w.ring;
+  // the rings live in the taps region, dead once the Doppler stage has read
+  // it, unless the refinement reads the taps later or the region is too small
+  if (peaks_only_supported(d)) {
+    const size_t ring = window_ring_bytes(d->n_sub, n_frames);
+    if ((d->flags & RADAR_FLAG_REFINE) || ring > w.U - w.taps)
+      w.total += align256(ring);
+    else
+      w.ring = w.taps;
+  }
   return w;
 }
 
@@ -357,27 +378,24 @@ void launch_k3x4p_rowmax(const radar::K3Args& a, int N, int m_pad, int F, hipStr
   }
 }
 template <radar::Prec PR>
-void launch_rows_recompute(const radar::K3Args& a, int N, int F, int k, const float* tau, const int32_t* list,
-                           const int32_t* cnt, uint64_t* cand, hipStream_t s) {
-  // one work-group per CU in all (each holds a CU's LDS), each looping over
-  // list entries of its frame, so its twiddle tables are built once per many
-  // rows rather than once per row
-  const int cus = g_num_cus > 0 ? g_num_cus : 256;
-  int groups = (cus + F - 1) / F;
-  if (groups > 64) groups = 64;
-  if (groups > a.m_pad) groups = a.m_pad;
+void launch_rows_window(const radar::K3Args& a, int N, int F, int k, const float* tau, const int32_t* list,
+                        const int32_t* cnt, uint64_t* cand, float* ring, hipStream_t s) {
+  // the range kernel's work-group and LDS, one per CU, each building its
+  // tables once and then taking (frame, share) items in turn
+  const int blocks = window_blocks(F);
+  const int per_frame = std::max(1, blocks / F);
   switch (N) {
     case 256:
-      hipLaunchKernelGGL((radar::k_peak_rows_recompute<256, PR>), dim3(groups, F), dim3(256), 0, s, a, k, tau, list,
-                         cnt, cand);
+      hipLaunchKernelGGL((radar::k_peak_rows_window<256, PR>), dim3(blocks), dim3(radar::K3p<256>::BLOCK), 0, s, a,
+                         F, per_frame, k, tau, list, cnt, cand, ring);
       break;
     case 512:
-      hipLaunchKernelGGL((radar::k_peak_rows_recompute<512, PR>), dim3(groups, F), dim3(256), 0, s, a, k, tau, list,
-                         cnt, cand);
+      hipLaunchKernelGGL((radar::k_peak_rows_window<512, PR>), dim3(blocks), dim3(radar::K3p<512>::BLOCK), 0, s, a,
+                         F, per_frame, k, tau, list, cnt, cand, ring);
       break;
     default:
-      hipLaunchKernelGGL((radar::k_peak_rows_recompute<1024, PR>), dim3(groups, F), dim3(256), 0, s, a, k, tau,
-                         list, cnt, cand);
+      hipLaunchKernelGGL((radar::k_peak_rows_window<1024, PR>), dim3(blocks), dim3(radar::K3p<1024>::BLOCK), 0, s,
+                         a, F, per_frame, k, tau, list, cnt, cand, ring);
       break;
   }
 }
@@ -598,7 +616,7 @@ int enqueue_refine(const radar_frame_desc* d, int F, int k, const float2* taps, 
 int enqueue_peaks(const float* P, int64_t p_stride, int m_pad, int n_pad, int F, int k, const PeakWs& w, char* ws,
                   radar_peak* peaks, int32_t* n_peaks, hipStream_t s, const radar::FrameRef* refs = nullptr,
                   const float* inv_sum = nullptr, int M = 0, float eta_factor = 0.0f,
-                  const radar_frame_desc* d = nullptr, const float2* U = nullptr) {
+                  const radar_frame_desc* d = nullptr, const float2* U = nullptr, float* ring = nullptr) {
   float* rowmax = reinterpret_cast<float*>(ws + w.rowmax);
   float* tau = reinterpret_cast<float*>(ws + w.tau);
   int32_t* cnt = reinterpret_cast<int32_t*>(ws + w.cnt);
@@ -612,15 +630,15 @@ int enqueue_peaks(const float* P, int64_t p_stride, int m_pad, int n_pad, int F,
                      tau, list, cnt, slack);
   RADAR_HIP_CHECK(hipGetLastError());
   if (!P && !refs) {
-    if (!d || !U) return RADAR_E_ARG;
+    if (!d || !U || !ring) return RADAR_E_ARG;
     const radar::K3Args a3 = range_args(d, U, nullptr, 0, rowmax, nullptr);
     const radar::Prec prec = prec_of(d);
     if (prec == radar::Prec::BF16X3)
-      launch_rows_recompute<radar::Prec::BF16X3>(a3, d->n_sub, F, k, tau, list, cnt, cand, s);
+      launch_rows_window<radar::Prec::BF16X3>(a3, d->n_sub, F, k, tau, list, cnt, cand, ring, s);
     else if (prec == radar::Prec::FP16X3)
-      launch_rows_recompute<radar::Prec::FP16X3>(a3, d->n_sub, F, k, tau, list, cnt, cand, s);
+      launch_rows_window<radar::Prec::FP16X3>(a3, d->n_sub, F, k, tau, list, cnt, cand, ring, s);
     else
-      launch_rows_recompute<radar::Prec::FP32>(a3, d->n_sub, F, k, tau, list, cnt, cand, s);
+      launch_rows_window<radar::Prec::FP32>(a3, d->n_sub, F, k, tau, list, cnt, cand, ring, s);
   } else {
     const int groups = m_pad < 32 ? m_pad : 32;
     hipLaunchKernelGGL(radar::k_peak_rows_listed, dim3(groups, F), dim3(256), n_pad * sizeof(uint32_t), s, P,
@@ -1331,7 +1349,8 @@ int radar_frame_process(const radar_frame_desc* d, int32_t n_frames, const radar
   const bool thr = (d->flags & RADAR_FLAG_THRESHOLD) != 0;
   rc = enqueue_peaks(P, p_frame_stride, d->m_pad, d->n_pad, n_frames, k, w.pk, wsb, peaks, n_peaks, s, nullptr,
                      thr ? reinterpret_cast<const float*>(wsb + w.inv_sum) : nullptr, d->n_sym,
-                     thr ? eta_factor_of(d) : 0.0f, d, reinterpret_cast<const float2*>(wsb + w.U));
+                     thr ? eta_factor_of(d) : 0.0f, d, reinterpret_cast<const float2*>(wsb + w.U),
+                     reinterpret_cast<float*>(wsb + w.ring));
   if (rc != RADAR_OK || !(d->flags & RADAR_FLAG_REFINE)) return rc;
   return enqueue_refine(d, n_frames, k, reinterpret_cast<const float2*>(wsb + w.taps), peaks, n_peaks, nullptr, s);
 }

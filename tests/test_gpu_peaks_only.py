@@ -2,8 +2,8 @@
 NULL) against the same call with P written, through the C ABI.
 
 With P NULL the range stage keeps only its row maxima and the peak search
-recomputes each listed row and its two neighbours with the range stage's own
-row code.  That code is compiled into two kernels, and the compiler may order
+recomputes the listed rows and their neighbours (each row once per run of
+listed rows) with the range stage's own row code.  That code is compiled into two kernels, and the compiler may order
 a few multiply-adds differently in each, so a recomputed cell can differ from
 the written one by a few FP32 ulps.  The rule: the same counts and status, the
 same cells rank by rank except at near-ties of the materialised P (the
