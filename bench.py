@@ -148,7 +148,8 @@ def time_extras(radar, torch, Yd, Ad, cfg, ws, peaks, n_peaks, status, stream, B
     the k peaks, with threshold detection (Eq. 18), with the periodogram not
     materialised (peaks only), with dense ZC precoding
     (on frames precoded that way), the time-domain frame simulation, in the
-    BF16x3 and FP16x3 matrix-core forms, the CNN refiner, and FPS-SFT (eight
+    BF16x3, FP16x3 and FP16 matrix-core forms (FP16 also without P), the CNN
+    refiner, and FPS-SFT (eight
     directions, K = 8) on the same frames."""
     import dataclasses
 
@@ -280,6 +281,25 @@ def time_extras(radar, torch, Yd, Ad, cfg, ws, peaks, n_peaks, status, stream, B
                                              for k in ("taps", "doppler", "range", "peaks")}
         del P
 
+    # the FP16 form without P: its matrix-core row maxima choose the rows and
+    # the peak search rescans them in FP32 (the FP32 periodogram's peaks)
+    cfg_p = dataclasses.replace(cfg, precision=radar.FLAG_FP16)
+    for _ in range(warmup):
+        radar.frame_process(Yd, Ad, cfg_p, K, workspace=ws, peaks=peaks, n_peaks=n_peaks, status=status,
+                            stream=stream, materialise=False)
+    radar.timing_start(steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        radar.frame_process(Yd, Ad, cfg_p, K, workspace=ws, peaks=peaks, n_peaks=n_peaks, status=status,
+                            stream=stream, materialise=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = radar.timing_stop()
+    out["fp16_peaks_only_frames_per_s"] = B * steps / dt
+    out["fp16_peaks_only_stage_us_per_frame"] = {k: st[k][0] / max(st[k][1], 1) * 1e3 / B
+                                                 for k in ("taps", "doppler", "range", "peaks")}
+
     # the CNN refiner: inference on 8192 patches cut from the benchmark frames'
     # periodograms around their peaks (the frames' 32 x 8 patches, tiled), and
     # one training step of 256 patches
@@ -408,7 +428,8 @@ def rmse_comparison(radar, torch, dev, fps, per_snr=24, train_frames=768, train_
     errors within one native bin, RMSE over hits (Eq. 19 units and native
     bins), hit rate beside it.  The forms: the FP32 grid peak, FP32 with the
     interpolation refinement, the grid peaks of the three matrix-core range
-    forms, and FP32 with the CNN refiner (trained here, by the library's own
+    forms, the FP16 form without P (its rows rescanned in FP32), and FP32
+    with the CNN refiner (trained here, by the library's own
     kernels, on train_frames frames of the same workload drawn from other
     seeds).  fps: each form's frames/s on the benchmark batch."""
     import dataclasses
@@ -430,6 +451,7 @@ def rmse_comparison(radar, torch, dev, fps, per_snr=24, train_frames=768, train_
         "bf16x3_grid": dict(precision=radar.FLAG_BF16X3),
         "fp16x3_grid": dict(precision=radar.FLAG_FP16X3),
         "fp16_grid": dict(precision=radar.FLAG_FP16),
+        "fp16_peaks_only_grid": dict(precision=radar.FLAG_FP16),  # P not written, rows rescanned in FP32
         "fp32_cnn": dict(),
     }
     snrs = [-20.0, -15.0, -10.0, -5.0, 0.0, 5.0, 10.0]
@@ -443,7 +465,8 @@ def rmse_comparison(radar, torch, dev, fps, per_snr=24, train_frames=768, train_
         del drawn
         grid32 = {}
         for name, kw in forms.items():
-            P, peaks, n_peaks, st = radar.frame_process(Y, A, dataclasses.replace(base, **kw), K)
+            P, peaks, n_peaks, st = radar.frame_process(Y, A, dataclasses.replace(base, **kw), K,
+                                                        materialise=name != "fp16_peaks_only_grid")
             off = None
             if name == "fp32_cnn":
                 pt, _ = radar.cnn_patches(P, peaks, n_peaks)
@@ -676,7 +699,9 @@ def main():
         fps_forms = {"fp32_grid": fps, "fp32_refined": extras.get("with_refinement_frames_per_s"),
                      "bf16x3_grid": extras.get("bf16x3_frames_per_s"),
                      "fp16x3_grid": extras.get("fp16x3_frames_per_s"),
-                     "fp16_grid": extras.get("fp16_frames_per_s"), "fp32_cnn": extras.get("with_cnn_frames_per_s")}
+                     "fp16_grid": extras.get("fp16_frames_per_s"),
+                     "fp16_peaks_only_grid": extras.get("fp16_peaks_only_frames_per_s"),
+                     "fp32_cnn": extras.get("with_cnn_frames_per_s")}
         extras["equal_rmse"] = rmse_comparison(radar, torch, dev, fps_forms, per_snr=args.rmse_frames)
     copy_gbs = device_copy_gbs(torch, dev)
     rng_ms, rng_n = stages["range"]

@@ -161,7 +161,9 @@ int radar_init(void);
  *   above with each operand rounded once to FP16 (one product per pass, a
  *   third of the matrix-core work): the periodogram's normwise error is of
  *   the order of 1e-4 instead of 1e-7.  Only for N = 1024, N' = 4N,
- *   4 N_cp <= N, with P written (RADAR_E_UNSUPPORTED otherwise).
+ *   4 N_cp <= N (RADAR_E_UNSUPPORTED otherwise).  With P = NULL the form's
+ *   row maxima only choose the rows to scan, and those rows are recomputed
+ *   in FP32: the peaks are the FP32 periodogram's.
  *   At most one of RADAR_FLAG_BF16X3, RADAR_FLAG_FP16X3, RADAR_FLAG_FP16.
  *   With RADAR_FLAG_THRESHOLD the peaks are the paper's detections (Eq. 18):
  *   local maxima with P >= eta = -ln(pfa) sigma_P^2, at most k, where
@@ -175,14 +177,20 @@ int radar_init(void);
  *           p_frame_stride >= M'*N' and a multiple of 4; P 16-byte aligned.
  *           NULL: peaks only, P is not materialised (p_frame_stride ignored).
  *           The range stage then keeps only its row maxima, and the peak
- *           search recomputes each row it scans (and that row's two
- *           neighbours) with the range stage's own row code, compiled into
- *           a second kernel: a recomputed cell may differ from the written
- *           one by a few FP32 ulps (the compiler may order a multiply-add
- *           differently), so the peaks match those found with P written
- *           except at near-ties.  Supported for N in {256, 512, 1024},
- *           N' = 4N and 4 N_cp <= N, in every precision form
- *           (RADAR_E_UNSUPPORTED otherwise).
+ *           search recomputes the rows it scans and their neighbours with
+ *           the range stage's own row code, compiled into a second kernel:
+ *           a recomputed cell may differ from the written one by a few FP32
+ *           ulps (the compiler may order a multiply-add differently), so the
+ *           peaks match those found with P written except at near-ties.  The
+ *           rows are listed twice: first those whose maximum reaches the
+ *           bound of the row maxima, then, from the k-th candidate found,
+ *           any other row that can still hold a top-k peak given the error
+ *           of the maxima (a few ulps; with RADAR_FLAG_FP16, 1/32 relative).
+ *           The environment variable RADAR_PEAKS_ONLY_FIRST_ROWS = R
+ *           (1..64), a diagnostic, cuts the first listing to the R rows with
+ *           the largest maxima; the result is the same.  Supported for N in
+ *           {256, 512, 1024}, N' = 4N and 4 N_cp <= N, in every precision
+ *           form (RADAR_E_UNSUPPORTED otherwise).
  * peaks:    output, k entries per frame at peaks + f*k; n_peaks[f] = number
  *           written (< k only if P has fewer than k local maxima).
  * status:   output, one word per frame (RADAR_ST_* bits; 0 = clean).

@@ -113,6 +113,10 @@ __device__ __forceinline__ void block_topk(int n, int k, const KeyAt& key_at, ui
   __syncthreads();
 }
 
+// Nonzero candidate keys a frame's ranking gathers into LDS before it ranks
+// them (beyond that it ranks the slots in global memory).
+constexpr int kMergeCap = 4096;
+
 // Row maxima of arbitrary periodograms (used when the range kernel did not
 // produce them).  Grid (m_pad, F), 256 threads.
 __global__ void __launch_bounds__(256) k_row_max(const float* P, int64_t p_stride, int m_pad, int n_pad,
@@ -140,7 +144,7 @@ __global__ void __launch_bounds__(256) k_row_max(const float* P, int64_t p_strid
 // found; the merge keeps only the k best, so the extra candidates cost only
 // scanning.
 __global__ void __launch_bounds__(256) k_peak_threshold(const float* rowmax, int m_pad, int k, float* tau_out,
-                                                        int32_t* list, int32_t* cnt_out, float slack) {
+                                                        int32_t* list, int32_t* cnt_out, float slack, int top_r) {
   extern __shared__ uint32_t s_dyn[];  // the row maxima, then the indices of profile peaks
   __shared__ uint64_t s_top[4][64];
   __shared__ uint64_t s_best[64];
@@ -197,11 +201,107 @@ __global__ void __launch_bounds__(256) k_peak_threshold(const float* rowmax, int
   }
   int pos = before + incl - c;
   int32_t* out = list + (int64_t)f * m_pad;
+  if (top_r > 0 && total > top_r) {
+    // a shortened first listing (peaks only, top_r <= 64): just the top_r
+    // rows with the largest maxima, ascending; k_peak_second_listing adds
+    // whatever else can hold a top-k peak
+    __syncthreads();  // the ranking's reads of pk are done
+    for (int i = lo; i < hi; ++i)
+      if (m[i] >= tau) pk[pos++] = (uint32_t)i;
+    __syncthreads();
+    block_topk(total, top_r, [&](int j) { const uint32_t i = pk[j]; return make_key(ord_bits(m[i]), i); }, s_top,
+               s_best);
+    // rank by row index among the chosen (the keys are distinct)
+    if (tid < top_r) {
+      const uint32_t row = 0xFFFFFFFFu - (uint32_t)s_best[tid];
+      int rank = 0;
+      for (int q = 0; q < top_r; ++q) rank += (0xFFFFFFFFu - (uint32_t)s_best[q]) < row ? 1 : 0;
+      out[rank] = (int32_t)row;
+    }
+    if (tid == 0) {
+      cnt_out[f] = top_r;
+      tau_out[f] = tau;
+    }
+    return;
+  }
   for (int i = lo; i < hi; ++i)
     if (m[i] >= tau) out[pos++] = i;
   if (tid == 0) {
     cnt_out[f] = total;
     tau_out[f] = tau;
+  }
+}
+
+// Peaks only: the second listing.  The first listing's rows [0, cnt[f]) have
+// been recomputed and scanned, their k best candidates each in cand.  The
+// k-th best of those, v, is a lower bound on the k-th peak (k distinct local
+// maxima reach it), so a row can hold a top-k peak only if its recomputed
+// maximum reaches v; the range stage's maximum m, which may fall short of it
+// by the relative error `slack`, then reaches v / (1 + slack).  Every row
+// that does and is not listed yet is appended, ascending; start[f] is set to
+// the first of them and cnt[f] to the new end.  With fewer than k
+// candidates found every remaining row is appended.  Grid F, 256 threads,
+// dynamic LDS (m_pad + 31) / 32 words.
+__global__ void __launch_bounds__(256) k_peak_second_listing(const float* rowmax, int m_pad, int k,
+                                                             const uint64_t* cand, int32_t* list, int32_t* cnt,
+                                                             int32_t* start, float slack) {
+  extern __shared__ uint32_t s_bits[];  // the first listing's rows
+  __shared__ uint64_t s_key[kMergeCap];
+  __shared__ uint64_t s_top[4][64];
+  __shared__ uint64_t s_best[64];
+  __shared__ int s_cnt[4];
+  __shared__ int s_n;
+  const int f = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int na = cnt[f];
+  int32_t* lst = list + (int64_t)f * m_pad;
+  const float* m = rowmax + (int64_t)f * m_pad;
+  for (int j = tid; j < (m_pad + 31) / 32; j += 256) s_bits[j] = 0u;
+  if (tid == 0) s_n = 0;
+  __syncthreads();
+  for (int j = tid; j < na; j += 256) atomicOr(&s_bits[lst[j] >> 5], 1u << (lst[j] & 31));
+  const int count = na * k;
+  const uint64_t* c = cand + (int64_t)f * m_pad * k;
+  for (int j = tid; j < count; j += 256) {
+    const uint64_t key = c[j];
+    if (key) {
+      const int p = atomicAdd(&s_n, 1);
+      if (p < kMergeCap) s_key[p] = key;
+    }
+  }
+  __syncthreads();
+  const int n = s_n;
+  if (n <= kMergeCap)
+    block_topk(n, k, [&](int j) { return s_key[j]; }, s_top, s_best);
+  else
+    block_topk(count, k, [&](int j) { return c[j]; }, s_top, s_best);
+  const uint64_t kth = s_best[k - 1];
+  const float bound = kth ? ord_value((uint32_t)(kth >> 32)) / (1.0f + slack) : -__builtin_huge_valf();
+  const int chunk = (m_pad + 255) / 256;
+  const int lo = tid * chunk < m_pad ? tid * chunk : m_pad;
+  const int hi = lo + chunk <= m_pad ? lo + chunk : m_pad;
+  const auto open = [&](int i) { return m[i] >= bound && !((s_bits[i >> 5] >> (i & 31)) & 1u); };
+  int cc = 0;
+  for (int i = lo; i < hi; ++i) cc += open(i) ? 1 : 0;
+  int incl = cc;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int up = __shfl_up(incl, off);
+    if ((tid & 63) >= off) incl += up;
+  }
+  if ((tid & 63) == 63) s_cnt[tid >> 6] = incl;
+  __syncthreads();
+  int before = 0, total = 0;
+  for (int w = 0; w < 4; ++w) {
+    if (w < (tid >> 6)) before += s_cnt[w];
+    total += s_cnt[w];
+  }
+  int pos = na + before + incl - cc;
+  for (int i = lo; i < hi; ++i)
+    if (open(i)) lst[pos++] = i;
+  if (tid == 0) {
+    start[f] = na;
+    cnt[f] = na + total;
   }
 }
 
@@ -338,7 +438,6 @@ __global__ void __launch_bounds__(256) k_peak_rows_listed(const float* P, int64_
 // inv_sum (threshold detection, Eq. 18) the list stops at the first peak
 // below eta = eta_factor * sum_l inv_sum[f][l]; the peaks come in descending
 // P, so what is kept is exactly the top-k local maxima at or above eta.
-constexpr int kMergeCap = 4096;
 __global__ void __launch_bounds__(256) k_peak_merge(const uint64_t* cand, const int32_t* cnt, int m_pad, int n_pad,
                                                     int k, radar_peak* peaks, int32_t* n_peaks,
                                                     const FrameRef* refs, const float* inv_sum, int M,

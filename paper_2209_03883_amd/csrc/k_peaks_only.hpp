@@ -112,13 +112,14 @@ struct K3Window {
 // Grid (G_total), K3p<N>::BLOCK threads; work items (frame f, share gs) for
 // f < n_frames, gs < per_frame, taken in turn by the work-groups.  The
 // wavefronts of a work-group split the item's share of frame f's list
-// entries [0, cnt[f]) into contiguous pieces.  Output cand[f][j][0..k) for
-// every entry j, as k_peak_rows_listed.  ring: gridDim.x *
-// kRingFloatsPerBlock floats.
+// entries [start[f] (0 without start), cnt[f]) into contiguous pieces, each
+// ascending.  Output cand[f][j][0..k) for every such entry j, as
+// k_peak_rows_listed.  ring: gridDim.x * kRingFloatsPerBlock floats.
 template <int N, Prec PR>
 __global__ void __launch_bounds__(K3p<N>::BLOCK) k_peak_rows_window(K3Args a, int n_frames, int per_frame, int k,
                                                                     const float* tau, const int32_t* list,
-                                                                    const int32_t* cnt, uint64_t* cand, float* ring) {
+                                                                    const int32_t* cnt, const int32_t* start,
+                                                                    uint64_t* cand, float* ring) {
   using C = K3p<N>;
   using W = K3Window<N>;
   constexpr int T = C::T;
@@ -148,11 +149,12 @@ __global__ void __launch_bounds__(K3p<N>::BLOCK) k_peak_rows_window(K3Args a, in
   for (int item = blockIdx.x; item < items; item += gridDim.x) {
     const int f = item / per_frame;
     const int share = item - f * per_frame;
-    const int count = cnt[f];
+    const int j0 = start ? start[f] : 0;
+    const int count = cnt[f] - j0;
     const int pieces = per_frame * C::WAVES;
     const int per = (count + pieces - 1) / pieces;
-    const int ja = (share * C::WAVES + wave) * per;
-    const int jb = ja + per < count ? ja + per : count;
+    const int ja = j0 + (share * C::WAVES + wave) * per;
+    const int jb = ja + per < j0 + count ? ja + per : j0 + count;
     if (ja >= jb) continue;  // wave-uniform
     const float th = tau[f];
     const int32_t* L = list + (int64_t)f * a.m_pad;

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -91,7 +92,7 @@ int validate_desc(const radar_frame_desc* d) {
 
 // Scratch of the peak search for F frames of m_pad rows (offsets in bytes).
 struct PeakWs {
-  size_t rowmax, tau, cnt, list, cand, total;
+  size_t rowmax, tau, cnt, start, list, cand, total;
 };
 PeakWs peak_ws_layout(int m_pad, int n_frames, int k, size_t base) {
   PeakWs w;
@@ -99,7 +100,8 @@ PeakWs peak_ws_layout(int m_pad, int n_frames, int k, size_t base) {
   w.rowmax = base;
   w.tau = w.rowmax + align256(F * m_pad * sizeof(float));
   w.cnt = w.tau + align256(F * sizeof(float));
-  w.list = w.cnt + align256(F * sizeof(int32_t));
+  w.start = w.cnt + align256(F * sizeof(int32_t));  // peaks only: first entry of the second listing
+  w.list = w.start + align256(F * sizeof(int32_t));
   w.cand = w.list + align256(F * m_pad * sizeof(int32_t));
   w.total = w.cand + align256(F * m_pad * (size_t)k * sizeof(uint64_t));
   return w;
@@ -379,7 +381,7 @@ void launch_k3x4p_rowmax(const radar::K3Args& a, int N, int m_pad, int F, hipStr
 }
 template <radar::Prec PR>
 void launch_rows_window(const radar::K3Args& a, int N, int F, int k, const float* tau, const int32_t* list,
-                        const int32_t* cnt, uint64_t* cand, float* ring, hipStream_t s) {
+                        const int32_t* cnt, const int32_t* start, uint64_t* cand, float* ring, hipStream_t s) {
   // the range kernel's work-group and LDS, one per CU, each building its
   // tables once and then taking (frame, share) items in turn
   const int blocks = window_blocks(F);
@@ -387,15 +389,15 @@ void launch_rows_window(const radar::K3Args& a, int N, int F, int k, const float
   switch (N) {
     case 256:
       hipLaunchKernelGGL((radar::k_peak_rows_window<256, PR>), dim3(blocks), dim3(radar::K3p<256>::BLOCK), 0, s, a,
-                         F, per_frame, k, tau, list, cnt, cand, ring);
+                         F, per_frame, k, tau, list, cnt, start, cand, ring);
       break;
     case 512:
       hipLaunchKernelGGL((radar::k_peak_rows_window<512, PR>), dim3(blocks), dim3(radar::K3p<512>::BLOCK), 0, s, a,
-                         F, per_frame, k, tau, list, cnt, cand, ring);
+                         F, per_frame, k, tau, list, cnt, start, cand, ring);
       break;
     default:
       hipLaunchKernelGGL((radar::k_peak_rows_window<1024, PR>), dim3(blocks), dim3(radar::K3p<1024>::BLOCK), 0, s,
-                         a, F, per_frame, k, tau, list, cnt, cand, ring);
+                         a, F, per_frame, k, tau, list, cnt, start, cand, ring);
       break;
   }
 }
@@ -405,8 +407,7 @@ void launch_rows_window(const radar::K3Args& a, int N, int F, int k, const float
 // P, and the peak search recomputes the rows it scans.
 bool peaks_only_supported(const radar_frame_desc* d) {
   const int N = d->n_sub;
-  return (N == 256 || N == 512 || N == 1024) && d->n_pad == 4 * N && d->n_cp * 4 <= N &&
-         !(d->flags & RADAR_FLAG_FP16);
+  return (N == 256 || N == 512 || N == 1024) && d->n_pad == 4 * N && d->n_cp * 4 <= N;
 }
 
 // The matrix-core range kernel runs the range stage: N = 1024, N' = 4N,
@@ -551,8 +552,12 @@ int enqueue_transforms(const radar_frame_desc* d, int F, const float2* in, const
   const bool x4 = f2 == 4 && d->n_cp * 4 <= N && N >= 256 && !(g_tune.k3_generic && prec == radar::Prec::FP32);
   slot = timer_open(RADAR_STAGE_RANGE, s);
   if (!P && !refs) {
-    // peaks only: row maxima, no P (peaks_only_supported was checked)
-    if (prec == radar::Prec::BF16X3)
+    // peaks only: row maxima, no P (peaks_only_supported was checked); the
+    // FP16 form's from its matrix-core kernel where it has one (N = 1024;
+    // elsewhere it runs in FP32)
+    if (prec == radar::Prec::FP16 && range_on_mx(d, true))
+      launch_k3mx<radar::Prec::FP16, false>(a3, d->m_pad, F, s);
+    else if (prec == radar::Prec::BF16X3)
       launch_k3x4p_rowmax<radar::Prec::BF16X3>(a3, N, d->m_pad, F, s);
     else if (prec == radar::Prec::FP16X3)
       launch_k3x4p_rowmax<radar::Prec::FP16X3>(a3, N, d->m_pad, F, s);
@@ -611,6 +616,26 @@ int enqueue_refine(const radar_frame_desc* d, int F, int k, const float2* taps, 
 
 // Peak search from P and its row maxima (already in the workspace).
 // With inv_sum (threshold detection) the merge keeps only peaks at or above eta.
+// Peaks only: the relative error bound of the range stage's row maxima
+// against the rows the peak search recomputes.  The FP32 and split forms
+// recompute with their own row code, compiled into another kernel (a few
+// ulps); the FP16 form's maxima come from its matrix-core kernel and the rows
+// are recomputed in FP32, so the bound is that form's error with a wide
+// margin (its rows are scaled one by one; the largest relative difference
+// measured at a peak is 1.3e-3).
+float peaks_only_slack(const radar_frame_desc* d) {
+  return (d->flags & RADAR_FLAG_FP16) && range_on_mx(d, true) ? 1.0f / 32.0f : 1.0f / 65536.0f;
+}
+// RADAR_PEAKS_ONLY_FIRST_ROWS = R (1..64, a diagnostic): the first listing
+// keeps only the R rows with the largest maxima, so that the second listing
+// finds the rest (tests use it to exercise that listing).
+int peaks_only_first_rows() {
+  const char* e = std::getenv("RADAR_PEAKS_ONLY_FIRST_ROWS");
+  if (!e) return 0;
+  const int r = std::atoi(e);
+  return r < 1 ? 0 : (r > 64 ? 64 : r);
+}
+
 // With P null (peaks only, frame_process) the listed rows are recomputed from
 // the Doppler-tap rows U by the range kernel's row code (`d` and `U` given).
 int enqueue_peaks(const float* P, int64_t p_stride, int m_pad, int n_pad, int F, int k, const PeakWs& w, char* ws,
@@ -623,22 +648,41 @@ int enqueue_peaks(const float* P, int64_t p_stride, int m_pad, int n_pad, int F,
   int32_t* list = reinterpret_cast<int32_t*>(ws + w.list);
   uint64_t* cand = reinterpret_cast<uint64_t*>(ws + w.cand);
   const int slot = timer_open(RADAR_STAGE_PEAKS, s);
-  // peaks only: the rows scanned are recomputed by another kernel than the
-  // one whose row maxima set tau, and may differ from them by a few ulps
-  const float slack = (!P && !refs) ? 1.0f / 65536.0f : 0.0f;
+  const bool recompute = !P && !refs;
+  if (recompute && (!d || !U || !ring)) return RADAR_E_ARG;
+  // peaks only: the rows scanned are recomputed in FP32 or the split form
+  // by another kernel than the one whose row maxima set tau.  Those maxima
+  // differ from the recomputed ones by a few ulps, or, from the FP16
+  // matrix-core range kernel, by that form's error: at most peaks_only_slack
+  // relative.
+  const float slack = recompute ? peaks_only_slack(d) : 0.0f;
+  const int first_rows = recompute ? peaks_only_first_rows() : 0;
   hipLaunchKernelGGL(radar::k_peak_threshold, dim3(F), dim3(256), 2 * m_pad * sizeof(uint32_t), s, rowmax, m_pad, k,
-                     tau, list, cnt, slack);
+                     tau, list, cnt, slack, first_rows);
   RADAR_HIP_CHECK(hipGetLastError());
-  if (!P && !refs) {
-    if (!d || !U || !ring) return RADAR_E_ARG;
+  if (recompute) {
     const radar::K3Args a3 = range_args(d, U, nullptr, 0, rowmax, nullptr);
     const radar::Prec prec = prec_of(d);
-    if (prec == radar::Prec::BF16X3)
-      launch_rows_window<radar::Prec::BF16X3>(a3, d->n_sub, F, k, tau, list, cnt, cand, ring, s);
-    else if (prec == radar::Prec::FP16X3)
-      launch_rows_window<radar::Prec::FP16X3>(a3, d->n_sub, F, k, tau, list, cnt, cand, ring, s);
-    else
-      launch_rows_window<radar::Prec::FP32>(a3, d->n_sub, F, k, tau, list, cnt, cand, ring, s);
+    int32_t* start = reinterpret_cast<int32_t*>(ws + w.start);
+    for (int pass = 0; pass < 2; ++pass) {
+      const int32_t* st = nullptr;
+      if (pass == 1) {
+        // the second listing: whatever rows the first one's k-th candidate
+        // shows can still hold a top-k peak
+        hipLaunchKernelGGL(radar::k_peak_second_listing, dim3(F), dim3(256),
+                           ((m_pad + 31) / 32) * sizeof(uint32_t), s, rowmax, m_pad, k, cand, list, cnt, start,
+                           slack);
+        RADAR_HIP_CHECK(hipGetLastError());
+        st = start;
+      }
+      if (prec == radar::Prec::BF16X3)
+        launch_rows_window<radar::Prec::BF16X3>(a3, d->n_sub, F, k, tau, list, cnt, st, cand, ring, s);
+      else if (prec == radar::Prec::FP16X3)
+        launch_rows_window<radar::Prec::FP16X3>(a3, d->n_sub, F, k, tau, list, cnt, st, cand, ring, s);
+      else  // FP32, and the FP16 form's rows again in FP32
+        launch_rows_window<radar::Prec::FP32>(a3, d->n_sub, F, k, tau, list, cnt, st, cand, ring, s);
+      RADAR_HIP_CHECK(hipGetLastError());
+    }
   } else {
     const int groups = m_pad < 32 ? m_pad : 32;
     hipLaunchKernelGGL(radar::k_peak_rows_listed, dim3(groups, F), dim3(256), n_pad * sizeof(uint32_t), s, P,

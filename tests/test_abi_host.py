@@ -49,8 +49,9 @@ def _al(x):
 
 
 def _peak_ws(F, m_pad, k):
-    # row maxima, tau, row count, row list, per-row candidates
-    return _al(F * m_pad * 4) + _al(F * 4) + _al(F * 4) + _al(F * m_pad * 4) + _al(F * m_pad * k * 8)
+    # row maxima, tau, row count, second-listing start, row list, per-row candidates
+    return (_al(F * m_pad * 4) + _al(F * 4) + _al(F * 4) + _al(F * 4) + _al(F * m_pad * 4)
+            + _al(F * m_pad * k * 8))
 
 
 def test_workspace_size_arithmetic():
@@ -352,14 +353,16 @@ def test_precision_flag_validation(kw, code):
     assert L.radar_frame_process(ctypes.byref(cfg.desc()), 1, p, p, 0, p, 0, 8, p, p, p, p, 1 << 40, None) == code
 
 
-def test_fp16_form_needs_the_periodogram_written():
+def test_fp16_form_takes_both_outputs():
+    # with P written or peaks only (its rows then rescanned in FP32), the FP16
+    # form passes validation and stops at the workspace check, before any HIP call
     L = radar.lib()
     cfg = radar.Config(1024, 1024, 4096, 4096, 256, zc_root=7, precision=radar.FLAG_FP16)
     d = ctypes.byref(cfg.desc())
     need = L.radar_frame_workspace_size(d, 1, 8)
     assert need > 0
     p = 256
-    assert L.radar_frame_process(d, 1, p, p, 0, None, 0, 8, p, p, p, p, need, None) == radar.RADAR_E_UNSUPPORTED
+    assert L.radar_frame_process(d, 1, p, p, 0, None, 0, 8, p, p, p, p, need - 1, None) == radar.RADAR_E_WORKSPACE
     assert L.radar_frame_process(d, 1, p, p, 0, p, 0, 8, p, p, p, p, need - 1, None) == radar.RADAR_E_WORKSPACE
 
 

@@ -12,6 +12,12 @@ the split matrix-core forms write P with the two-pass 32-point range kernel,
 whose row code peaks-only does not use; there the two runs agree to the
 forms' error instead.  The small workload is also checked against the FP64
 oracle.
+
+The FP16 form (N = 1024) keeps its matrix-core row maxima and rescans the
+listed rows in FP32, so its peaks are held to the FP32 run with P written by
+the same rule.  The second listing (rows the first one's k-th candidate shows
+can still hold a top-k peak) is exercised by cutting the first listing short
+with RADAR_PEAKS_ONLY_FIRST_ROWS: the result must not change.
 """
 
 import dataclasses
@@ -36,11 +42,12 @@ def _need_gpu():
     radar.lib()
 
 
-def _both(frames, cfg, k):
+def _both(frames, cfg, k, cfg_peaks_only=None):
+    """The frames with P written (cfg) and peaks only (cfg_peaks_only, else cfg)."""
     Y, A = S.frames_to_complex64(frames)
     Yd, Ad = torch.from_numpy(Y).cuda(), torch.from_numpy(A).cuda()
     P, pk1, n1, st1 = radar.frame_process(Yd, Ad, cfg, k)
-    P0, pk0, n0, st0 = radar.frame_process(Yd, Ad, cfg, k, materialise=False)
+    P0, pk0, n0, st0 = radar.frame_process(Yd, Ad, cfg_peaks_only or cfg, k, materialise=False)
     torch.cuda.synchronize()
     assert P0 is None
     return P.cpu().numpy(), radar.unpack_peaks(pk1, n1.cpu()), st1.cpu().numpy(), \
@@ -161,3 +168,69 @@ def test_kth_peak_at_the_bound(n, m, ncp):
     for f in range(len(frames)):
         assert len(res[3][f]) == k, (f, res[3][f])
     _same(res, f"k-th at tau {n}x{m}")
+
+
+# ------------------------------------------------- the FP16 form, peaks only
+def _fp16(cfg):
+    return dataclasses.replace(cfg, precision=radar.FLAG_FP16)
+
+
+@pytest.mark.parametrize("m, ncp, k, snr", [(128, 256, 8, -5.0), (64, 100, 16, 0.0), (256, 1, 4, 10.0)])
+def test_fp16_peaks_only_matches_fp32(m, ncp, k, snr):
+    # the FP16 form's row maxima choose the rows, FP32 rescans them: the
+    # peaks are the FP32 periodogram's
+    spec = S.FrameSpec(n_sub=1024, n_sym=m, qam=16, zc_root=3, n_targets=6, snr_db=snr, on_grid=False,
+                       rho_min=0.0, rho_max=ncp - 1.0, nu_abs_max=m / 2 - 1, rayleigh=True, min_sep=1.5)
+    frames = [S.make_frame(spec, 85, i) for i in range(3)]
+    cfg = radar.Config(1024, m, 4096, 4 * m, ncp, zc_root=3)
+    say(f"FP16 peaks only against FP32 with P, 1024x{m} cp{ncp} k{k}")
+    _same(_both(frames, cfg, k, _fp16(cfg)), f"fp16 1024x{m}")
+
+
+def test_fp16_peaks_only_full_frames():
+    frames = [S.make_frame(S.spec_full(snr_db=snr), 2, i) for i, snr in enumerate((0.0, -20.0))]
+    cfg = radar.Config(1024, 1024, 4096, 4096, 256, zc_root=7)
+    say("FP16 peaks only, full frames")
+    _same(_both(frames, cfg, 8, _fp16(cfg)), "fp16 full")
+
+
+def test_fp16_kth_peak_at_the_bound():
+    # as test_kth_peak_at_the_bound, with the FP16 form's maxima choosing the
+    # rows: they may miss the FP32 k-th peak by the form's error, which the
+    # second listing covers
+    k = 6
+    spec = S.FrameSpec(n_sub=1024, n_sym=128, qam=16, zc_root=3, n_targets=k, snr_db=0.0, on_grid=False,
+                       rho_min=1.0, rho_max=254.0, nu_abs_max=62.0, rayleigh=True, min_sep=4.0, noise=False)
+    frames = [S.make_frame(spec, 83, i) for i in range(8)]
+    cfg = radar.Config(1024, 128, 4096, 512, 256, zc_root=3)
+    say("FP16 peaks only, k-th peak at the bound")
+    res = _both(frames, cfg, k, _fp16(cfg))
+    for f in range(len(frames)):
+        assert len(res[3][f]) == k, (f, res[3][f])
+    _same(res, "fp16 k-th at tau")
+
+
+@pytest.mark.parametrize("first_rows", [2, 8])
+@pytest.mark.parametrize("fp16", [False, True])
+def test_second_listing_finds_the_rest(monkeypatch, first_rows, fp16):
+    # the first listing cut to the rows with the largest maxima (fewer than k
+    # of them, or about k): the second one must list every row that can still
+    # hold a top-k peak, so the peaks are those of the full listing, bit for bit
+    spec = S.FrameSpec(n_sub=1024, n_sym=128, qam=16, zc_root=3, n_targets=6, snr_db=-5.0, on_grid=False,
+                       rho_min=0.0, rho_max=255.0, nu_abs_max=63.0, rayleigh=True, min_sep=1.5)
+    frames = [S.make_frame(spec, 87, i) for i in range(3)]
+    cfg = radar.Config(1024, 128, 4096, 512, 256, zc_root=3)
+    cfg0 = _fp16(cfg) if fp16 else cfg
+    k = 12
+    Y, A = S.frames_to_complex64(frames)
+    Yd, Ad = torch.from_numpy(Y).cuda(), torch.from_numpy(A).cuda()
+    _, pk_full, n_full, _ = radar.frame_process(Yd, Ad, cfg0, k, materialise=False)
+    monkeypatch.setenv("RADAR_PEAKS_ONLY_FIRST_ROWS", str(first_rows))
+    say(f"second listing after the top {first_rows} rows, fp16={fp16}")
+    res = _both(frames, cfg, k, cfg0)
+    torch.cuda.synchronize()
+    full = radar.unpack_peaks(pk_full, n_full.cpu())
+    for f in range(len(frames)):
+        assert [p[:2] for p in res[3][f]] == [p[:2] for p in full[f]], (f, res[3][f], full[f])
+        assert [p[2] for p in res[3][f]] == [p[2] for p in full[f]], f
+    _same(res, f"second listing {first_rows} fp16={fp16}")
