@@ -126,6 +126,18 @@ __global__ void __launch_bounds__(K3p<N>::BLOCK) k_peak_rows_window(K3Args a, in
   constexpr int R = C::ROWS;
   constexpr int NP = 4 * N;
   constexpr int kNone = -0x40000000;  // no row (below any row index, less one)
+  const int items = n_frames * per_frame;
+  // a work-group whose frames have no entries in range leaves before building
+  // its tables (the second listing usually adds none); the test depends on
+  // blockIdx only, so the whole work-group leaves together
+  {
+    bool any = false;
+    for (int item = blockIdx.x; item < items && !any; item += gridDim.x) {
+      const int f = item / per_frame;
+      any = cnt[f] > (start ? start[f] : 0);
+    }
+    if (!any) return;
+  }
   typename DftFor<PR>::type df;
   df.init();
   __shared__ float2 pool[C::TAB + C::WAVES * C::ROWS * (C::EXCH + C::UBUF)];
@@ -144,20 +156,80 @@ __global__ void __launch_bounds__(K3p<N>::BLOCK) k_peak_rows_window(K3Args a, in
   k3p_zero_pads<N>(ub, t0);
   RADAR_GLOBAL float* const my_ring = gptr(ring) + ((size_t)blockIdx.x * C::WAVES + wave) * (W::RING * NP);
   const int mask = a.m_pad - 1;
-  const int items = n_frames * per_frame;
+
+  __shared__ int s_sum[C::WAVES];
+  __shared__ int s_piece[C::WAVES][2];
+  const int tid = threadIdx.x;
+  // work-group sum of one value per thread (every thread gets it)
+  const auto block_sum = [&](int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) s_sum[wave] = v;
+    __syncthreads();
+    int t = 0;
+#pragma unroll
+    for (int w = 0; w < C::WAVES; ++w) t += s_sum[w];
+    __syncthreads();
+    return t;
+  };
 
   for (int item = blockIdx.x; item < items; item += gridDim.x) {
     const int f = item / per_frame;
     const int share = item - f * per_frame;
     const int j0 = start ? start[f] : 0;
     const int count = cnt[f] - j0;
+    if (count <= 0) continue;  // work-group-uniform
+    const int32_t* L = list + (int64_t)f * a.m_pad;
+    // Pieces of equal work: entry j adds min(3, s_j - s_{j-1}) rows to the
+    // union (3 for the first), and the frame's pieces split the running
+    // total evenly; this work-group's wavefronts take pieces share * WAVES +
+    // wave.  Entries stay in order, so each piece is a contiguous range.
+    const auto cost = [&](int j) {
+      if (j == 0) return 3;
+      const int d = L[j0 + j] - L[j0 + j - 1];
+      return d < 3 ? d : 3;
+    };
+    int part = 0;
+    for (int j = tid; j < count; j += C::BLOCK) part += cost(j);
+    const int64_t total = block_sum(part);
     const int pieces = per_frame * C::WAVES;
-    const int per = (count + pieces - 1) / pieces;
-    const int ja = j0 + (share * C::WAVES + wave) * per;
-    const int jb = ja + per < j0 + count ? ja + per : j0 + count;
+    if (tid < C::WAVES) {
+      s_piece[tid][0] = count;
+      s_piece[tid][1] = 0;
+    }
+    int run = 0;  // the union rows of the entries before this chunk
+    for (int base = 0; base < count; base += C::BLOCK) {
+      const int j = base + tid;
+      const int c = j < count ? cost(j) : 0;
+      int incl = c;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int up = __shfl_up(incl, off);
+        if (lane >= off) incl += up;
+      }
+      if (lane == 63) s_sum[wave] = incl;
+      __syncthreads();  // also orders this chunk's s_piece updates after the initialisation
+      int before = 0, chunk = 0;
+#pragma unroll
+      for (int w = 0; w < C::WAVES; ++w) {
+        before += w < wave ? s_sum[w] : 0;
+        chunk += s_sum[w];
+      }
+      if (j < count) {
+        const int64_t excl = run + before + incl - c;
+        const int q = (int)(excl * pieces / total) - share * C::WAVES;
+        if (q >= 0 && q < C::WAVES) {
+          atomicMin(&s_piece[q][0], j);
+          atomicMax(&s_piece[q][1], j + 1);
+        }
+      }
+      run += chunk;
+      __syncthreads();  // s_sum is reused by the next chunk
+    }
+    const int ja = j0 + s_piece[wave][0];
+    const int jb = j0 + s_piece[wave][1];
     if (ja >= jb) continue;  // wave-uniform
     const float th = tau[f];
-    const int32_t* L = list + (int64_t)f * a.m_pad;
     const float2* Uf = a.U + (int64_t)f * a.m_pad * a.n_cp;
 
     // the union of {s-1, s, s+1} over entries ja .. jb-1, ascending, each
