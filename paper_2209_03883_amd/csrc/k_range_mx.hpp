@@ -313,6 +313,7 @@ __global__ void __launch_bounds__(K3Mx<N>::BLOCK) k3_range_power_mx(K3Args a, in
       dst = gptr(kRefs ? crefs[f].P : a.P + (int64_t)f * a.p_stride) + (int64_t)row * (4 * N);
     }
     float mx = 0.0f;
+    float mg = 0.0f;  // without stores: the largest |G|^2 of phases 1..3, unscaled
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
       f32x16_t z0{}, z1{};
@@ -349,7 +350,26 @@ __global__ void __launch_bounds__(K3Mx<N>::BLOCK) k3_range_power_mx(K3Args a, in
           g1 = mma3<PR>(vc[1][q], d, g1);
         }
       }
-      if (b < 2) {
+      if (!kStore) {
+        // only the maximum is kept: scaling by cp > 0 is monotone, so it is
+        // applied once to the largest |G|^2
+#pragma unroll
+        for (int e = 0; e < 16; ++e) mg = fmaxf(mg, g0[e] * g0[e] + g1[e] * g1[e]);
+        if (b == 2) {
+          if (gnext < total_rows) load_taps(un, gnext);
+          mx = mg * cp;
+#pragma unroll
+          for (int e = 0; e < 16; ++e) {
+            const int r1 = i + 32 * mx_row(h, e);
+            if (mx_row(h, e) <= Q / 32) {
+              if (r1 <= Q)
+                mx = fmaxf(mx, cabs2(cadd(cscale(ub[r1], c0), cscale(cadd(ub[r1 - 1], ub[r1 + 1]), c1))));
+            } else if (mx_row(h, e) == 31) {
+              if (i == 31) mx = fmaxf(mx, cabs2(cscale(ub[0], c1)));
+            }
+          }
+        }
+      } else if (b < 2) {
 #pragma unroll
         for (int e = 0; e < 16; ++e) s_p[wave][b][e][lane] = (g0[e] * g0[e] + g1[e] * g1[e]) * cp;
       } else {
