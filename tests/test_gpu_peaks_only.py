@@ -234,3 +234,29 @@ def test_second_listing_finds_the_rest(monkeypatch, first_rows, fp16):
         assert [p[:2] for p in res[3][f]] == [p[:2] for p in full[f]], (f, res[3][f], full[f])
         assert [p[2] for p in res[3][f]] == [p[2] for p in full[f]], f
     _same(res, f"second listing {first_rows} fp16={fp16}")
+
+
+def test_fp16_row_maxima_within_the_slack():
+    # the listings take the FP16 form's row maxima to be within 1/32 (relative)
+    # of the FP32 rows' maxima.  The form's P holds exactly the values whose
+    # maxima its store-free kernel keeps (the same products, scaled alike), so
+    # the bound is checked here on every row of P, with a wide margin
+    specs = [S.spec_full(snr_db=snr) for snr in (-20.0, 0.0, 10.0)]
+    specs.append(dataclasses.replace(S.spec_full(), noise=False, n_targets=2))
+    frames = [S.make_frame(sp, 89, i) for i, sp in enumerate(specs)]
+    cfg = radar.Config(1024, 1024, 4096, 4096, 256, zc_root=7)
+    Y, A = S.frames_to_complex64(frames)
+    Yd, Ad = torch.from_numpy(Y).cuda(), torch.from_numpy(A).cuda()
+    worst = 0.0
+    for f in range(len(frames)):
+        P32, _, _, _ = radar.frame_process(Yd[f:f + 1], Ad[f:f + 1], cfg, 8)
+        m32 = P32[0].amax(dim=1).double()
+        del P32
+        P16, _, _, _ = radar.frame_process(Yd[f:f + 1], Ad[f:f + 1], _fp16(cfg), 8)
+        m16 = P16[0].amax(dim=1).double()
+        del P16
+        big = m32 > m32.max() * 1e-30  # rows that are not numerically zero
+        rel = ((m32 - m16).abs() / m32.clamp_min(1e-300))[big]
+        worst = max(worst, float(rel.max()))
+    say(f"FP16 row maxima: largest relative difference {worst:.2e} (bound 1/32)")
+    assert worst <= (1.0 / 32) / 4, worst
