@@ -260,3 +260,14 @@ def test_fp16_row_maxima_within_the_slack():
         worst = max(worst, float(rel.max()))
     say(f"FP16 row maxima: largest relative difference {worst:.2e} (bound 1/32)")
     assert worst <= (1.0 / 32) / 4, worst
+
+
+def test_fp16_peaks_only_with_threshold_and_refinement():
+    # the refinement reads the taps after the peak search, so the recompute
+    # rings take their own workspace region here
+    spec = S.FrameSpec(n_sub=1024, n_sym=64, qam=16, zc_root=3, n_targets=5, snr_db=0.0, on_grid=False,
+                       rho_min=0.0, rho_max=255.0, nu_abs_max=31.0, rayleigh=True, min_sep=1.5)
+    frames = [S.make_frame(spec, 91, i) for i in range(3)]
+    cfg = radar.Config(1024, 64, 4096, 256, 256, zc_root=3, threshold=True, pfa=1e-4, noise_power=1.0, refine=True)
+    say("FP16 peaks only, threshold and refinement")
+    _same(_both(frames, cfg, 8, _fp16(cfg)), "fp16 threshold+refine")
