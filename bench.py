@@ -31,6 +31,7 @@ HBM_PEAK_GBS = 8000.0
 # which halves what one instruction can do (64 FMA lanes per clock per CU)
 FP32_VECTOR_PEAK_TFLOPS = 256 * 2.4e9 * 128 * 2 / 1e12
 FP32_UNPACKED_PEAK_TFLOPS = FP32_VECTOR_PEAK_TFLOPS / 2
+FP16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense FP16 matrix-core peak (published, without sparsity)
 N, M, PAD, NCP, ROOT_ZC, K = 1024, 1024, 4, 256, 7, 8
 # Table I: subcarrier spacing and carrier (Eq. 13-15, 19 units); the
 # workload's own N, M and prefix N_cp / N set the bin sizes
@@ -621,6 +622,22 @@ def fp16_range_hbm(extras, copy_gbs):
                                "frac_of_device_copy": gbs / copy_gbs}}
 
 
+def fp16_peaks_only_range_mfma(extras):
+    """The FP16 form's store-free range kernel (peaks only) against the FP16
+    matrix-core peak: its issued matrix-core work per frame, 58
+    v_mfma_f32_32x32x16_f16 per Doppler row (f1 2, f2 8, and i1 8 + i2 8 for
+    each of three phases) of 2 x 32 x 32 x 16 flops each, over its HIP-event
+    time per frame.  These are the flops the matrix cores execute (dense 32-point
+    DFTs by matrix product), not the FFT's 5 n log2 n count."""
+    st = extras.get("fp16_peaks_only_stage_us_per_frame")
+    if not st or not st.get("range"):
+        return {}
+    flops = 58 * 2 * 32 * 32 * 16 * PAD * M
+    tf = flops / (st["range"] * 1e-6) / 1e12
+    return {"fp16_peaks_only_range_mfma": {"achieved": tf, "peak": FP16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                           "frac": tf / FP16_MFMA_PEAK_TFLOPS}}
+
+
 def dataclasses_replace(cfg, **kw):
     import dataclasses
 
@@ -741,6 +758,7 @@ def main():
                        "frac": achieved / HBM_PEAK_GBS},
             "k3_frac_of_unpacked_fp32": k3_tflops / FP32_UNPACKED_PEAK_TFLOPS,
             **fp16_range_hbm(extras, copy_gbs),
+            **fp16_peaks_only_range_mfma(extras),
             "stage_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in stages.items() if v[1]},
             **extras,
         },
