@@ -184,6 +184,8 @@ struct Tuning {
   int k1_mult = 1;         // persistent taps kernel: work-groups per CU
   int k3_mult = 1;         // persistent range kernel: work-groups per CU
   bool k3_generic = false; // use the one-team-per-row range kernel instead of the four-phase one
+  bool k2_half = false;    // Doppler tiles of half the taps (FP32)
+  int scan_groups = 32;    // work-groups per frame of the listed-row peak scan
   float ms = 0.0f;         // measured time of one pass of the group with these settings (0: not measured)
 };
 thread_local Tuning g_tune;
@@ -218,12 +220,8 @@ void launch_k1_n(const radar::K1Args& a, int M, int F, hipStream_t s) {
   dim3 grid((M + TEAMS - 1) / TEAMS, F);
   hipLaunchKernelGGL(radar::k1_taps<N>, grid, dim3(radar::kBlock), 0, s, a);
 }
-template <int M, radar::Prec PR>
-void launch_k2_m(const radar::K2Args& a, int n_cp, int F, hipStream_t s) {
-  // tiles of TW taps: at most 64, at most 1024 threads, padded tile M*(TW+1) <= 17408 entries
-  constexpr int T = M / 16;
-  constexpr int TW0 = 1024 / T < 64 ? 1024 / T : 64;
-  constexpr int TW = M * (TW0 + 1) <= 17408 ? TW0 : 17408 / M - 1;
+template <int M, int TW, radar::Prec PR>
+void launch_k2_tw(const radar::K2Args& a, int n_cp, int F, hipStream_t s) {
   // persistent: as many work-groups as fit on the device at once (a static
   // initialised once, thread-safely, on the first call for this shape)
   static const int per_cu = [] {
@@ -240,6 +238,22 @@ void launch_k2_m(const radar::K2Args& a, int n_cp, int F, hipStream_t s) {
   if (grid > total || !radar::K2Persistent<PR>::value) grid = total;
   hipLaunchKernelGGL((radar::k2_doppler_tiled<M, TW, PR>), dim3(grid), dim3(radar::K2Tile<M, TW>::BLOCK), 0, s, a,
                      n_tiles, total);
+}
+template <int M, radar::Prec PR>
+void launch_k2_m(const radar::K2Args& a, int n_cp, int F, hipStream_t s) {
+  // tiles of TW taps: at most 64, at most 1024 threads, padded tile M*(TW+1) <= 17408 entries
+  constexpr int T = M / 16;
+  constexpr int TW0 = 1024 / T < 64 ? 1024 / T : 64;
+  constexpr int TW = M * (TW0 + 1) <= 17408 ? TW0 : 17408 / M - 1;
+  // the autotuner's alternative (FP32, M >= 64): tiles of half the taps and
+  // about half the LDS (two work-groups per CU where two fit)
+  if constexpr (PR == radar::Prec::FP32 && M >= 64 && TW >= 2) {
+    if (g_tune.k2_half) {
+      launch_k2_tw<M, TW / 2, PR>(a, n_cp, F, s);
+      return;
+    }
+  }
+  launch_k2_tw<M, TW, PR>(a, n_cp, F, s);
 }
 template <int N, int F2>
 void launch_k3_nf(const radar::K3Args& a, int m_pad, int F, hipStream_t s) {
@@ -684,7 +698,7 @@ int enqueue_peaks(const float* P, int64_t p_stride, int m_pad, int n_pad, int F,
       RADAR_HIP_CHECK(hipGetLastError());
     }
   } else {
-    const int groups = m_pad < 32 ? m_pad : 32;
+    const int groups = m_pad < g_tune.scan_groups ? m_pad : g_tune.scan_groups;
     hipLaunchKernelGGL(radar::k_peak_rows_listed, dim3(groups, F), dim3(256), n_pad * sizeof(uint32_t), s, P,
                        p_stride, m_pad, n_pad, k, tau, list, cnt, cand, refs);
   }
@@ -1109,45 +1123,69 @@ int tune_group(radar_batch& b, BatchGroup& g, hipStream_t s) {
   const bool x4 = d.n_pad == 4 * N && 4 * d.n_cp <= N && N >= 256;
   const bool fp32 = !(d.flags & (RADAR_FLAG_BF16X3 | RADAR_FLAG_FP16X3 | RADAR_FLAG_FP16));
   const bool x4p = x4 && (N <= 1024 || (N == 2048 && fp32));  // a persistent range kernel
-  std::vector<Tuning> cands(1);
+  // One dimension at a time, each candidate a change of the best plan so far
+  // (every plan is timed, a single one too: the time balances the concurrent
+  // branches of the captured batch): work-groups per CU of the persistent
+  // taps and range kernels; the range kernel's FFT plan (four N-point phase
+  // transforms, or one N'-point transform per row); the Doppler tile width;
+  // the peak scan's work-groups per frame.
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return RADAR_E_HIP;
+  const auto time_plan = [&](const Tuning& t, float& ms) -> int {
+    g.tune = t;
+    int rc = enqueue_group(b, g, s);  // warm-up
+    if (rc != RADAR_OK) return rc;
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < 3 && rc == RADAR_OK; ++r) rc = enqueue_group(b, g, s);
+    (void)hipEventRecord(e1, s);
+    if (rc != RADAR_OK || hipEventSynchronize(e1) != hipSuccess) return RADAR_E_HIP;
+    ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    ms /= 3.0f;
+    return RADAR_OK;
+  };
+  Tuning best;
+  int rc = time_plan(best, best.ms);
+  std::vector<Tuning> alts;
   if (persistent_k1 || x4p) {
     Tuning t;
     t.k1_mult = persistent_k1 ? 2 : 1;
     t.k3_mult = x4p ? 2 : 1;
-    cands.push_back(t);
+    alts.push_back(t);
   }
   if (x4 && fp32) {
     Tuning t;
     t.k3_generic = true;
-    cands.push_back(t);
+    alts.push_back(t);
   }
-  {
-    // every candidate is timed (a single one too: the time balances the
-    // concurrent branches of the captured batch)
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return RADAR_E_HIP;
-    float best = 1e30f;
-    Tuning pick = cands[0];
-    for (const Tuning& t : cands) {
-      g.tune = t;
-      int rc = enqueue_group(b, g, s);  // warm-up
-      if (rc != RADAR_OK) return rc;
-      (void)hipEventRecord(e0, s);
-      for (int r = 0; r < 3 && rc == RADAR_OK; ++r) rc = enqueue_group(b, g, s);
-      (void)hipEventRecord(e1, s);
-      if (rc != RADAR_OK || hipEventSynchronize(e1) != hipSuccess) return RADAR_E_HIP;
-      float ms = 0.0f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      if (ms < best) {
-        best = ms;
-        pick = t;
-        pick.ms = ms / 3.0f;
-      }
+  if (fp32 && d.n_sym >= 64) {
+    Tuning t;
+    t.k2_half = true;
+    alts.push_back(t);
+  }
+  if (d.m_pad > 32) {
+    Tuning t;
+    t.scan_groups = 128;
+    alts.push_back(t);
+  }
+  for (const Tuning& alt : alts) {
+    if (rc != RADAR_OK) break;
+    // apply this candidate's changed dimension to the best plan so far
+    Tuning t = best;
+    if (alt.k1_mult != 1 || alt.k3_mult != 1) {
+      t.k1_mult = alt.k1_mult;
+      t.k3_mult = alt.k3_mult;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    g.tune = pick;
+    if (alt.k3_generic) t.k3_generic = true;
+    if (alt.k2_half) t.k2_half = true;
+    if (alt.scan_groups != 32) t.scan_groups = alt.scan_groups;
+    rc = time_plan(t, t.ms);
+    if (rc == RADAR_OK && t.ms < best.ms) best = t;
   }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != RADAR_OK) return rc;
+  g.tune = best;
   std::lock_guard<std::mutex> lock(g_tune_mu);
   g_tune_cache[key] = g.tune;
   return RADAR_OK;
