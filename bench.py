@@ -597,6 +597,7 @@ def time_batch(radar, torch, n_frames, steps):
 
     grid = rmse_table(b)
     groups = b.groups()
+    plans = b.plans()
     b.close()
     del b
     rjobs = [(Y, A, dataclasses_replace(cfg, refine=True), k) for Y, A, cfg, k in jobs]
@@ -608,6 +609,11 @@ def time_batch(radar, torch, n_frames, steps):
     return {"batch_frames": n_frames, "batch_shape_groups": len(groups),
             "batch_frames_per_s": n_frames / dt, "batch_ms_per_launch": dt * 1e3,
             "batch_algorithmic_gbytes": alg / 1e9, "batch_hbm_gbs": alg / dt / 1e9,
+            "batch_tuned_plans": {"groups": len(plans),
+                                  "two_per_cu": sum(1 for p in plans if p["k3_mult"] == 2 or p["k1_mult"] == 2),
+                                  "per_row_range_kernel": sum(p["k3_generic"] for p in plans),
+                                  "half_doppler_tiles": sum(p["k2_half_tile"] for p in plans),
+                                  "scan_128_per_frame": sum(1 for p in plans if p["scan_groups"] == 128)},
             "batch_rmse_vs_snr_grid": grid, "batch_rmse_vs_snr_refined": refined}
 
 

@@ -400,6 +400,11 @@ int radar_batch_launch(radar_batch *b, void *hip_stream);
  * the one-team-per-row range kernel was chosen). */
 int radar_batch_info(const radar_batch *b, int32_t g, int32_t *n_groups, int32_t *n_frames,
                      int32_t *k1_mult, int32_t *k3_mult, int32_t *k3_generic);
+/* The rest of group g's tuned plan: k2_half_tile = 1 when the Doppler stage
+ * runs tiles of half the taps, scan_groups = the peak scan's work-groups per
+ * frame.  Outputs may be NULL.  RADAR_E_ARG for a NULL batch or g out of
+ * range. */
+int radar_batch_plan(const radar_batch *b, int32_t g, int32_t *k2_half_tile, int32_t *scan_groups);
 void radar_batch_destroy(radar_batch *b);
 
 /* ------------------------------------------------------------------------

@@ -1763,6 +1763,14 @@ int radar_batch_info(const radar_batch* b, int32_t g, int32_t* n_groups, int32_t
   return RADAR_OK;
 }
 
+int radar_batch_plan(const radar_batch* b, int32_t g, int32_t* k2_half_tile, int32_t* scan_groups) {
+  if (!b || g < 0 || g >= (int32_t)b->groups.size()) return RADAR_E_ARG;
+  const Tuning& t = b->groups[g].tune;
+  if (k2_half_tile) *k2_half_tile = t.k2_half ? 1 : 0;
+  if (scan_groups) *scan_groups = t.scan_groups;
+  return RADAR_OK;
+}
+
 void radar_batch_destroy(radar_batch* b) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);

@@ -34,7 +34,7 @@ EXPORTED = (
     "radar_frame_workspace_size", "radar_frame_process", "radar_periodogram",
     "radar_detect_workspace_size", "radar_detect_topk", "radar_timing_start", "radar_timing_stop",
     "radar_sft_default", "radar_fps_sft_workspace_size", "radar_fps_sft",
-    "radar_batch_workspace_size", "radar_batch_create", "radar_batch_launch", "radar_batch_info",
+    "radar_batch_workspace_size", "radar_batch_create", "radar_batch_launch", "radar_batch_info", "radar_batch_plan",
     "radar_batch_destroy",
     "radar_cnn_param_count", "radar_cnn_workspace_size", "radar_cnn_patches", "radar_cnn_forward",
     "radar_cnn_gradient", "radar_cnn_adam", "radar_cnn_train_step", "radar_tap_wiener_weights",
@@ -134,6 +134,8 @@ def lib() -> ctypes.CDLL:
     L.radar_batch_info.restype = ctypes.c_int
     ip = ctypes.POINTER(i32)
     L.radar_batch_info.argtypes = [vp, i32, ip, ip, ip, ip, ip]
+    L.radar_batch_plan.restype = ctypes.c_int
+    L.radar_batch_plan.argtypes = [vp, i32, ip, ip]
     L.radar_batch_destroy.restype = None
     L.radar_batch_destroy.argtypes = [vp]
     fp = ctypes.c_void_p
@@ -597,6 +599,18 @@ class Batch:
             v = [ctypes.c_int32() for _ in range(4)]
             _check(L.radar_batch_info(self._h, g, None, *[ctypes.byref(x) for x in v]), "radar_batch_info")
             out.append(tuple(x.value for x in v))
+        return out
+
+    def plans(self):
+        """The tuned plan of every shape group: {n_frames, k1_mult, k3_mult,
+        k3_generic, k2_half_tile, scan_groups}."""
+        L = lib()
+        out = []
+        for g, (nf, k1, k3, gen) in enumerate(self.groups()):
+            half, scan = ctypes.c_int32(), ctypes.c_int32()
+            _check(L.radar_batch_plan(self._h, g, ctypes.byref(half), ctypes.byref(scan)), "radar_batch_plan")
+            out.append(dict(n_frames=nf, k1_mult=k1, k3_mult=k3, k3_generic=gen, k2_half_tile=half.value,
+                            scan_groups=scan.value))
         return out
 
     def results(self, i):

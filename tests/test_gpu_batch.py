@@ -160,7 +160,11 @@ def test_batch_autotuned_plan():
     jobs, frames = _setup()
     alone = [_alone(j) for j in jobs]
     b = radar.Batch(jobs, graph=True, tune=True)
-    say(f"tuned plans: {b.groups()}")
+    plans = b.plans()
+    say(f"tuned plans: {plans}")
+    for pl in plans:
+        assert pl["k1_mult"] in (1, 2) and pl["k3_mult"] in (1, 2) and pl["k3_generic"] in (0, 1)
+        assert pl["k2_half_tile"] in (0, 1) and pl["scan_groups"] in (32, 128)
     for rep in range(2):
         _clobber(b)
         b.launch()
