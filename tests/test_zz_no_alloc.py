@@ -63,6 +63,13 @@ def test_noalloc_two_calls_second_smaller():
                        pfa=1e-3, noise_power=1.0)
     say("no-alloc call 3: peaks only, threshold and refinement")
     _both(torch.from_numpy(Y).cuda(), torch.from_numpy(A).cuda(), cfg, 8, materialise=False)
+    # call 4: a full frame in the FP16 form, peaks only (its rows rescanned in FP32)
+    cfg = radar.Config(1024, 1024, 4096, 4096, 256, zc_root=7, window=radar.WIN_HANN, precision=radar.FLAG_FP16)
+    frames = [S.make_frame(S.spec_full(snr_db=0.0), 2, 5)]
+    Y, A = S.frames_to_complex64(frames)
+    say("no-alloc call 4: FP16 form, peaks only, one 1024x1024 frame")
+    n = _both(torch.from_numpy(Y).cuda(), torch.from_numpy(A).cuda(), cfg, 8, materialise=False)
+    assert bool((n == 8).all().cpu())
 
 
 def test_noalloc_rejects_beyond_its_workspace():
